@@ -1,0 +1,193 @@
+"""FP64 CPU oracle for folded-data SGWB radiometer map-making (arXiv:1803.08285).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg use it; the library never does.  It shares no code with the
+HIP path and never imports it.
+
+The heavy loops live in ``sgwb_oracle.c`` (plain C, double precision, libm
+``cos``/``sin`` per term).  This module compiles it with gcc on first use and
+wraps it with ctypes.  ``paper_form`` holds a second, independent route: the
+paper's own per-bin formulation (materialised ORF, complex matrix product).
+
+Definitions (constant prefactors dropped, real part kept):
+  * seeds, Sec. III.D / Fig. 3: gamma(t,p) = sum_A F^A_1 F^A_2,
+    tau(t,p) = Omega_p . dx(t) / c
+  * dirty map, Eq. eq_dirtymap split per bin as in Eq. eq:narrowband:
+    X(k,p) = sum_t w(t,k) gamma(t,p) Re[C(t,k) exp(2 pi i f_k tau(t,p))]
+  * Fisher diagonal per bin, Eq. eq_fisher with p = p':
+    G(k,p) = sum_t w(t,k) gamma(t,p)^2
+  * broadband, Sec. V: Xbb = sum_k X(k,.), Gbb = sum_k H(f_k) G(k,.)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sgwb_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+T_SIDEREAL = 86164.0905
+C_LIGHT = 299792458.0
+EARTH_R = 6.371e6
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle (gcc -O2, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.orc_healpix_centres.argtypes = [ctypes.c_int, dp]
+        lib.orc_healpix_centres.restype = ctypes.c_int
+        lib.orc_detector.argtypes = [ctypes.c_double] * 3 + [dp, dp]
+        lib.orc_detector.restype = None
+        lib.orc_antenna.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
+        lib.orc_antenna.restype = None
+        lib.orc_geometry.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, dp, dp]
+        lib.orc_geometry.restype = ctypes.c_int
+        lib.orc_maps.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, ctypes.c_long, dp, dp,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_long, dp, dp, dp, dp, dp,
+                                 ctypes.c_int]
+        lib.orc_maps.restype = None
+        lib.orc_maps_at.argtypes = [ctypes.c_int, ctypes.c_long, ctypes.c_long, dp, dp, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_long, dp, dp, ctypes.c_long, i64p, i64p,
+                                    dp, dp, dp, ctypes.c_int]
+        lib.orc_maps_at.restype = None
+        lib.orc_band.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp, dp, ctypes.c_int, ctypes.c_int,
+                                 dp, dp]
+        lib.orc_band.restype = None
+        _lib = lib
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _cplx(C) -> np.ndarray:
+    """Complex array -> contiguous interleaved float64 view [..., 2]."""
+    C = np.ascontiguousarray(C, dtype=np.complex128)
+    return C.view(np.float64)
+
+
+def default_threads() -> int:
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+
+def healpix_centres(nside: int) -> np.ndarray:
+    """Unit vectors of the HEALPix RING pixel centres, shape [12 nside^2, 3]."""
+    out = np.empty((12 * nside * nside, 3), dtype=np.float64)
+    rc = _load().orc_healpix_centres(int(nside), _dp(out))
+    if rc != 0:
+        raise ValueError(f"healpix_centres failed ({rc})")
+    return out
+
+
+def detector(lat_deg: float, lon_deg: float, az_deg: float):
+    """Return (position [3] in metres, response tensor [3,3]) of an L-shaped detector."""
+    r = np.empty(3)
+    D = np.empty(9)
+    _load().orc_detector(lat_deg, lon_deg, az_deg, _dp(r), _dp(D))
+    return r, D.reshape(3, 3)
+
+
+def antenna(D: np.ndarray, theta: float, phi: float):
+    """(F+, Fx) of response tensor D for the direction (theta, phi)."""
+    D = _f64(D).reshape(9)
+    fp = np.empty(1)
+    fx = np.empty(1)
+    _load().orc_antenna(_dp(D), float(np.cos(theta)), float(np.sin(theta)), float(phi), _dp(fp), _dp(fx))
+    return float(fp[0]), float(fx[0])
+
+
+def geometry(det, nside: int, nt: int, t0: float, stride: float, dur: float):
+    """Seed matrices gamma[nt][npix], tau[nt][npix] (seconds), both float64.
+
+    ``det`` = (latA, lonA, azA, latB, lonB, azB) in degrees.
+    """
+    det = _f64(det).reshape(6)
+    npix = 12 * nside * nside
+    gamma = np.empty((nt, npix))
+    tau = np.empty((nt, npix))
+    rc = _load().orc_geometry(_dp(det), int(nside), int(nt), float(t0), float(stride), float(dur),
+                              _dp(gamma), _dp(tau))
+    if rc != 0:
+        raise ValueError(f"geometry failed ({rc})")
+    return gamma, tau
+
+
+def maps(C, w, f0: float, df: float, k0: int, gamma, tau, with_scale: bool = False,
+         nthreads: int | None = None):
+    """Full X[nf][npix] and G[nf][npix] (and S = sum_t |w gamma||C| if asked)."""
+    Cv = _cplx(C)
+    w = _f64(w)
+    gamma = _f64(gamma)
+    tau = _f64(tau)
+    nt, nf = w.shape
+    npix = gamma.shape[1]
+    assert C.shape == (nt, nf) and gamma.shape == (nt, npix) and tau.shape == (nt, npix)
+    X = np.empty((nf, npix))
+    G = np.empty((nf, npix))
+    S = np.empty((nf, npix)) if with_scale else None
+    _load().orc_maps(nt, nf, nf, npix, _dp(Cv), _dp(w), float(f0), float(df), int(k0), _dp(gamma),
+                     _dp(tau), _dp(X), _dp(G), _dp(S) if S is not None else None,
+                     int(nthreads or default_threads()))
+    return (X, G, S) if with_scale else (X, G)
+
+
+def maps_at(C, w, f0: float, df: float, k0: int, gamma, tau, cols, pix, nthreads: int | None = None):
+    """X, G, S at the selected (column, pixel) pairs (1-D arrays of equal length)."""
+    Cv = _cplx(C)
+    w = _f64(w)
+    gamma = _f64(gamma)
+    tau = _f64(tau)
+    nt, nf = w.shape
+    npix = gamma.shape[1]
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    assert cols.shape == pix.shape
+    if cols.size and (cols.min() < 0 or cols.max() >= nf or pix.min() < 0 or pix.max() >= npix):
+        raise IndexError("selection out of range")
+    n = cols.size
+    X = np.empty(n)
+    G = np.empty(n)
+    S = np.empty(n)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    _load().orc_maps_at(nt, nf, npix, _dp(Cv), _dp(w), float(f0), float(df), int(k0), _dp(gamma),
+                        _dp(tau), n, cols.ctypes.data_as(i64p), pix.ctypes.data_as(i64p), _dp(X),
+                        _dp(G), _dp(S), int(nthreads or default_threads()))
+    return X, G, S
+
+
+def band(X, G, H, klo: int, khi: int):
+    """Broadband Xbb[npix] = sum_k X, Gbb[npix] = sum_k H G over rows [klo, khi)."""
+    X = _f64(X)
+    G = _f64(G)
+    H = _f64(H)
+    nf, npix = X.shape
+    if not (0 <= klo <= khi <= nf):
+        raise IndexError("band out of range")
+    Xbb = np.empty(npix)
+    Gbb = np.empty(npix)
+    _load().orc_band(nf, npix, _dp(X), _dp(G), _dp(H), int(klo), int(khi), _dp(Xbb), _dp(Gbb))
+    return Xbb, Gbb
