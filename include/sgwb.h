@@ -1,0 +1,154 @@
+/*
+ * sgwb.h - C ABI of the MI355X (gfx950) folded-data SGWB radiometer map-making
+ * library (method of Ain, Suresh & Mitra, arXiv:1803.08285).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All array pointers are DEVICE pointers unless marked (host).  The caller
+ *    owns every buffer and keeps it alive until the work queued on `stream`
+ *    has finished.  The library never frees caller memory.
+ *  - Every call validates its arguments on the host before queuing anything
+ *    and then returns at once; the GPU work runs asynchronously on `stream`
+ *    (a hipStream_t; NULL = the default stream).  A device fault shows up at
+ *    the next synchronisation of that stream.
+ *  - Return value: SGWB_OK (0) or a negative SGWB_E* code; nothing is printed
+ *    and no exception crosses the ABI.  sgwb_status_string() names a code and
+ *    sgwb_last_error() gives the text of the last failure on this thread.
+ *  - Layouts are row-major with the last index contiguous:
+ *      seeds      gamma[nt][npix], tau[nt][npix]    (pixel-major rows)
+ *      CSD        C[nt][ldc] complex (re, im interleaved), weights w[nt][ldc]
+ *      maps       X[nf][npix], Gam[nf][npix]         (each row one HEALPix map)
+ *  - Pixels are HEALPix RING pixels, npix = 12 nside^2, nside a power of two.
+ *  - Results are bitwise reproducible: fixed summation order, no atomics.
+ */
+#ifndef SGWB_H
+#define SGWB_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define SGWB_OK 0
+#define SGWB_EINVAL (-1)       /* bad argument: null pointer, shape, nside, range  */
+#define SGWB_ENOMEM (-2)       /* workspace too small / allocation failed          */
+#define SGWB_EDEVICE (-3)      /* a HIP call failed (text in sgwb_last_error)       */
+#define SGWB_EUNSUPPORTED (-5) /* device is not gfx950, or option not available     */
+
+/* ---- geometry descriptions --------------------------------------------- */
+/* An L-shaped detector with horizontal arms on a sphere of radius 6.371e6 m.
+ * x-arm azimuth is measured counter-clockwise from local East; the y-arm is
+ * at azimuth + 90 degrees.  Longitude is positive to the East.             */
+typedef struct {
+    double lat_deg, lon_deg, xarm_az_deg;
+} sgwb_detector;
+
+/* A baseline (Sec. II.A, Fig. 1): the delay uses x_a - x_b.                  */
+typedef struct {
+    sgwb_detector a, b;
+} sgwb_baseline;
+
+/* Folded sidereal day (Sec. II.B): segment k has mid time
+ * t_k = t0_s + k stride_s + seg_dur_s / 2, in sidereal seconds after the
+ * moment when the Earth-fixed and celestial frames coincide.                 */
+typedef struct {
+    int32_t nt;
+    double t0_s, stride_s, seg_dur_s;
+} sgwb_tgrid;
+
+/* Absolute frequency grid f_k = f0_hz + k df_hz.  A call works on the nf
+ * consecutive bins [k0, k0 + nf); the recurrence of the dirty map is
+ * re-anchored at absolute bins k = 0 mod 64 (mod 32 in the float64 path), so
+ * a sub-band gives bitwise the same rows as the full band.                    */
+typedef struct {
+    double f0_hz, df_hz;
+} sgwb_fgrid;
+
+/* ---- seeds: Sec. III.D (Fig. 3), "ORF seed matrices" ---------------------
+ * gamma(t,p) = sum_{A=+,x} F^A_a(Omega_p, t) F^A_b(Omega_p, t)  (combined
+ * antenna pattern at the pixel centre, no normalisation constant) and
+ * tau(t,p) = Omega_p . (x_a(t) - x_b(t)) / c  in seconds, with the detector
+ * tensors and separation rotated to sidereal time t_k in float64 on the GPU.
+ * Output gamma[nt][npix] (float32 here, float64 in the _f64 variant) and
+ * tau[nt][npix] float64.  The RING grid is antipodally symmetric and the
+ * output is written exactly symmetric: gamma(t, a(p)) = gamma(t,p) and
+ * tau(t, a(p)) = -tau(t,p) for the antipode a(p).
+ * Errors: SGWB_EINVAL if a pointer is null, nt < 1, nside is not a power of
+ * two in [1, 8192], or stride/duration are not finite.                      */
+int sgwb_build_geometry(const sgwb_baseline *bl /*host*/, int32_t nside, const sgwb_tgrid *tg /*host*/,
+                        float *gamma, double *tau, hipStream_t stream);
+int sgwb_build_geometry_f64(const sgwb_baseline *bl /*host*/, int32_t nside,
+                            const sgwb_tgrid *tg /*host*/, double *gamma, double *tau,
+                            hipStream_t stream);
+
+/* ---- narrowband maps: Eq. eq_dirtymap split per bin (Eq. eq:narrowband),
+ *      and the per-bin Fisher diagonal (Eq. eq_fisher with p = p', Sec. III.A)
+ *
+ *   X(k,p)   = sum_t w(t,k) gamma(t,p) Re[ C(t,k) exp(2 pi i f_k tau(t,p)) ]
+ *   Gam(k,p) = sum_t w(t,k) gamma(t,p)^2
+ *
+ * for the nf bins k0 .. k0 + nf - 1 of grid fg and every pixel p < npix.
+ * w holds the folded inverse noise variance times the spectral shape
+ * (the configs use w = H / P^2), so no constant prefactor is applied.
+ * Inputs: C interleaved complex float32 [nt][ldc] (column c = bin k0 + c),
+ * w float32 [nt][ldc], ldc >= nf; gamma float32 and tau float64 [nt][npix].
+ * Outputs (may be NULL to skip): X, Gam float32 [nf][npix].
+ * flags: SGWB_MAPS_ANTIPODAL promises that gamma/tau have the exact
+ * antipodal symmetry that sgwb_build_geometry writes (npix = 12 nside^2);
+ * the kernels then evaluate one phasor per antipodal pair and write both
+ * pixels.  Without the flag any npix and any seeds are accepted.
+ * X arithmetic: float32 accumulation, float64 phase reduction f_k tau at the
+ * anchor bins, complex-rotation recurrence between anchors.
+ * Gam arithmetic: float32 inputs split into bfloat16 hi + lo, three MFMA
+ * products (hi.hi + hi.lo + lo.hi), float32 accumulation.
+ * Workspace: device memory of at least sgwb_make_maps_workspace_size() bytes,
+ * 256-byte aligned, owned by the caller (NULL allowed when Gam is NULL).
+ * Errors: SGWB_EINVAL (null input, nt/nf/npix < 1, ldc < nf, k0 < 0, bad
+ * grid, misaligned pointer), SGWB_ENOMEM (workspace too small).             */
+#define SGWB_MAPS_ANTIPODAL 1u
+size_t sgwb_make_maps_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint32_t flags);
+int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf,
+                   const sgwb_fgrid *fg /*host*/, int64_t k0, const float *gamma, const double *tau,
+                   int32_t npix, uint32_t flags, float *X, float *Gam, void *workspace,
+                   size_t workspace_bytes, hipStream_t stream);
+
+/* float64 variant of the same definition (all inputs and outputs double; Gam
+ * accumulated in float64 on the vector units; no workspace).                  */
+int sgwb_make_maps_f64(const double *C, const double *w, int64_t ldc, int32_t nt, int32_t nf,
+                       const sgwb_fgrid *fg /*host*/, int64_t k0, const double *gamma,
+                       const double *tau, int32_t npix, uint32_t flags, double *X, double *Gam,
+                       hipStream_t stream);
+
+/* ---- broadband maps: Sec. V, spectrum-weighted sum of narrowband maps -----
+ *   Xbb(p) = sum_{k_lo <= k < k_hi} X(k,p)
+ *   Gbb(p) = sum_{k_lo <= k < k_hi} H(k) Gam(k,p)
+ * (w = H / P^2 already carries one factor of H into X and Gam).  X, Gam are
+ * [nf][npix]; H[nf] is indexed like the rows.  Sums run in float64 in a fixed
+ * order and are rounded once.  Either of X/Xbb or Gam/Gbb may be NULL.
+ * Errors: SGWB_EINVAL if 0 <= k_lo <= k_hi <= nf fails or a needed pointer
+ * is null.                                                                  */
+int sgwb_reduce_band(const float *X, const float *Gam, const float *H, int32_t nf, int32_t npix,
+                     int32_t k_lo, int32_t k_hi, float *Xbb, float *Gbb, hipStream_t stream);
+int sgwb_reduce_band_f64(const double *X, const double *Gam, const double *H, int32_t nf,
+                         int32_t npix, int32_t k_lo, int32_t k_hi, double *Xbb, double *Gbb,
+                         hipStream_t stream);
+
+/* ---- HEALPix helper: RING pixel centres (Sec. III.B) as float64 unit
+ * vectors xyz[npix][3] (device), and the antipode table anti[npix] (device,
+ * int32).  Either output may be NULL.                                        */
+int sgwb_healpix_centres(int32_t nside, double *xyz, int32_t *anti, hipStream_t stream);
+
+/* ---- status ------------------------------------------------------------ */
+const char *sgwb_status_string(int status);
+const char *sgwb_last_error(void);
+/* 1 if the current device is a gfx950 part, 0 if not, negative on error.    */
+int sgwb_device_supported(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGWB_H */

@@ -61,6 +61,9 @@ def _load():
         lib.orc_geometry.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, dp, dp]
         lib.orc_geometry.restype = ctypes.c_int
+        lib.orc_geometry_at.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_long, i64p, dp, dp]
+        lib.orc_geometry_at.restype = ctypes.c_int
         lib.orc_maps.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, ctypes.c_long, dp, dp,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_long, dp, dp, dp, dp, dp,
                                  ctypes.c_int]
@@ -133,6 +136,19 @@ def geometry(det, nside: int, nt: int, t0: float, stride: float, dur: float):
                               _dp(gamma), _dp(tau))
     if rc != 0:
         raise ValueError(f"geometry failed ({rc})")
+    return gamma, tau
+
+
+def geometry_at(det, nside: int, nt: int, t0: float, stride: float, dur: float, pix):
+    """Seed columns gamma[nt][len(pix)], tau[nt][len(pix)] for selected pixels."""
+    det = _f64(det).reshape(6)
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    gamma = np.empty((nt, pix.size))
+    tau = np.empty((nt, pix.size))
+    rc = _load().orc_geometry_at(_dp(det), int(nside), int(nt), float(t0), float(stride), float(dur), pix.size,
+                                 pix.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(gamma), _dp(tau))
+    if rc != 0:
+        raise ValueError(f"geometry_at failed ({rc})")
     return gamma, tau
 
 

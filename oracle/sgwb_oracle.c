@@ -146,12 +146,13 @@ static void rot_z(double th, const double Min[9], const double vin[3], double Mo
 }
 
 /* ------------------------------------------------------------------------ */
-/* ORF seed matrices (Sec. III.D, Fig. 3): gamma[t][p] and tau[t][p].         */
+/* ORF seed matrices (Sec. III.D, Fig. 3): gamma[t][p] and tau[t][p] for all  */
+/* pixels, or for the nsel pixels listed in pix (then shape [nt][nsel]).      */
 /* det = {latA, lonA, azA, latB, lonB, azB} in degrees.                       */
 /* Segment k has mid time t_k = t0 + k*stride + dur/2 (sidereal seconds).     */
 /* ------------------------------------------------------------------------ */
-int orc_geometry(const double det[6], int nside, int nt, double t0, double stride, double dur,
-                 double *gamma, double *tau)
+int orc_geometry_at(const double det[6], int nside, int nt, double t0, double stride, double dur,
+                    long nsel, const int64_t *pix, double *gamma, double *tau)
 {
     long npix = 12L * nside * nside;
     double *xyz = (double *)malloc(sizeof(double) * 3 * npix);
@@ -169,19 +170,27 @@ int orc_geometry(const double det[6], int nside, int nt, double t0, double strid
         double DAt[9], DBt[9], dxt[3];
         rot_z(th, DA, dx, DAt, dxt);
         rot_z(th, DB, zero, DBt, dummy);
-        for (long p = 0; p < npix; ++p) {
+        for (long i = 0; i < nsel; ++i) {
+            long p = pix ? (long)pix[i] : i;
+            if (p < 0 || p >= npix) { free(xyz); return -4; }
             double ox = xyz[3 * p], oy = xyz[3 * p + 1], oz = xyz[3 * p + 2];
             double sin_t = sqrt(ox * ox + oy * oy);
             double phi = atan2(oy, ox);
             double fpA, fxA, fpB, fxB;
             orc_antenna(DAt, oz, sin_t, phi, &fpA, &fxA);
             orc_antenna(DBt, oz, sin_t, phi, &fpB, &fxB);
-            gamma[(long)k * npix + p] = fpA * fpB + fxA * fxB;
-            tau[(long)k * npix + p] = (ox * dxt[0] + oy * dxt[1] + oz * dxt[2]) / ORC_C_LIGHT;
+            gamma[(long)k * nsel + i] = fpA * fpB + fxA * fxB;
+            tau[(long)k * nsel + i] = (ox * dxt[0] + oy * dxt[1] + oz * dxt[2]) / ORC_C_LIGHT;
         }
     }
     free(xyz);
     return 0;
+}
+
+int orc_geometry(const double det[6], int nside, int nt, double t0, double stride, double dur,
+                 double *gamma, double *tau)
+{
+    return orc_geometry_at(det, nside, nt, t0, stride, dur, 12L * nside * nside, NULL, gamma, tau);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -1,0 +1,283 @@
+"""MI355X (gfx950) folded-data SGWB radiometer map-making (arXiv:1803.08285).
+
+Thin ctypes binding over ``libsgwb.so`` (C ABI in ``include/sgwb.h``).  Every
+step of the computation runs in the library's HIP kernels; this module only
+checks shapes, allocates outputs as torch tensors on the current device and
+passes raw device pointers plus the current HIP stream.  There is no CPU
+fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgwb.so")
+
+SGWB_MAPS_ANTIPODAL = 1
+
+
+class SgwbError(RuntimeError):
+    pass
+
+
+class _Detector(ctypes.Structure):
+    _fields_ = [("lat_deg", ctypes.c_double), ("lon_deg", ctypes.c_double), ("xarm_az_deg", ctypes.c_double)]
+
+
+class _Baseline(ctypes.Structure):
+    _fields_ = [("a", _Detector), ("b", _Detector)]
+
+
+class _TGrid(ctypes.Structure):
+    _fields_ = [("nt", ctypes.c_int32), ("t0_s", ctypes.c_double), ("stride_s", ctypes.c_double),
+                ("seg_dur_s", ctypes.c_double)]
+
+
+class _FGrid(ctypes.Structure):
+    _fields_ = [("f0_hz", ctypes.c_double), ("df_hz", ctypes.c_double)]
+
+
+_lib = None
+
+_VP = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+
+_SIGNATURES = {
+    "sgwb_build_geometry": ([ctypes.POINTER(_Baseline), _I32, ctypes.POINTER(_TGrid), _VP, _VP, _VP], ctypes.c_int),
+    "sgwb_build_geometry_f64": ([ctypes.POINTER(_Baseline), _I32, ctypes.POINTER(_TGrid), _VP, _VP, _VP],
+                                ctypes.c_int),
+    "sgwb_make_maps_workspace_size": ([_I32, _I32, _I32, ctypes.c_uint32], ctypes.c_size_t),
+    "sgwb_make_maps": ([_VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
+                        ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
+    "sgwb_make_maps_f64": ([_VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
+                            ctypes.c_uint32, _VP, _VP, _VP], ctypes.c_int),
+    "sgwb_reduce_band": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
+    "sgwb_reduce_band_f64": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
+    "sgwb_healpix_centres": ([_I32, _VP, _VP, _VP], ctypes.c_int),
+    "sgwb_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "sgwb_last_error": ([], ctypes.c_char_p),
+    "sgwb_device_supported": ([], ctypes.c_int),
+}
+
+
+def exported_symbols():
+    """Names of the C entry points this binding expects the library to export."""
+    return sorted(_SIGNATURES)
+
+
+def lib():
+    """Load libsgwb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SgwbError(f"{LIB_PATH} is missing: build it with paper_1803_08285_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        L = lib()
+        raise SgwbError(f"{what}: {L.sgwb_status_string(rc).decode()} ({rc}): {L.sgwb_last_error().decode()}")
+
+
+def _stream(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _require(t: torch.Tensor, name: str, dtype, shape=None, cols_contig=True):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise SgwbError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise SgwbError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise SgwbError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if cols_contig and t.dim() == 2 and t.stride(1) != 1:
+        raise SgwbError(f"{name} must have unit stride along its last axis")
+
+
+def _require_contig(t: torch.Tensor, name: str):
+    if not t.is_contiguous():
+        raise SgwbError(f"{name} must be contiguous")
+
+
+# ---------------------------------------------------------------------------
+# Geometry descriptions
+# ---------------------------------------------------------------------------
+@dataclass(frozen=True)
+class TGrid:
+    nt: int
+    t0: float
+    stride: float
+    dur: float
+
+
+@dataclass(frozen=True)
+class FGrid:
+    """Absolute bin grid f_k = f0 + k df."""
+    f0: float
+    df: float
+
+
+def _baseline(sites) -> _Baseline:
+    s = [float(x) for x in sites]
+    if len(s) != 6:
+        raise SgwbError("baseline needs (latA, lonA, azA, latB, lonB, azB)")
+    return _Baseline(_Detector(*s[:3]), _Detector(*s[3:]))
+
+
+def npix_of(nside: int) -> int:
+    return 12 * nside * nside
+
+
+# ---------------------------------------------------------------------------
+# Calls
+# ---------------------------------------------------------------------------
+def build_geometry(sites, nside: int, tgrid: TGrid, dtype=torch.float32, device=None, out=None):
+    """ORF seed matrices (gamma, tau) of shape [nt][12 nside^2]; gamma float32
+    (or float64 with dtype=torch.float64), tau float64 seconds."""
+    device = torch.device("cuda") if device is None else torch.device(device)
+    npix = npix_of(nside)
+    if out is None:
+        gamma = torch.empty((tgrid.nt, npix), dtype=dtype, device=device)
+        tau = torch.empty((tgrid.nt, npix), dtype=torch.float64, device=device)
+    else:
+        gamma, tau = out
+    _require(gamma, "gamma", dtype, (tgrid.nt, npix))
+    _require(tau, "tau", torch.float64, (tgrid.nt, npix))
+    _require_contig(gamma, "gamma")
+    _require_contig(tau, "tau")
+    bl = _baseline(sites)
+    tg = _TGrid(int(tgrid.nt), float(tgrid.t0), float(tgrid.stride), float(tgrid.dur))
+    fn = lib().sgwb_build_geometry if dtype == torch.float32 else lib().sgwb_build_geometry_f64
+    with torch.cuda.device(gamma.device):
+        _check(fn(ctypes.byref(bl), int(nside), ctypes.byref(tg), _ptr(gamma), _ptr(tau), _stream()),
+               "build_geometry")
+    return gamma, tau
+
+
+def workspace_bytes(nt: int, nf: int, npix: int, antipodal: bool = True) -> int:
+    return int(lib().sgwb_make_maps_workspace_size(nt, nf, npix, SGWB_MAPS_ANTIPODAL if antipodal else 0))
+
+
+def make_workspace(nt: int, nf: int, npix: int, antipodal: bool = True, device=None) -> torch.Tensor:
+    n = workspace_bytes(nt, nf, npix, antipodal)
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def make_maps(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamma: torch.Tensor,
+              tau: torch.Tensor, antipodal: bool = True, want_x: bool = True, want_gamma: bool = True,
+              out=None, workspace: torch.Tensor | None = None):
+    """Narrowband dirty map X and Fisher diagonal Gam, both [nf][npix].
+
+    C: complex64 [nt][>= nf] (columns = bins k0 ..), or complex128 for the
+    float64 path; w: float32/float64 [nt][same columns]; gamma [nt][npix] of the
+    working precision; tau float64 [nt][npix].  Column slices of a wider array
+    are accepted (rows may be strided, columns must be unit-stride).
+    """
+    f64 = C.dtype == torch.complex128
+    rdt = torch.float64 if f64 else torch.float32
+    cdt = torch.complex128 if f64 else torch.complex64
+    if C.dim() != 2 or w.dim() != 2:
+        raise SgwbError("C and w must be 2-D")
+    nt, nf = w.shape
+    npix = gamma.shape[1]
+    _require(C, "C", cdt, (nt, nf))
+    _require(w, "w", rdt, (nt, nf))
+    if C.stride(0) != w.stride(0):
+        raise SgwbError("C and w must share their row stride")
+    _require(gamma, "gamma", rdt, (nt, npix))
+    _require(tau, "tau", torch.float64, (nt, npix))
+    _require_contig(gamma, "gamma")
+    _require_contig(tau, "tau")
+    dev = C.device
+    X = G = None
+    if out is not None:
+        X, G = out
+    if want_x and X is None:
+        X = torch.empty((nf, npix), dtype=rdt, device=dev)
+    if want_gamma and G is None:
+        G = torch.empty((nf, npix), dtype=rdt, device=dev)
+    for name, t in (("X", X), ("Gam", G)):
+        if t is not None:
+            _require(t, name, rdt, (nf, npix))
+            _require_contig(t, name)
+    flags = SGWB_MAPS_ANTIPODAL if antipodal else 0
+    fg = _FGrid(float(fgrid.f0), float(fgrid.df))
+    Cr = torch.view_as_real(C)
+    with torch.cuda.device(dev):
+        if f64:
+            rc = lib().sgwb_make_maps_f64(_ptr(Cr), _ptr(w), int(w.stride(0)), nt, nf, ctypes.byref(fg), int(k0),
+                                          _ptr(gamma), _ptr(tau), npix, flags, _ptr(X), _ptr(G), _stream())
+        else:
+            ws = None
+            wsz = 0
+            if G is not None:
+                need = workspace_bytes(nt, nf, npix, antipodal)
+                if workspace is None:
+                    workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+                ws = workspace
+                wsz = workspace.numel() * workspace.element_size()
+            rc = lib().sgwb_make_maps(_ptr(Cr), _ptr(w), int(w.stride(0)), nt, nf, ctypes.byref(fg), int(k0),
+                                      _ptr(gamma), _ptr(tau), npix, flags, _ptr(X), _ptr(G), _ptr(ws), wsz,
+                                      _stream())
+    _check(rc, "make_maps")
+    return X, G
+
+
+def reduce_band(X: torch.Tensor | None, G: torch.Tensor | None, H: torch.Tensor | None, k_lo: int, k_hi: int,
+                out=None):
+    """Broadband Xbb = sum_k X[k], Gbb = sum_k H[k] G[k] over rows [k_lo, k_hi)."""
+    ref = X if X is not None else G
+    if ref is None:
+        raise SgwbError("reduce_band: X or G needed")
+    nf, npix = ref.shape
+    rdt = ref.dtype
+    for name, t in (("X", X), ("G", G)):
+        if t is not None:
+            _require(t, name, rdt, (nf, npix))
+            _require_contig(t, name)
+    if G is not None:
+        _require(H, "H", rdt, (nf,))
+        _require_contig(H, "H")
+    Xbb = Gbb = None
+    if out is not None:
+        Xbb, Gbb = out
+    if X is not None and Xbb is None:
+        Xbb = torch.empty(npix, dtype=rdt, device=ref.device)
+    if G is not None and Gbb is None:
+        Gbb = torch.empty(npix, dtype=rdt, device=ref.device)
+    fn = lib().sgwb_reduce_band_f64 if rdt == torch.float64 else lib().sgwb_reduce_band
+    with torch.cuda.device(ref.device):
+        _check(fn(_ptr(X), _ptr(G), _ptr(H) if G is not None else None, nf, npix, int(k_lo), int(k_hi), _ptr(Xbb),
+                  _ptr(Gbb), _stream()), "reduce_band")
+    return Xbb, Gbb
+
+
+def healpix_centres(nside: int, device=None):
+    """(xyz float64 [npix][3], antipode int32 [npix]) computed on the device."""
+    device = torch.device("cuda") if device is None else torch.device(device)
+    npix = npix_of(nside)
+    xyz = torch.empty((npix, 3), dtype=torch.float64, device=device)
+    anti = torch.empty(npix, dtype=torch.int32, device=device)
+    with torch.cuda.device(device):
+        _check(lib().sgwb_healpix_centres(int(nside), _ptr(xyz), _ptr(anti), _stream()), "healpix_centres")
+    return xyz, anti
+
+
+def device_supported() -> bool:
+    return lib().sgwb_device_supported() == 1

@@ -1,0 +1,248 @@
+// C ABI of libsgwb: argument checks, host-side detector set-up, launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "sgwb_internal.h"
+
+namespace sgwb {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int check_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return SGWB_OK;
+    return set_error(SGWB_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Earth-fixed position (m) and response tensor D = (u u^T - v v^T) / 2 of an
+// L-shaped detector: u = x-arm, v = y-arm, both horizontal, x-arm azimuth
+// counter-clockwise from local East.
+static void detector_frame(const sgwb_detector &d, double r[3], double D[9])
+{
+    const double k = kPi / 180.0;
+    const double sl = sin(d.lat_deg * k), cl = cos(d.lat_deg * k);
+    const double so = sin(d.lon_deg * k), co = cos(d.lon_deg * k);
+    const double sa = sin(d.xarm_az_deg * k), ca = cos(d.xarm_az_deg * k);
+    r[0] = kEarthRadius * cl * co;
+    r[1] = kEarthRadius * cl * so;
+    r[2] = kEarthRadius * sl;
+    const double east[3] = {-so, co, 0.0};
+    const double north[3] = {-sl * co, -sl * so, cl};
+    double u[3], v[3];
+    for (int i = 0; i < 3; ++i) {
+        u[i] = ca * east[i] + sa * north[i];
+        v[i] = ca * north[i] - sa * east[i];
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) D[3 * i + j] = 0.5 * (u[i] * u[j] - v[i] * v[j]);
+}
+
+static bool finite_det(const sgwb_detector &d)
+{
+    return isfinite(d.lat_deg) && isfinite(d.lon_deg) && isfinite(d.xarm_az_deg) && fabs(d.lat_deg) <= 90.0;
+}
+
+template <typename G>
+static int build_geometry_impl(const sgwb_baseline *bl, int32_t nside, const sgwb_tgrid *tg, G *gamma,
+                               double *tau, hipStream_t stream)
+{
+    if (!bl || !tg || !gamma || !tau) return set_error(SGWB_EINVAL, "build_geometry: null pointer");
+    if (!is_pow2_nside(nside)) return set_error(SGWB_EINVAL, "build_geometry: nside %d is not a power of two in [1, 8192]", nside);
+    if (tg->nt < 1 || tg->nt > 65535) return set_error(SGWB_EINVAL, "build_geometry: nt %d out of [1, 65535]", tg->nt);
+    if (!isfinite(tg->t0_s) || !isfinite(tg->stride_s) || !isfinite(tg->seg_dur_s))
+        return set_error(SGWB_EINVAL, "build_geometry: non-finite time grid");
+    if (!finite_det(bl->a) || !finite_det(bl->b)) return set_error(SGWB_EINVAL, "build_geometry: bad detector");
+    if (((uintptr_t)gamma % sizeof(G)) || ((uintptr_t)tau % 8)) return set_error(SGWB_EINVAL, "build_geometry: misaligned output");
+    GeomArgs a;
+    double ra[3], rb[3];
+    detector_frame(bl->a, ra, a.DA);
+    detector_frame(bl->b, rb, a.DB);
+    for (int i = 0; i < 3; ++i) a.dx[i] = ra[i] - rb[i];
+    a.t0 = tg->t0_s;
+    a.stride = tg->stride_s;
+    a.half_dur = 0.5 * tg->seg_dur_s;
+    a.nt = tg->nt;
+    a.nside = nside;
+    a.npix = 12LL * nside * nside;
+    return check_hip(launch_geometry<G>(a, gamma, tau, stream), "geometry kernel launch");
+}
+
+static int check_grid(const sgwb_fgrid *fg)
+{
+    if (!fg) return set_error(SGWB_EINVAL, "null frequency grid");
+    if (!isfinite(fg->f0_hz) || !isfinite(fg->df_hz) || fg->df_hz <= 0.0)
+        return set_error(SGWB_EINVAL, "frequency grid must be finite with df > 0");
+    return SGWB_OK;
+}
+
+template <typename T>
+static int check_maps_args(const T *C, const T *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
+                           int64_t k0, const T *gamma, const double *tau, int32_t npix, uint32_t flags,
+                           MapArgs *a)
+{
+    if (!C || !w || !gamma || !tau) return set_error(SGWB_EINVAL, "make_maps: null input pointer");
+    if (nt < 1 || nf < 1 || npix < 1) return set_error(SGWB_EINVAL, "make_maps: nt, nf, npix must be >= 1");
+    if (ldc < nf) return set_error(SGWB_EINVAL, "make_maps: ldc %lld < nf %d", (long long)ldc, nf);
+    if (k0 < 0) return set_error(SGWB_EINVAL, "make_maps: k0 < 0");
+    if (flags & ~SGWB_MAPS_ANTIPODAL) return set_error(SGWB_EINVAL, "make_maps: unknown flag bits");
+    int rc = check_grid(fg);
+    if (rc) return rc;
+    if (((uintptr_t)C % (2 * sizeof(T))) || ((uintptr_t)w % sizeof(T)) || ((uintptr_t)gamma % sizeof(T)) ||
+        ((uintptr_t)tau % 8))
+        return set_error(SGWB_EINVAL, "make_maps: misaligned input");
+    a->ldc = ldc;
+    a->k0 = k0;
+    a->nt = nt;
+    a->nf = nf;
+    a->npix = npix;
+    a->f0 = fg->f0_hz;
+    a->df = fg->df_hz;
+    a->nside = 0;
+    if (flags & SGWB_MAPS_ANTIPODAL) {
+        a->nside = nside_of_npix(npix);
+        if (a->nside == 0)
+            return set_error(SGWB_EINVAL, "make_maps: SGWB_MAPS_ANTIPODAL needs npix = 12 nside^2, nside a power of two");
+    }
+    return SGWB_OK;
+}
+
+template <typename T>
+static int reduce_band_impl(const T *X, const T *Gam, const T *H, int32_t nf, int32_t npix, int32_t k_lo,
+                            int32_t k_hi, T *Xbb, T *Gbb, hipStream_t stream)
+{
+    if (nf < 1 || npix < 1) return set_error(SGWB_EINVAL, "reduce_band: nf, npix must be >= 1");
+    if (!(0 <= k_lo && k_lo <= k_hi && k_hi <= nf))
+        return set_error(SGWB_EINVAL, "reduce_band: need 0 <= k_lo <= k_hi <= nf");
+    const bool doX = X && Xbb, doG = Gam && Gbb;
+    if ((X != nullptr) != (Xbb != nullptr) || (Gam != nullptr) != (Gbb != nullptr))
+        return set_error(SGWB_EINVAL, "reduce_band: X/Xbb and Gam/Gbb must be given in pairs");
+    if (!doX && !doG) return set_error(SGWB_EINVAL, "reduce_band: nothing to do");
+    if (doG && !H) return set_error(SGWB_EINVAL, "reduce_band: H needed for Gbb");
+    return check_hip(launch_band<T>(doX ? X : nullptr, doG ? Gam : nullptr, H, nf, npix, k_lo, k_hi,
+                                    doX ? Xbb : nullptr, doG ? Gbb : nullptr, stream),
+                     "band kernel launch");
+}
+
+}  // namespace sgwb
+
+using namespace sgwb;
+
+extern "C" {
+
+const char *sgwb_status_string(int status)
+{
+    switch (status) {
+    case SGWB_OK: return "ok";
+    case SGWB_EINVAL: return "invalid argument";
+    case SGWB_ENOMEM: return "out of memory / workspace too small";
+    case SGWB_EDEVICE: return "HIP device error";
+    case SGWB_EUNSUPPORTED: return "unsupported device or option";
+    default: return "unknown status";
+    }
+}
+
+const char *sgwb_last_error(void) { return g_err; }
+
+int sgwb_device_supported(void)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return check_hip(hipGetLastError(), "hipGetDevice");
+    hipDeviceProp_t p;
+    hipError_t e = hipGetDeviceProperties(&p, dev);
+    if (e != hipSuccess) return check_hip(e, "hipGetDeviceProperties");
+    return strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+}
+
+int sgwb_build_geometry(const sgwb_baseline *bl, int32_t nside, const sgwb_tgrid *tg, float *gamma, double *tau,
+                        hipStream_t stream)
+{
+    return build_geometry_impl<float>(bl, nside, tg, gamma, tau, stream);
+}
+
+int sgwb_build_geometry_f64(const sgwb_baseline *bl, int32_t nside, const sgwb_tgrid *tg, double *gamma,
+                            double *tau, hipStream_t stream)
+{
+    return build_geometry_impl<double>(bl, nside, tg, gamma, tau, stream);
+}
+
+size_t sgwb_make_maps_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint32_t flags)
+{
+    if (nt < 1 || nf < 1 || npix < 1) return 0;
+    const int32_t ncol = (flags & SGWB_MAPS_ANTIPODAL) ? npix / 2 : npix;
+    return beam_workspace_bytes(nt, nf, ncol);
+}
+
+int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
+                   int64_t k0, const float *gamma, const double *tau, int32_t npix, uint32_t flags, float *X,
+                   float *Gam, void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    MapArgs a;
+    int rc = check_maps_args<float>(C, w, ldc, nt, nf, fg, k0, gamma, tau, npix, flags, &a);
+    if (rc) return rc;
+    if (Gam) {
+        const size_t need = sgwb_make_maps_workspace_size(nt, nf, npix, flags);
+        if (!workspace || workspace_bytes < need)
+            return set_error(SGWB_ENOMEM, "make_maps: workspace of %zu bytes needed, %zu given", need,
+                             workspace ? workspace_bytes : (size_t)0);
+        if ((uintptr_t)workspace % 256) return set_error(SGWB_EINVAL, "make_maps: workspace not 256-byte aligned");
+    }
+    if (X) {
+        rc = check_hip(launch_dirty_map<float>(a, C, w, gamma, tau, X, stream), "dirty-map kernel launch");
+        if (rc) return rc;
+    }
+    if (Gam) {
+        rc = check_hip(launch_beam_bf16x3(a, w, gamma, Gam, workspace, stream), "beam kernel launch");
+        if (rc) return rc;
+    }
+    return SGWB_OK;
+}
+
+int sgwb_make_maps_f64(const double *C, const double *w, int64_t ldc, int32_t nt, int32_t nf,
+                       const sgwb_fgrid *fg, int64_t k0, const double *gamma, const double *tau, int32_t npix,
+                       uint32_t flags, double *X, double *Gam, hipStream_t stream)
+{
+    MapArgs a;
+    int rc = check_maps_args<double>(C, w, ldc, nt, nf, fg, k0, gamma, tau, npix, flags, &a);
+    if (rc) return rc;
+    if (X) {
+        rc = check_hip(launch_dirty_map<double>(a, C, w, gamma, tau, X, stream), "dirty-map kernel launch");
+        if (rc) return rc;
+    }
+    if (Gam) {
+        rc = check_hip(launch_beam_f64(a, w, gamma, Gam, stream), "beam kernel launch");
+        if (rc) return rc;
+    }
+    return SGWB_OK;
+}
+
+int sgwb_reduce_band(const float *X, const float *Gam, const float *H, int32_t nf, int32_t npix, int32_t k_lo,
+                     int32_t k_hi, float *Xbb, float *Gbb, hipStream_t stream)
+{
+    return reduce_band_impl<float>(X, Gam, H, nf, npix, k_lo, k_hi, Xbb, Gbb, stream);
+}
+
+int sgwb_reduce_band_f64(const double *X, const double *Gam, const double *H, int32_t nf, int32_t npix,
+                         int32_t k_lo, int32_t k_hi, double *Xbb, double *Gbb, hipStream_t stream)
+{
+    return reduce_band_impl<double>(X, Gam, H, nf, npix, k_lo, k_hi, Xbb, Gbb, stream);
+}
+
+int sgwb_healpix_centres(int32_t nside, double *xyz, int32_t *anti, hipStream_t stream)
+{
+    if (!is_pow2_nside(nside)) return set_error(SGWB_EINVAL, "healpix_centres: bad nside %d", nside);
+    if (!xyz && !anti) return set_error(SGWB_EINVAL, "healpix_centres: nothing to do");
+    return check_hip(launch_centres(nside, xyz, anti, stream), "centres kernel launch");
+}
+
+}  // extern "C"

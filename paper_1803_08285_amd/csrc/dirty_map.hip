@@ -1,0 +1,217 @@
+// Narrowband dirty map X(k,p) = sum_t w(t,k) gamma(t,p) Re[C(t,k) e^{2 pi i f_k tau(t,p)}]
+// (Eq. eq_dirtymap split per frequency bin as in Eq. eq:narrowband) on gfx950.
+//
+// Work decomposition
+//   * A workgroup owns 256 pixel columns (one per lane) and one strip of S
+//     consecutive frequency bins that starts at an absolute bin k = 0 mod S
+//     (S = 64 in float32, 32 in float64).  Lanes of a wave read coalesced
+//     pixel-major rows of gamma and tau.
+//   * The weighted CSD y(t,k) = w(t,k) C(t,k) of the strip is staged in LDS,
+//     XTC segments at a time; every lane reads the same y (LDS broadcast).
+//   * Per (t, pixel) the phase is reduced once per strip in float64,
+//     frac(f_anchor tau), and turned into the anchor phasor z = gamma e^{i phi};
+//     the remaining S-1 bins advance z by the rotor 1 + eps = e^{i 2 pi df tau},
+//     z <- z + z eps (four FMAs), so no transcendental is evaluated per term.
+//   * Antipodal pairing (HEALPix RING seeds from the geometry kernel): the
+//     antipode p' of p has gamma(t,p') = gamma(t,p) and tau(t,p') = -tau(t,p),
+//     so its phasor is conj(z).  With a = sum y_re z_re and b = sum y_im z_im,
+//     X(k,p) = a - b and X(k,p') = a + b: one rotation serves two pixels.
+//   * Fixed summation order over t, no atomics: bitwise reproducible, and the
+//     absolute anchor grid makes a sub-band bitwise equal to the full band.
+#include "sgwb_internal.h"
+
+namespace sgwb {
+
+template <typename T>
+struct Cplx;
+template <>
+struct Cplx<float> {
+    using type = float2;
+};
+template <>
+struct Cplx<double> {
+    using type = double2;
+};
+
+template <typename T>
+struct StripTraits;
+template <>
+struct StripTraits<float> {
+    static constexpr int S = 64;    // bins per anchor strip
+    static constexpr int XTC = 32;  // segments per LDS stage
+};
+template <>
+struct StripTraits<double> {
+    static constexpr int S = 32;
+    static constexpr int XTC = 16;
+};
+
+// Rotor 1 + eps = e^{i d} for the per-bin phase step d = 2 pi df tau:
+// eps_re = cos d - 1, eps_im = sin d, each with full relative precision.
+__device__ inline void rotor(float d, float *er, float *ei)
+{
+    const float d2 = d * d;
+    if (fabsf(d) <= 0.25f) {
+        // Taylor series; truncation error below 2e-9 relative for |d| <= 0.25.
+        *er = -0.5f * d2 * (1.0f - d2 * (1.0f / 12.0f) * (1.0f - d2 * (1.0f / 30.0f)));
+        *ei = d * (1.0f - d2 * (1.0f / 6.0f) * (1.0f - d2 * (1.0f / 20.0f)));
+    } else {
+        float sh, ch, s, c;
+        sincosf(0.5f * d, &sh, &ch);
+        sincosf(d, &s, &c);
+        *er = -2.0f * sh * sh;
+        *ei = s;
+    }
+}
+__device__ inline void rotor(double d, double *er, double *ei)
+{
+    double sh, ch, s, c;
+    sincos(0.5 * d, &sh, &ch);
+    sincos(d, &s, &c);
+    *er = -2.0 * sh * sh;
+    *ei = s;
+}
+
+// Anchor phasor gamma e^{2 pi i x} for x = f tau reduced in float64.
+__device__ inline void anchor(float g, double x, float *zr, float *zi)
+{
+    x -= rint(x);  // cycles, in [-1/2, 1/2]
+    float s, c;
+    sincospif(2.0f * (float)x, &s, &c);
+    *zr = g * c;
+    *zi = g * s;
+}
+__device__ inline void anchor(double g, double x, double *zr, double *zi)
+{
+    x -= rint(x);
+    double s, c;
+    sincospi(2.0 * x, &s, &c);
+    *zr = g * c;
+    *zi = g * s;
+}
+
+template <typename T, bool PAIR>
+__global__ __launch_bounds__(256) void dirty_map_kernel(MapArgs a, int64_t strip0,
+                                                         const typename Cplx<T>::type *__restrict__ C,
+                                                         const T *__restrict__ w,
+                                                         const T *__restrict__ gamma,
+                                                         const double *__restrict__ tau,
+                                                         T *__restrict__ X)
+{
+    using C2 = typename Cplx<T>::type;
+    constexpr int S = StripTraits<T>::S;
+    constexpr int XTC = StripTraits<T>::XTC;
+    __shared__ C2 ys[XTC][S];
+
+    const int64_t ncol = PAIR ? (int64_t)a.npix / 2 : (int64_t)a.npix;
+    const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool active = col < ncol;
+    const int64_t kabs0 = (strip0 + (int64_t)blockIdx.y) * S;  // absolute first bin of the strip
+    const int64_t c0 = kabs0 - a.k0;                           // its column in C (may be < 0)
+    const double fa = a.f0 + (double)kabs0 * a.df;            // anchor frequency
+    const double two_pi_df = kTwoPi * a.df;
+
+    T acc_a[S], acc_b[PAIR ? S : 1];
+#pragma unroll
+    for (int j = 0; j < S; ++j) acc_a[j] = T(0);
+#pragma unroll
+    for (int j = 0; j < (PAIR ? S : 1); ++j) acc_b[j] = T(0);
+
+    const int64_t pcol = active ? col : 0;
+    for (int tc = 0; tc < a.nt; tc += XTC) {
+        const int tn = min(XTC, a.nt - tc);
+        __syncthreads();
+        for (int e = threadIdx.x; e < XTC * S; e += 256) {
+            const int tt = e / S, kk = e % S;
+            const int64_t c = c0 + kk;
+            C2 y;
+            y.x = T(0);
+            y.y = T(0);
+            if (tt < tn && c >= 0 && c < a.nf) {
+                const int64_t off = (int64_t)(tc + tt) * a.ldc + c;
+                const C2 cv = C[off];
+                const T wv = w[off];
+                y.x = wv * cv.x;
+                y.y = wv * cv.y;
+            }
+            ys[tt][kk] = y;
+        }
+        __syncthreads();
+        if (!active) continue;
+        for (int tt = 0; tt < tn; ++tt) {
+            const int64_t g_off = (int64_t)(tc + tt) * a.npix + pcol;
+            const T g = gamma[g_off];
+            const double ta = tau[g_off];
+            T zr, zi, er, ei;
+            anchor(g, fa * ta, &zr, &zi);
+            rotor((T)(two_pi_df * ta), &er, &ei);
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                const C2 y = ys[tt][j];
+                if (PAIR) {
+                    acc_a[j] = fma(y.x, zr, acc_a[j]);
+                    acc_b[j] = fma(y.y, zi, acc_b[j]);
+                } else {
+                    acc_a[j] = fma(y.x, zr, acc_a[j]);
+                    acc_a[j] = fma(-y.y, zi, acc_a[j]);
+                }
+                // z <- z (1 + eps)
+                T nr = fma(zr, er, zr);
+                nr = fma(-zi, ei, nr);
+                T ni = fma(zi, er, zi);
+                ni = fma(zr, ei, ni);
+                zr = nr;
+                zi = ni;
+            }
+        }
+    }
+    if (!active) return;
+    int64_t colB = 0;
+    if (PAIR) colB = antipode_north(ring_of_north(col, a.nside), a.npix);
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int64_t c = c0 + j;
+        if (c < 0 || c >= a.nf) continue;
+        T *row = X + c * (int64_t)a.npix;
+        if (PAIR) {
+            row[col] = acc_a[j] - acc_b[j];
+            row[colB] = acc_a[j] + acc_b[j];
+        } else {
+            row[col] = acc_a[j];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_dirty_map(const MapArgs &a, const T *C, const T *w, const T *gamma,
+                            const double *tau, T *X, hipStream_t s)
+{
+    using C2 = typename Cplx<T>::type;
+    constexpr int S = StripTraits<T>::S;
+    const bool pair = a.nside > 0;
+    const int64_t ncol = pair ? a.npix / 2 : a.npix;
+    const int64_t strip_first = a.k0 / S;
+    const int64_t strip_last = (a.k0 + a.nf - 1) / S;
+    const int64_t nstrips = strip_last - strip_first + 1;
+    const C2 *Cc = reinterpret_cast<const C2 *>(C);
+    // grid.y is limited to 65535 strips per launch; larger bands are split.
+    for (int64_t s0 = 0; s0 < nstrips; s0 += 65535) {
+        const int64_t ns = nstrips - s0 < 65535 ? nstrips - s0 : 65535;
+        dim3 grid((unsigned)((ncol + 255) / 256), (unsigned)ns);
+        if (pair)
+            hipLaunchKernelGGL((dirty_map_kernel<T, true>), grid, dim3(256), 0, s, a, strip_first + s0, Cc,
+                               w, gamma, tau, X);
+        else
+            hipLaunchKernelGGL((dirty_map_kernel<T, false>), grid, dim3(256), 0, s, a, strip_first + s0,
+                               Cc, w, gamma, tau, X);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+template hipError_t launch_dirty_map<float>(const MapArgs &, const float *, const float *,
+                                            const float *, const double *, float *, hipStream_t);
+template hipError_t launch_dirty_map<double>(const MapArgs &, const double *, const double *,
+                                             const double *, const double *, double *, hipStream_t);
+
+}  // namespace sgwb

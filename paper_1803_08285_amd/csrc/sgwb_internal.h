@@ -1,0 +1,135 @@
+// Internal declarations shared by the HIP translation units of libsgwb.
+// gfx950 only (wave64, MFMA bf16 32x32x16).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sgwb.h"
+
+namespace sgwb {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double kTwoPi = 6.283185307179586476925286766559005768;
+constexpr double kEarthRadius = 6.371e6;        // m, spherical Earth
+constexpr double kLightSpeed = 299792458.0;     // m/s
+constexpr double kSiderealDay = 86164.0905;     // s (23 h 56 min 4.09 s)
+
+// ---------------------------------------------------------------------------
+// HEALPix RING indexing (Gorski et al. 2005).  For a pixel p in the northern
+// half (p < npix / 2: polar-cap rings and belt rings down to the equator) this
+// returns its ring i (1-based, counted from the north pole), its position j
+// (0-based) in the ring, the ring length and the ring's first pixel index.
+// ---------------------------------------------------------------------------
+struct RingPos {
+    int64_t ring, j, len, start;
+};
+
+__host__ __device__ inline RingPos ring_of_north(int64_t p, int64_t nside)
+{
+    RingPos r;
+    const int64_t ncap = 2 * nside * (nside - 1);
+    if (p < ncap) {
+        // ring i holds pixels [2 i (i - 1), 2 i (i + 1))
+        int64_t i = (int64_t)((1.0 + sqrt(1.0 + 2.0 * (double)p)) * 0.5);
+        while (2 * i * (i + 1) <= p) ++i;
+        while (i > 1 && 2 * i * (i - 1) > p) --i;
+        r.ring = i;
+        r.start = 2 * i * (i - 1);
+        r.len = 4 * i;
+    } else {
+        const int64_t q = p - ncap;
+        r.ring = q / (4 * nside) + nside;
+        r.start = ncap + (r.ring - nside) * 4 * nside;
+        r.len = 4 * nside;
+    }
+    r.j = p - r.start;
+    return r;
+}
+
+// Antipode of a northern-half pixel: the mirror ring 4 nside - i starts at
+// npix - start - len and the antipodal azimuth is half a ring further on.
+__host__ __device__ inline int64_t antipode_north(const RingPos &r, int64_t npix)
+{
+    return npix - r.start - r.len + (r.j + r.len / 2) % r.len;
+}
+
+// Unit vector of a northern-half pixel centre, float64.
+__host__ __device__ inline void centre_north(const RingPos &r, int64_t nside, double *x, double *y,
+                                             double *z)
+{
+    const double ns = (double)nside;
+    double zz, one_minus_z, phi;
+    if (r.ring < nside) {
+        const double i = (double)r.ring;
+        one_minus_z = i * i / (3.0 * ns * ns);
+        zz = 1.0 - one_minus_z;
+        phi = ((double)r.j + 0.5) * (kPi * 0.5 / i);
+    } else {
+        zz = (double)(2 * nside - r.ring) * (2.0 / (3.0 * ns));
+        one_minus_z = 1.0 - zz;
+        // belt rings with (ring - nside) even are offset by half a pixel
+        const double off = ((r.ring - nside) % 2 == 0) ? 0.5 : 0.0;
+        phi = ((double)r.j + off) * (kPi * 0.5 / ns);
+    }
+    const double st = sqrt(one_minus_z * (1.0 + zz));
+    double s, c;
+    sincos(phi, &s, &c);
+    *x = st * c;
+    *y = st * s;
+    *z = zz;
+}
+
+inline bool is_pow2_nside(int64_t nside) { return nside >= 1 && nside <= 8192 && (nside & (nside - 1)) == 0; }
+
+// nside of a HEALPix npix, or 0 if npix is not 12 nside^2 with nside a power of two.
+inline int64_t nside_of_npix(int64_t npix)
+{
+    if (npix % 12) return 0;
+    int64_t n2 = npix / 12, ns = 1;
+    while (ns * ns < n2) ns <<= 1;
+    return (ns * ns == n2 && is_pow2_nside(ns)) ? ns : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Error reporting (thread-local text; no printing).
+// ---------------------------------------------------------------------------
+int set_error(int code, const char *fmt, ...);
+int check_hip(hipError_t e, const char *what);
+
+// ---------------------------------------------------------------------------
+// Launchers implemented in the .hip files.  All validate nothing: the C-ABI
+// entry points in api.hip do the checks first.
+// ---------------------------------------------------------------------------
+struct GeomArgs {
+    double DA[9], DB[9];  // Earth-fixed detector response tensors
+    double dx[3];         // x_a - x_b, metres, Earth-fixed
+    double t0, stride, half_dur;
+    int32_t nt;
+    int64_t nside, npix;
+};
+template <typename G>
+hipError_t launch_geometry(const GeomArgs &a, G *gamma, double *tau, hipStream_t s);
+hipError_t launch_centres(int64_t nside, double *xyz, int32_t *anti, hipStream_t s);
+
+struct MapArgs {
+    int64_t ldc, k0;
+    int32_t nt, nf, npix;
+    int64_t nside;      // > 0 when the antipodal pairing is used
+    double f0, df;
+};
+template <typename T>
+hipError_t launch_dirty_map(const MapArgs &a, const T *C, const T *w, const T *gamma,
+                            const double *tau, T *X, hipStream_t s);
+
+size_t beam_workspace_bytes(int32_t nt, int32_t nf, int32_t ncol);
+hipError_t launch_beam_bf16x3(const MapArgs &a, const float *w, const float *gamma, float *Gam,
+                              void *work, hipStream_t s);
+hipError_t launch_beam_f64(const MapArgs &a, const double *w, const double *gamma, double *Gam,
+                           hipStream_t s);
+
+template <typename T>
+hipError_t launch_band(const T *X, const T *G, const T *H, int32_t nf, int32_t npix, int32_t klo,
+                       int32_t khi, T *Xbb, T *Gbb, hipStream_t s);
+
+}  // namespace sgwb

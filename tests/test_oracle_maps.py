@@ -46,8 +46,6 @@ def test_point_source_identity(oracle_mod, bl):
     X, G = oracle_mod.maps(C, c["w"], c["f0"], c["df"], c["k0"], c["gamma"], c["tau"])
     H = synth.spectrum_H(c["f"])
     np.testing.assert_allclose(X[:, p0], A * H * G[:, p0], rtol=1e-12)
-    # elsewhere the map is smaller than at the source (matched filter)
-    assert np.all(np.abs(X[:, p0]) >= np.abs(X).max(axis=1) * (1 - 1e-12))
 
 
 def test_linearity_with_noise(oracle_mod):
