@@ -74,7 +74,7 @@ def cpu_baseline(inp, wl, target_s=CPU_BASELINE_TARGET_S):
     t0 = time.perf_counter()
     oracle.maps_at(inp["C_host"], inp["w_host"], fgd.f0, fgd.df, fgd.k0, gh, th, cols, pix, nthreads=threads)
     dt0 = time.perf_counter() - t0
-    n = int(max(n0, min(5e6, n0 * target_s / max(dt0, 1e-3))))
+    n = int(max(n0, min(4e7, n0 * target_s / max(dt0, 1e-3))))
     cols = rng.integers(0, fgd.nf, n)
     pix = rng.integers(0, npix, n)
     t0 = time.perf_counter()
@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=2, help="2: full band nside 32; 3: full band nside 64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path shards by "
@@ -150,6 +152,16 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     terms = tg.nt * fgd.nf * npix
     x_tflops = X_FLOPS_PER_TERM * terms / (t_x.mean() * 1e-3) / 1e12
+
+    if args.copy_calib_mib:
+        nbytes = args.copy_calib_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nbytes} bytes read, {nbytes} bytes written")
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -129,10 +129,17 @@ int sgwb_make_maps_f64(const double *C, const double *w, int64_t ldc, int32_t nt
  * (w = H / P^2 already carries one factor of H into X and Gam).  X, Gam are
  * [nf][npix]; H[nf] is indexed like the rows.  Sums run in float64 in a fixed
  * order and are rounded once.  Either of X/Xbb or Gam/Gbb may be NULL.
- * Errors: SGWB_EINVAL if 0 <= k_lo <= k_hi <= nf fails or a needed pointer
- * is null.                                                                  */
+ * Workspace (optional, caller-owned device memory, 256-byte aligned, at least
+ * sgwb_reduce_band_workspace_size() bytes): with it the rows are reduced in
+ * parallel slabs (needs npix % 4 == 0 and 16-byte aligned maps), without it
+ * (NULL) a single-pass kernel runs.  Results are reproducible for a given
+ * choice; the two choices may differ in the last bit.
+ * Errors: SGWB_EINVAL if 0 <= k_lo <= k_hi <= nf fails, a needed pointer
+ * is null or the workspace is misaligned.                                    */
+size_t sgwb_reduce_band_workspace_size(int32_t npix, int32_t k_lo, int32_t k_hi);
 int sgwb_reduce_band(const float *X, const float *Gam, const float *H, int32_t nf, int32_t npix,
-                     int32_t k_lo, int32_t k_hi, float *Xbb, float *Gbb, hipStream_t stream);
+                     int32_t k_lo, int32_t k_hi, float *Xbb, float *Gbb, void *workspace,
+                     size_t workspace_bytes, hipStream_t stream);
 int sgwb_reduce_band_f64(const double *X, const double *Gam, const double *H, int32_t nf,
                          int32_t npix, int32_t k_lo, int32_t k_hi, double *Xbb, double *Gbb,
                          hipStream_t stream);

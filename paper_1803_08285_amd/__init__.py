@@ -56,7 +56,8 @@ _SIGNATURES = {
                         ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_make_maps_f64": ([_VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
                             ctypes.c_uint32, _VP, _VP, _VP], ctypes.c_int),
-    "sgwb_reduce_band": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
+    "sgwb_reduce_band_workspace_size": ([_I32, _I32, _I32], ctypes.c_size_t),
+    "sgwb_reduce_band": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_reduce_band_f64": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
     "sgwb_healpix_centres": ([_I32, _VP, _VP, _VP], ctypes.c_int),
     "sgwb_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -239,9 +240,17 @@ def make_maps(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamma: to
     return X, G
 
 
+def band_workspace_bytes(npix: int, k_lo: int, k_hi: int) -> int:
+    return int(lib().sgwb_reduce_band_workspace_size(npix, k_lo, k_hi))
+
+
 def reduce_band(X: torch.Tensor | None, G: torch.Tensor | None, H: torch.Tensor | None, k_lo: int, k_hi: int,
-                out=None):
-    """Broadband Xbb = sum_k X[k], Gbb = sum_k H[k] G[k] over rows [k_lo, k_hi)."""
+                out=None, workspace: torch.Tensor | None | bool = True):
+    """Broadband Xbb = sum_k X[k], Gbb = sum_k H[k] G[k] over rows [k_lo, k_hi).
+
+    workspace: a uint8 device tensor, True to allocate one (parallel slab
+    reduction), or None for the single-pass kernel.
+    """
     ref = X if X is not None else G
     if ref is None:
         raise SgwbError("reduce_band: X or G needed")
@@ -261,10 +270,21 @@ def reduce_band(X: torch.Tensor | None, G: torch.Tensor | None, H: torch.Tensor 
         Xbb = torch.empty(npix, dtype=rdt, device=ref.device)
     if G is not None and Gbb is None:
         Gbb = torch.empty(npix, dtype=rdt, device=ref.device)
-    fn = lib().sgwb_reduce_band_f64 if rdt == torch.float64 else lib().sgwb_reduce_band
     with torch.cuda.device(ref.device):
-        _check(fn(_ptr(X), _ptr(G), _ptr(H) if G is not None else None, nf, npix, int(k_lo), int(k_hi), _ptr(Xbb),
-                  _ptr(Gbb), _stream()), "reduce_band")
+        if rdt == torch.float64:
+            rc = lib().sgwb_reduce_band_f64(_ptr(X), _ptr(G), _ptr(H) if G is not None else None, nf, npix,
+                                            int(k_lo), int(k_hi), _ptr(Xbb), _ptr(Gbb), _stream())
+        else:
+            ws = None
+            if workspace is True:
+                n = band_workspace_bytes(npix, k_lo, k_hi)
+                ws = torch.empty(max(n, 256), dtype=torch.uint8, device=ref.device) if n else None
+            elif isinstance(workspace, torch.Tensor):
+                ws = workspace
+            wsz = ws.numel() if ws is not None else 0
+            rc = lib().sgwb_reduce_band(_ptr(X), _ptr(G), _ptr(H) if G is not None else None, nf, npix,
+                                        int(k_lo), int(k_hi), _ptr(Xbb), _ptr(Gbb), _ptr(ws), wsz, _stream())
+    _check(rc, "reduce_band")
     return Xbb, Gbb
 
 

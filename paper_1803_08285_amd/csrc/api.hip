@@ -119,7 +119,7 @@ static int check_maps_args(const T *C, const T *w, int64_t ldc, int32_t nt, int3
 
 template <typename T>
 static int reduce_band_impl(const T *X, const T *Gam, const T *H, int32_t nf, int32_t npix, int32_t k_lo,
-                            int32_t k_hi, T *Xbb, T *Gbb, hipStream_t stream)
+                            int32_t k_hi, T *Xbb, T *Gbb, void *work, size_t work_bytes, hipStream_t stream)
 {
     if (nf < 1 || npix < 1) return set_error(SGWB_EINVAL, "reduce_band: nf, npix must be >= 1");
     if (!(0 <= k_lo && k_lo <= k_hi && k_hi <= nf))
@@ -129,8 +129,9 @@ static int reduce_band_impl(const T *X, const T *Gam, const T *H, int32_t nf, in
         return set_error(SGWB_EINVAL, "reduce_band: X/Xbb and Gam/Gbb must be given in pairs");
     if (!doX && !doG) return set_error(SGWB_EINVAL, "reduce_band: nothing to do");
     if (doG && !H) return set_error(SGWB_EINVAL, "reduce_band: H needed for Gbb");
+    if (work && ((uintptr_t)work % 256)) return set_error(SGWB_EINVAL, "reduce_band: workspace not 256-byte aligned");
     return check_hip(launch_band<T>(doX ? X : nullptr, doG ? Gam : nullptr, H, nf, npix, k_lo, k_hi,
-                                    doX ? Xbb : nullptr, doG ? Gbb : nullptr, stream),
+                                    doX ? Xbb : nullptr, doG ? Gbb : nullptr, work, work_bytes, stream),
                      "band kernel launch");
 }
 
@@ -226,16 +227,23 @@ int sgwb_make_maps_f64(const double *C, const double *w, int64_t ldc, int32_t nt
     return SGWB_OK;
 }
 
-int sgwb_reduce_band(const float *X, const float *Gam, const float *H, int32_t nf, int32_t npix, int32_t k_lo,
-                     int32_t k_hi, float *Xbb, float *Gbb, hipStream_t stream)
+size_t sgwb_reduce_band_workspace_size(int32_t npix, int32_t k_lo, int32_t k_hi)
 {
-    return reduce_band_impl<float>(X, Gam, H, nf, npix, k_lo, k_hi, Xbb, Gbb, stream);
+    if (npix < 1 || k_lo < 0 || k_hi <= k_lo) return 0;
+    return band_workspace_bytes(npix, k_lo, k_hi);
+}
+
+int sgwb_reduce_band(const float *X, const float *Gam, const float *H, int32_t nf, int32_t npix, int32_t k_lo,
+                     int32_t k_hi, float *Xbb, float *Gbb, void *workspace, size_t workspace_bytes,
+                     hipStream_t stream)
+{
+    return reduce_band_impl<float>(X, Gam, H, nf, npix, k_lo, k_hi, Xbb, Gbb, workspace, workspace_bytes, stream);
 }
 
 int sgwb_reduce_band_f64(const double *X, const double *Gam, const double *H, int32_t nf, int32_t npix,
                          int32_t k_lo, int32_t k_hi, double *Xbb, double *Gbb, hipStream_t stream)
 {
-    return reduce_band_impl<double>(X, Gam, H, nf, npix, k_lo, k_hi, Xbb, Gbb, stream);
+    return reduce_band_impl<double>(X, Gam, H, nf, npix, k_lo, k_hi, Xbb, Gbb, nullptr, 0, stream);
 }
 
 int sgwb_healpix_centres(int32_t nside, double *xyz, int32_t *anti, hipStream_t stream)

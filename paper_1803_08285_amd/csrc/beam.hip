@@ -89,8 +89,69 @@ __global__ __launch_bounds__(256) void prep_frag_kernel(const float *__restrict_
     dst[frag_index(blk, ks, 1, lane, fd.nks)] = lo;
 }
 
-// Each wave computes a (WM x 32) x (WN x 32) tile of Gam; waves are independent.
-constexpr int WM = 2, WN = 2;
+// Each wave computes a (WM x 32) x (WN x 32) tile of Gam; waves are independent
+// and read their operand fragments straight from L2 (the fragment arrays are
+// small: every fragment is reused by all waves of its tile row or column).
+// The next K-step's fragments are loaded while the current step's MFMAs run.
+constexpr int WM = 4, WN = 4;
+
+struct Frags {
+    uint4 a[WM][2], b[WN][2];
+};
+
+__device__ inline void load_frags(Frags &f, const uint4 *__restrict__ Wf, const uint4 *__restrict__ Gf,
+                                  int64_t tm, int64_t tn, int64_t ks, const FragDims &fm, const FragDims &fn,
+                                  int lane)
+{
+    const uint4 zero4 = make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+        const int64_t mb = tm * WM + i;
+#pragma unroll
+        for (int part = 0; part < 2; ++part)
+            f.a[i][part] = mb < fm.nblk ? Wf[frag_index(mb, ks, part, lane, fm.nks)] : zero4;
+    }
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+        const int64_t nb = tn * WN + j;
+#pragma unroll
+        for (int part = 0; part < 2; ++part)
+            f.b[j][part] = nb < fn.nblk ? Gf[frag_index(nb, ks, part, lane, fn.nks)] : zero4;
+    }
+}
+
+// Wave-tile order.  Workgroups are dispatched round-robin over the 8 XCDs
+// (each with its own L2), so workgroup b runs on XCD b % 8.  The tile grid is
+// cut into patches of kPatch x kPatch wave tiles; XCD x works through patches
+// x, x + 8, x + 16, ... and the 16 workgroups (64 waves) of a patch share its
+// 8 bin tiles and 8 pixel tiles through that XCD's L2.
+constexpr int kXcds = 8;
+constexpr int kPatch = 8;
+constexpr int kWavesPerWg = 4;
+constexpr int kWgPerPatch = kPatch * kPatch / kWavesPerWg;
+
+__device__ inline bool patch_tile(int64_t b, int w, int64_t tiles_m, int64_t tiles_n, int64_t *tm, int64_t *tn)
+{
+    const int64_t pm = (tiles_m + kPatch - 1) / kPatch, pn = (tiles_n + kPatch - 1) / kPatch;
+    const int64_t xcd = b % kXcds, l = b / kXcds;
+    const int64_t patch = xcd + kXcds * (l / kWgPerPatch);
+    if (patch >= pm * pn) return false;
+    const int64_t in = (l % kWgPerPatch) * kWavesPerWg + w;  // 0 .. 63 inside the patch
+    // patches walk the bin direction fastest, so neighbouring patches share pixel tiles
+    const int64_t pi = patch % pm, pj = patch / pm;
+    *tm = pi * kPatch + in % kPatch;
+    *tn = pj * kPatch + in / kPatch;
+    return *tm < tiles_m && *tn < tiles_n;
+}
+
+// Number of workgroups that covers every patch for the XCD-striped order.
+__host__ inline int64_t patch_grid(int64_t tiles_m, int64_t tiles_n)
+{
+    const int64_t pm = (tiles_m + kPatch - 1) / kPatch, pn = (tiles_n + kPatch - 1) / kPatch;
+    const int64_t patches = pm * pn;
+    const int64_t per_xcd = (patches + kXcds - 1) / kXcds;
+    return per_xcd * kWgPerPatch * kXcds;
+}
 
 __global__ __launch_bounds__(256) void beam_gemm_kernel(const uint4 *__restrict__ Wf,
                                                          const uint4 *__restrict__ Gf, FragDims fm,
@@ -99,12 +160,10 @@ __global__ __launch_bounds__(256) void beam_gemm_kernel(const uint4 *__restrict_
                                                          float *__restrict__ Gam)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t tiles_m = (fm.nblk + WM - 1) / WM;
     const int64_t tiles_n = (fn.nblk + WN - 1) / WN;
-    if (wave >= tiles_m * tiles_n) return;
-    const int64_t tm = wave / tiles_n;
-    const int64_t tn = wave % tiles_n;
+    int64_t tm, tn;
+    if (!patch_tile(blockIdx.x, threadIdx.x >> 6, tiles_m, tiles_n, &tm, &tn)) return;
     const int64_t nks = fm.nks;
 
     f32x16 acc[WM][WN];
@@ -115,35 +174,23 @@ __global__ __launch_bounds__(256) void beam_gemm_kernel(const uint4 *__restrict_
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-    const uint4 zero4 = make_uint4(0, 0, 0, 0);
+    Frags cur, nxt;
+    load_frags(cur, Wf, Gf, tm, tn, 0, fm, fn, lane);
     for (int64_t ks = 0; ks < nks; ++ks) {
-        uint4 af[WM][2], bf[WN][2];
-#pragma unroll
-        for (int i = 0; i < WM; ++i) {
-            const int64_t mb = tm * WM + i;
-#pragma unroll
-            for (int part = 0; part < 2; ++part)
-                af[i][part] = mb < fm.nblk ? Wf[frag_index(mb, ks, part, lane, nks)] : zero4;
-        }
-#pragma unroll
-        for (int j = 0; j < WN; ++j) {
-            const int64_t nb = tn * WN + j;
-#pragma unroll
-            for (int part = 0; part < 2; ++part)
-                bf[j][part] = nb < fn.nblk ? Gf[frag_index(nb, ks, part, lane, nks)] : zero4;
-        }
+        if (ks + 1 < nks) load_frags(nxt, Wf, Gf, tm, tn, ks + 1, fm, fn, lane);
 #pragma unroll
         for (int i = 0; i < WM; ++i)
 #pragma unroll
             for (int j = 0; j < WN; ++j) {
-                const bf16x8 ah = __builtin_bit_cast(bf16x8, af[i][0]);
-                const bf16x8 al = __builtin_bit_cast(bf16x8, af[i][1]);
-                const bf16x8 bh = __builtin_bit_cast(bf16x8, bf[j][0]);
-                const bf16x8 bl = __builtin_bit_cast(bf16x8, bf[j][1]);
+                const bf16x8 ah = __builtin_bit_cast(bf16x8, cur.a[i][0]);
+                const bf16x8 al = __builtin_bit_cast(bf16x8, cur.a[i][1]);
+                const bf16x8 bh = __builtin_bit_cast(bf16x8, cur.b[j][0]);
+                const bf16x8 bl = __builtin_bit_cast(bf16x8, cur.b[j][1]);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[i][j], 0, 0, 0);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[i][j], 0, 0, 0);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[i][j], 0, 0, 0);
             }
+        if (ks + 1 < nks) cur = nxt;
     }
 
     // Accumulator layout of the 32x32 MFMA: lane l holds column l % 32 and rows
@@ -188,8 +235,8 @@ hipError_t launch_beam_bf16x3(const MapArgs &a, const float *w, const float *gam
                        a.ldc, a.nt, (int64_t)a.nf, fm, Wf);
     hipLaunchKernelGGL(prep_frag_kernel<true>, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, gamma,
                        (int64_t)a.npix, a.nt, ncol, fn, Gf);
-    const int64_t waves = ((fm.nblk + WM - 1) / WM) * ((fn.nblk + WN - 1) / WN);
-    hipLaunchKernelGGL(beam_gemm_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, Wf, Gf, fm, fn,
+    const int64_t grid = patch_grid((fm.nblk + WM - 1) / WM, (fn.nblk + WN - 1) / WN);
+    hipLaunchKernelGGL(beam_gemm_kernel, dim3((unsigned)grid), dim3(256), 0, s, Wf, Gf, fm, fn,
                        a.nf, ncol, a.npix, pair ? a.nside : (int64_t)0, Gam);
     return hipGetLastError();
 }

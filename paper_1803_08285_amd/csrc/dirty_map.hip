@@ -72,17 +72,34 @@ __device__ inline void rotor(double d, double *er, double *ei)
     *ei = s;
 }
 
-// Anchor phasor gamma e^{2 pi i x} for x = f tau reduced in float64.
-__device__ inline void anchor(float g, double x, float *zr, float *zi)
+// Anchor phasor gamma e^{2 pi i x} for x = f tau cycles, given as x4 = 4 x.
+// float64 reduction to the nearest quarter turn q (x4 - q in [-1/2, 1/2]),
+// Taylor series for sin and cos on |theta| <= pi/4 (truncation below 3e-8),
+// then a rotation by i^q.
+__device__ inline void anchor4(float g, double x4, float *zr, float *zi)
 {
-    x -= rint(x);  // cycles, in [-1/2, 1/2]
-    float s, c;
-    sincospif(2.0f * (float)x, &s, &c);
-    *zr = g * c;
-    *zi = g * s;
+    const double q = rint(x4);
+    const float th = (float)(x4 - q) * 1.57079632679489662f;
+    const int m = (int)q & 3;
+    const float t2 = th * th;
+    const float s =
+        th * fmaf(t2, fmaf(t2, fmaf(t2, fmaf(t2, 2.75573192e-6f, -1.98412698e-4f), 8.33333333e-3f),
+                           -1.66666667e-1f),
+                  1.0f);
+    const float c =
+        fmaf(t2, fmaf(t2, fmaf(t2, fmaf(t2, 2.48015873e-5f, -1.38888889e-3f), 4.16666667e-2f), -0.5f), 1.0f);
+    float cr = (m & 1) ? -s : c;
+    float ci = (m & 1) ? c : s;
+    if (m & 2) {
+        cr = -cr;
+        ci = -ci;
+    }
+    *zr = g * cr;
+    *zi = g * ci;
 }
-__device__ inline void anchor(double g, double x, double *zr, double *zi)
+__device__ inline void anchor4(double g, double x4, double *zr, double *zi)
 {
+    double x = 0.25 * x4;
     x -= rint(x);
     double s, c;
     sincospi(2.0 * x, &s, &c);
@@ -108,7 +125,7 @@ __global__ __launch_bounds__(256) void dirty_map_kernel(MapArgs a, int64_t strip
     const bool active = col < ncol;
     const int64_t kabs0 = (strip0 + (int64_t)blockIdx.y) * S;  // absolute first bin of the strip
     const int64_t c0 = kabs0 - a.k0;                           // its column in C (may be < 0)
-    const double fa = a.f0 + (double)kabs0 * a.df;            // anchor frequency
+    const double fa4 = 4.0 * (a.f0 + (double)kabs0 * a.df);   // anchor frequency, quarter turns
     const double two_pi_df = kTwoPi * a.df;
 
     T acc_a[S], acc_b[PAIR ? S : 1];
@@ -143,7 +160,7 @@ __global__ __launch_bounds__(256) void dirty_map_kernel(MapArgs a, int64_t strip
             const T g = gamma[g_off];
             const double ta = tau[g_off];
             T zr, zi, er, ei;
-            anchor(g, fa * ta, &zr, &zi);
+            anchor4(g, fa4 * ta, &zr, &zi);
             rotor((T)(two_pi_df * ta), &er, &ei);
 #pragma unroll
             for (int j = 0; j < S; ++j) {

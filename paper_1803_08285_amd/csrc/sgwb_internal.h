@@ -128,8 +128,9 @@ hipError_t launch_beam_bf16x3(const MapArgs &a, const float *w, const float *gam
 hipError_t launch_beam_f64(const MapArgs &a, const double *w, const double *gamma, double *Gam,
                            hipStream_t s);
 
+size_t band_workspace_bytes(int32_t npix, int32_t klo, int32_t khi);
 template <typename T>
 hipError_t launch_band(const T *X, const T *G, const T *H, int32_t nf, int32_t npix, int32_t klo,
-                       int32_t khi, T *Xbb, T *Gbb, hipStream_t s);
+                       int32_t khi, T *Xbb, T *Gbb, void *work, size_t work_bytes, hipStream_t s);
 
 }  // namespace sgwb

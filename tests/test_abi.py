@@ -61,7 +61,7 @@ def test_host_side_validation_rejects_before_any_device_work():
     rc = L.sgwb_make_maps(dummy, dummy, 8, 10, 8, ctypes.byref(fg), 0, dummy, dummy, 768, 1, None, dummy, None, 0,
                           None)
     assert rc == -2
-    rc = L.sgwb_reduce_band(dummy, dummy, dummy, 10, 768, 4, 11, dummy, dummy, None)
+    rc = L.sgwb_reduce_band(dummy, dummy, dummy, 10, 768, 4, 11, dummy, dummy, None, 0, None)
     assert rc == -1
     bad = sg._FGrid(20.0, 0.0)
     rc = L.sgwb_make_maps(dummy, dummy, 8, 10, 8, ctypes.byref(bad), 0, dummy, dummy, 768, 1, dummy, None, None, 0,

@@ -170,6 +170,22 @@ def test_reduce_band_vs_oracle(sg, oracle_mod, klo, khi):
     assert np.all(np.abs(Gbb.cpu().numpy() - Go) <= 2 ** -24 * np.abs(Go) * 1.01 + 1e-300)
 
 
+def test_reduce_band_single_pass_matches_split(sg):
+    nside, nt, nf = 16, 40, 3000
+    g, t = _geom(sg, "AC", nside, synth.TGrid(nt, 0.0, 2154.0, 2154.0))
+    f = freqs(20.0, 1 / 32, 0, nf)
+    C, w = make_csd(8, nt, f)
+    X, G = sg.make_maps(torch.from_numpy(C).cuda(), torch.from_numpy(w).cuda(), sg.FGrid(20.0, 1 / 32), 0, g, t)
+    H = torch.from_numpy(synth.spectrum_H(f).astype(np.float32)).cuda()
+    a = sg.reduce_band(X, G, H, 11, 2990, workspace=True)
+    b = sg.reduce_band(X, G, H, 11, 2990, workspace=None)
+    c = sg.reduce_band(X, G, H, 11, 2990, workspace=True)
+    torch.cuda.synchronize()
+    for u, v in zip(a, b):
+        torch.testing.assert_close(u, v, rtol=2 ** -23, atol=0)
+    assert torch.equal(a[0], c[0]) and torch.equal(a[1], c[1])
+
+
 def test_reduce_band_float64(sg, oracle_mod):
     nside, nt, nf = 2, 10, 100
     g, t = _geom(sg, "AB", nside, synth.TGrid(nt, 0.0, 8616.0, 8616.0), dtype=torch.float64)
