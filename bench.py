@@ -86,6 +86,168 @@ def cpu_baseline(inp, wl, target_s=CPU_BASELINE_TARGET_S):
                       f"{dt:.1f} s wall on {threads} threads"}
 
 
+def bench_batched(args, torch, sg):
+    """Batched form: three baselines with uneven jobs in one plan (graph replay)
+    against the plain path (one make_maps + reduce_band call per job)."""
+    dev = torch.device("cuda:0")
+    jobs, terms = [], 0
+    for wl in synth.batched_jobs():
+        tg, fgd = wl.tgrid, wl.fgrid
+        npix = 12 * wl.nside ** 2
+        gamma, tau = sg.build_geometry(synth.baseline_sites(wl.baseline), wl.nside,
+                                       sg.TGrid(tg.nt, tg.t0, tg.stride, tg.dur), device=dev)
+        f = fgd.freqs()
+        C = synth.noise_csd(wl.noise_seed, tg.nt, f, dtype=np.complex64)
+        w = synth.weights(f, synth.segment_scale(tg.nt, wl.nonstationary_seed)).astype(np.float32)
+        Cd = torch.from_numpy(C).to(dev)
+        wd = torch.from_numpy(w).to(dev)
+        Hd = torch.from_numpy(synth.spectrum_H(f).astype(np.float32)).to(dev)
+        X = torch.empty((fgd.nf, npix), device=dev)
+        G = torch.empty_like(X)
+        Xbb = torch.empty(npix, device=dev)
+        Gbb = torch.empty_like(Xbb)
+        jobs.append(sg.Job(Cd, wd, sg.FGrid(fgd.f0, fgd.df), fgd.k0, gamma, tau, X=X, G=G, H=Hd,
+                           band=(0, fgd.nf), Xbb=Xbb, Gbb=Gbb))
+        terms += tg.nt * fgd.nf * npix
+        log(f"job {wl.name}: nside {wl.nside} nf {fgd.nf} k0 {fgd.k0}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = sg.Plan(jobs, autotune=True)
+    log(f"plan created in {time.perf_counter() - t0:.1f} s: {plan.describe()}")
+    ws = [sg.make_workspace(j.w.shape[0], j.w.shape[1], j.gamma.shape[1], True, device=dev) for j in jobs]
+
+    def plain():
+        for j, wsp in zip(jobs, ws):
+            sg.make_maps(j.C, j.w, j.fgrid, j.k0, j.gamma, j.tau, out=(j.X, j.G), workspace=wsp)
+            sg.reduce_band(j.X, j.G, j.H, *j.band, out=(j.Xbb, j.Gbb))
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    ms_plan = timed(plan.launch, args.steps)
+    log(f"plan: {ms_plan:.2f} ms per launch")
+    ms_plain = timed(plain, args.steps)
+    log(f"plain path: {ms_plain:.2f} ms per pass")
+    out = {
+        "metric": "map terms/s (t*f*pix) for X+Gamma", "value": terms / (ms_plan * 1e-3), "unit": "terms/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": ms_plan, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched_AB64_AC32_BC16", "terms_per_step": terms, "jobs": len(jobs),
+                   "parallelism": "single GPU"},
+        "plain_path": {"value": terms / (ms_plain * 1e-3), "ms_per_step": ms_plain},
+        "plan": plan.describe(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args, torch, sg):
+    """Serving form: Poisson streams of map queries against three resident
+    baselines, through the continuous-batching server and through the plain
+    per-query path (one query at a time, synchronous), same queries."""
+    dev = torch.device("cuda:0")
+    datasets = []
+    for i, bl in enumerate(("AB", "AC", "BC")):
+        tg, fgd = synth.TGRID_FULL, synth.FGRID_FULL
+        f = fgd.freqs()
+        C = synth.noise_csd(4 + i, tg.nt, f, dtype=np.complex64)
+        w = synth.weights(f, np.ones(tg.nt)).astype(np.float32)
+        datasets.append(sg.Dataset(torch.from_numpy(C).to(dev), torch.from_numpy(w).to(dev),
+                                   torch.from_numpy(synth.spectrum_H(f).astype(np.float32)).to(dev),
+                                   sg.FGrid(fgd.f0, fgd.df), fgd.k0, synth.baseline_sites(bl),
+                                   sg.TGrid(tg.nt, tg.t0, tg.stride, tg.dur)))
+        log(f"dataset {bl} resident")
+    nt = synth.TGRID_FULL.nt
+    srv = sg.Server(datasets, slots=args.slots, hbm_budget_bytes=args.arena_gib << 30)
+    # build every (baseline, nside) seed matrix once, as a long-running server would have
+    warm = [srv.submit(d, n, 0, 1) for d in range(3) for n in synth.NSIDES_SERVED]
+    while any(srv.poll(t) is None for t in warm):
+        time.sleep(0.001)
+    for t in warm:
+        srv.release(t)
+    geoms = {}
+
+    def plain_query(ds, nside, lo, hi):
+        d = datasets[ds]
+        if (ds, nside) not in geoms:
+            geoms[(ds, nside)] = sg.build_geometry(d.sites, nside, d.tgrid, device=dev)
+        g, t = geoms[(ds, nside)]
+        X, G = sg.make_maps(d.C[:, lo:hi], d.w[:, lo:hi], d.fgrid, d.k0 + lo, g, t)
+        sg.reduce_band(X, G, d.H[lo:hi], 0, hi - lo)
+        torch.cuda.synchronize()
+
+    for ds in range(3):  # warm the plain path's seeds too
+        for n in synth.NSIDES_SERVED:
+            plain_query(ds, n, 0, 1)
+
+    results = []
+    for rate in args.rates:
+        qs = synth.serving_queries(rate, args.duration)
+        terms = sum(nt * (hi - lo) * 12 * n * n for _, _, n, lo, hi in qs)
+        # server
+        t0 = time.perf_counter()
+        tickets = {}
+        i = 0
+        done = {}
+        while len(done) < len(qs):
+            now = time.perf_counter() - t0
+            while i < len(qs) and qs[i][0] <= now:
+                tk = srv.submit(*qs[i][1:])
+                if tk < 0:
+                    break
+                tickets[tk] = i
+                i += 1
+            for tk in list(tickets):
+                r = srv.poll(tk)
+                if r is not None:
+                    done[tk] = r
+                    srv.release(tk)
+                    del tickets[tk]
+            time.sleep(0.0002)
+        lat = np.array([r["t_done"] - r["t_submit"] for r in done.values()]) * 1e3
+        span = max(r["t_done"] for r in done.values()) - min(r["t_submit"] for r in done.values())
+        st = srv.stats()
+        log(f"rate {rate}/s server: {len(qs)} queries, p50 {np.percentile(lat, 50):.1f} ms, "
+            f"p99 {np.percentile(lat, 99):.1f} ms, {terms / span:.3e} terms/s")
+        # plain per-query path, same arrivals, first come first served
+        t0 = time.perf_counter()
+        plat = []
+        for (ta, ds, n, lo, hi) in qs:
+            now = time.perf_counter() - t0
+            if now < ta:
+                time.sleep(ta - now)
+            plain_query(ds, n, lo, hi)
+            plat.append((time.perf_counter() - t0 - ta) * 1e3)
+        pspan = time.perf_counter() - t0 - qs[0][0]
+        plat = np.array(plat)
+        log(f"rate {rate}/s plain: p50 {np.percentile(plat, 50):.1f} ms, p99 {np.percentile(plat, 99):.1f} ms, "
+            f"{terms / pspan:.3e} terms/s")
+        results.append({"rate_hz": rate, "queries": len(qs), "terms": terms,
+                        "server": {"terms_per_s": terms / span, "p50_ms": float(np.percentile(lat, 50)),
+                                   "p99_ms": float(np.percentile(lat, 99)), "arena_peak_bytes": st["arena_peak"]},
+                        "plain": {"terms_per_s": terms / pspan, "p50_ms": float(np.percentile(plat, 50)),
+                                  "p99_ms": float(np.percentile(plat, 99))}})
+    srv.close()
+    top = results[-1]
+    out = {
+        "metric": "map terms/s (t*f*pix) for X+Gamma; p50/p99 query latency", "value": top["server"]["terms_per_s"],
+        "unit": "terms/s", "n_gpus": 1, "steps": len(results), "warmup": 1, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving_poisson", "duration_s": args.duration, "slots": args.slots,
+                   "nsides": list(synth.NSIDES_SERVED), "max_band": 4096, "parallelism": "single GPU"},
+        "latency_ms": {"p50": top["server"]["p50_ms"], "p99": top["server"]["p99_ms"]},
+        "sweep": results,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +255,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=2, help="2: full band nside 32; 3: full band nside 64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched", action="store_true", help="batched plan of three uneven baseline jobs")
+    ap.add_argument("--serve", action="store_true", help="Poisson query stream through the server")
+    ap.add_argument("--rates", type=float, nargs="+", default=[25.0, 50.0, 100.0, 200.0])
+    ap.add_argument("--duration", type=float, default=5.0)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--arena-gib", type=int, default=64)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -107,6 +275,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.batched:
+        bench_batched(args, torch, sg)
+        return
+    if args.serve:
+        bench_serve(args, torch, sg)
+        return
     wl = synth.workload(args.workload)
     tg, fgd = wl.tgrid, wl.fgrid
     npix = 12 * wl.nside ** 2

@@ -37,7 +37,9 @@ extern "C" {
 #define SGWB_EINVAL (-1)       /* bad argument: null pointer, shape, nside, range  */
 #define SGWB_ENOMEM (-2)       /* workspace too small / allocation failed          */
 #define SGWB_EDEVICE (-3)      /* a HIP call failed (text in sgwb_last_error)       */
+#define SGWB_EBUSY (-4)        /* server queue full: submit again later            */
 #define SGWB_EUNSUPPORTED (-5) /* device is not gfx950, or option not available     */
+#define SGWB_EAGAIN 1          /* server query not finished yet (not an error)     */
 
 /* ---- geometry descriptions --------------------------------------------- */
 /* An L-shaped detector with horizontal arms on a sphere of radius 6.371e6 m.
@@ -143,6 +145,112 @@ int sgwb_reduce_band(const float *X, const float *Gam, const float *H, int32_t n
 int sgwb_reduce_band_f64(const double *X, const double *Gam, const double *H, int32_t nf,
                          int32_t npix, int32_t k_lo, int32_t k_hi, double *Xbb, double *Gbb,
                          hipStream_t stream);
+
+/* ---- batched plans ------------------------------------------------------
+ * Several map jobs (baselines, resolutions, uneven bands; Sec. III.C notes
+ * that maps of several baselines are made the same way and added) run as one
+ * persistent dirty-map launch over the concatenated tiles of all jobs and one
+ * persistent beam launch, together with each job's operand preparation and
+ * optional broadband reduction, captured once in a HIP graph.
+ * A job has the arguments of sgwb_make_maps (float32 only) plus an optional
+ * broadband reduction of rows [band_lo, band_hi) into Xbb/Gbb (H needed for
+ * Gbb).  The plan records the pointers: the caller keeps every buffer alive
+ * and unchanged in size until sgwb_plan_destroy, and may change their
+ * contents between launches.
+ * flags: SGWB_PLAN_AUTOTUNE times candidate schedules on the current device
+ * (a few seconds at full-band sizes, then cached on disk under the key of
+ * the device and the job shapes; SGWB_TUNE_CACHE names the cache file);
+ * without it the default schedule is used.  SGWB_PLAN_NO_GRAPH launches the
+ * kernels directly instead of replaying a graph.  The schedule never changes
+ * a result: maps are bitwise equal to the single-call path.
+ * plan_create allocates the workspaces and job tables (device memory owned by
+ * the plan) and synchronises the device; plan_launch allocates nothing and
+ * queues the graph asynchronously on `stream`.
+ * Errors: SGWB_EINVAL (a job fails the sgwb_make_maps checks, computes
+ * nothing, or has a bad band), SGWB_ENOMEM, SGWB_EDEVICE.                    */
+typedef struct {
+    const float *C, *w;
+    int64_t ldc;
+    int32_t nt, nf;
+    sgwb_fgrid fg;
+    int64_t k0;
+    const float *gamma;
+    const double *tau;
+    int32_t npix;
+    uint32_t flags;   /* SGWB_MAPS_ANTIPODAL */
+    float *X, *Gam;   /* [nf][npix]; either may be NULL */
+    const float *H;   /* [nf], for Gbb */
+    int32_t band_lo, band_hi;
+    float *Xbb, *Gbb; /* [npix] or NULL */
+} sgwb_job;
+typedef struct sgwb_plan sgwb_plan;
+#define SGWB_PLAN_AUTOTUNE 1u
+#define SGWB_PLAN_NO_GRAPH 2u
+int sgwb_plan_create(const sgwb_job *jobs /*host*/, int32_t njobs, uint32_t flags, sgwb_plan **out);
+int sgwb_plan_launch(sgwb_plan *plan, hipStream_t stream);
+void sgwb_plan_destroy(sgwb_plan *plan);
+/* JSON text describing the plan's schedule and tuning times (host buffer).  */
+int sgwb_plan_describe(const sgwb_plan *plan, char *buf, size_t len);
+
+/* ---- query server with continuous batching ------------------------------
+ * Serves broadband maps (Sec. V) of a baseline, resolution and contiguous
+ * band, from narrowband maps of that band (Eq. eq_dirtymap split per bin,
+ * Eq. eq_fisher diagonal): folding makes the day's data small enough to stay
+ * resident (Sec. I), so every query reuses it and the cached seeds.
+ * Datasets: the folded CSD C [nt][ldc] (interleaved complex float32), weights
+ * w [nt][ldc] and shape H [nf] of one baseline, covering absolute bins
+ * [k0, k0 + nf) of grid fg; device memory owned by the caller, kept alive and
+ * unchanged until sgwb_server_destroy.  The seeds of each (dataset, nside)
+ * are built on first use and kept.
+ * A worker thread admits queries in arrival order while one of `slots` HIP
+ * streams is free and the query's footprint (two band x npix float32 maps,
+ * the beam and band workspaces, the result, and new seeds) fits in an HBM
+ * arena of hbm_budget_bytes (0: 60 % of the free memory) reserved at
+ * creation; queries that arrive while others run are admitted as slots and
+ * memory free up, and their kernels overlap on the device.  A query larger
+ * than the whole arena fails with SGWB_ENOMEM; nothing is ever allocated
+ * after creation.  Results are bitwise the same alone and in any mix.
+ * submit is non-blocking (SGWB_EBUSY when queue_capacity queries are
+ * pending; SGWB_EINVAL for a bad query, before any device work).  poll
+ * returns SGWB_EAGAIN until the query is done, then SGWB_OK with the query's
+ * status, device pointers to its result (valid until release) and
+ * timestamps in seconds of the server clock.  fetch copies a finished result
+ * into caller memory on `stream`.  stats writes a JSON summary.
+ * destroy waits for running queries and frees everything the server owns.  */
+typedef struct {
+    const float *C, *w;
+    int64_t ldc;
+    int32_t nf;
+    sgwb_fgrid fg;
+    int64_t k0;
+    const float *H;
+    sgwb_baseline bl;
+    sgwb_tgrid tg;
+} sgwb_dataset;
+typedef struct {
+    const sgwb_dataset *datasets; /* host array */
+    int32_t ndatasets;
+    size_t hbm_budget_bytes;
+    int32_t slots;          /* 1..16 concurrent queries */
+    int32_t queue_capacity; /* <= 0: unbounded */
+} sgwb_server_cfg;
+typedef struct {
+    int32_t dataset, nside;
+    int32_t k_lo, k_hi; /* rows [k_lo, k_hi) of the dataset */
+} sgwb_query;
+typedef struct {
+    int32_t status, npix;
+    const float *Xbb, *Gbb; /* device */
+    double t_submit_s, t_start_s, t_done_s;
+} sgwb_result;
+typedef struct sgwb_server sgwb_server;
+int sgwb_server_create(const sgwb_server_cfg *cfg /*host*/, sgwb_server **out);
+int sgwb_server_submit(sgwb_server *s, const sgwb_query *q /*host*/, uint64_t *ticket);
+int sgwb_server_poll(sgwb_server *s, uint64_t ticket, sgwb_result *out /*host*/);
+int sgwb_server_fetch(sgwb_server *s, uint64_t ticket, float *Xbb, float *Gbb, hipStream_t stream);
+int sgwb_server_release(sgwb_server *s, uint64_t ticket);
+int sgwb_server_stats(sgwb_server *s, char *buf /*host*/, size_t len);
+void sgwb_server_destroy(sgwb_server *s);
 
 /* ---- HEALPix helper: RING pixel centres (Sec. III.B) as float64 unit
  * vectors xyz[npix][3] (device), and the antipode table anti[npix] (device,

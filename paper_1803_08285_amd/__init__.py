@@ -41,6 +41,36 @@ class _FGrid(ctypes.Structure):
     _fields_ = [("f0_hz", ctypes.c_double), ("df_hz", ctypes.c_double)]
 
 
+class _Job(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_void_p), ("w", ctypes.c_void_p), ("ldc", ctypes.c_int64), ("nt", ctypes.c_int32),
+                ("nf", ctypes.c_int32), ("fg", _FGrid), ("k0", ctypes.c_int64), ("gamma", ctypes.c_void_p),
+                ("tau", ctypes.c_void_p), ("npix", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("X", ctypes.c_void_p), ("Gam", ctypes.c_void_p), ("H", ctypes.c_void_p),
+                ("band_lo", ctypes.c_int32), ("band_hi", ctypes.c_int32), ("Xbb", ctypes.c_void_p),
+                ("Gbb", ctypes.c_void_p)]
+
+
+class _Dataset(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_void_p), ("w", ctypes.c_void_p), ("ldc", ctypes.c_int64), ("nf", ctypes.c_int32),
+                ("fg", _FGrid), ("k0", ctypes.c_int64), ("H", ctypes.c_void_p), ("bl", _Baseline), ("tg", _TGrid)]
+
+
+class _ServerCfg(ctypes.Structure):
+    _fields_ = [("datasets", ctypes.c_void_p), ("ndatasets", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("slots", ctypes.c_int32), ("queue_capacity", ctypes.c_int32)]
+
+
+class _Query(ctypes.Structure):
+    _fields_ = [("dataset", ctypes.c_int32), ("nside", ctypes.c_int32), ("k_lo", ctypes.c_int32),
+                ("k_hi", ctypes.c_int32)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("npix", ctypes.c_int32), ("Xbb", ctypes.c_void_p),
+                ("Gbb", ctypes.c_void_p), ("t_submit_s", ctypes.c_double), ("t_start_s", ctypes.c_double),
+                ("t_done_s", ctypes.c_double)]
+
+
 _lib = None
 
 _VP = ctypes.c_void_p
@@ -60,6 +90,17 @@ _SIGNATURES = {
     "sgwb_reduce_band": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_reduce_band_f64": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
     "sgwb_healpix_centres": ([_I32, _VP, _VP, _VP], ctypes.c_int),
+    "sgwb_server_create": ([ctypes.POINTER(_ServerCfg), ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "sgwb_server_submit": ([_VP, ctypes.POINTER(_Query), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "sgwb_server_poll": ([_VP, ctypes.c_uint64, ctypes.POINTER(_Result)], ctypes.c_int),
+    "sgwb_server_fetch": ([_VP, ctypes.c_uint64, _VP, _VP, _VP], ctypes.c_int),
+    "sgwb_server_release": ([_VP, ctypes.c_uint64], ctypes.c_int),
+    "sgwb_server_stats": ([_VP, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
+    "sgwb_server_destroy": ([_VP], None),
+    "sgwb_plan_create": ([ctypes.POINTER(_Job), _I32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "sgwb_plan_launch": ([_VP, _VP], ctypes.c_int),
+    "sgwb_plan_destroy": ([_VP], None),
+    "sgwb_plan_describe": ([_VP, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
     "sgwb_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "sgwb_last_error": ([], ctypes.c_char_p),
     "sgwb_device_supported": ([], ctypes.c_int),
@@ -286,6 +327,180 @@ def reduce_band(X: torch.Tensor | None, G: torch.Tensor | None, H: torch.Tensor 
                                         int(k_lo), int(k_hi), _ptr(Xbb), _ptr(Gbb), _ptr(ws), wsz, _stream())
     _check(rc, "reduce_band")
     return Xbb, Gbb
+
+
+SGWB_PLAN_AUTOTUNE = 1
+SGWB_PLAN_NO_GRAPH = 2
+
+
+@dataclass
+class Job:
+    """One map job of a batched plan (float32 path).  Outputs X/G/Xbb/Gbb may be None."""
+    C: torch.Tensor
+    w: torch.Tensor
+    fgrid: FGrid
+    k0: int
+    gamma: torch.Tensor
+    tau: torch.Tensor
+    X: torch.Tensor | None = None
+    G: torch.Tensor | None = None
+    H: torch.Tensor | None = None
+    band: tuple | None = None
+    Xbb: torch.Tensor | None = None
+    Gbb: torch.Tensor | None = None
+    antipodal: bool = True
+
+
+class Plan:
+    """A batched plan: all jobs' maps in one persistent launch per kernel, replayed from a HIP graph.
+
+    The plan holds references to every tensor of its jobs; their storage must
+    not be resized while the plan lives.
+    """
+
+    def __init__(self, jobs, autotune: bool = True, graph: bool = True):
+        self.jobs = list(jobs)
+        arr = (_Job * len(self.jobs))()
+        for i, j in enumerate(self.jobs):
+            nt, nf = j.w.shape
+            npix = j.gamma.shape[1]
+            _require(j.C, "C", torch.complex64, (nt, nf))
+            _require(j.w, "w", torch.float32, (nt, nf))
+            _require(j.gamma, "gamma", torch.float32, (nt, npix))
+            _require(j.tau, "tau", torch.float64, (nt, npix))
+            for name, t in (("X", j.X), ("G", j.G)):
+                if t is not None:
+                    _require(t, name, torch.float32, (nf, npix))
+                    _require_contig(t, name)
+            lo, hi = j.band if j.band is not None else (0, 0)
+            arr[i] = _Job(j.C.data_ptr(), j.w.data_ptr(), j.w.stride(0), nt, nf, _FGrid(j.fgrid.f0, j.fgrid.df),
+                          int(j.k0), j.gamma.data_ptr(), j.tau.data_ptr(), npix,
+                          SGWB_MAPS_ANTIPODAL if j.antipodal else 0,
+                          j.X.data_ptr() if j.X is not None else None, j.G.data_ptr() if j.G is not None else None,
+                          j.H.data_ptr() if j.H is not None else None, int(lo), int(hi),
+                          j.Xbb.data_ptr() if j.Xbb is not None else None,
+                          j.Gbb.data_ptr() if j.Gbb is not None else None)
+        flags = (SGWB_PLAN_AUTOTUNE if autotune else 0) | (0 if graph else SGWB_PLAN_NO_GRAPH)
+        self._h = ctypes.c_void_p()
+        self.device = self.jobs[0].C.device
+        with torch.cuda.device(self.device):
+            torch.cuda.synchronize()
+            _check(lib().sgwb_plan_create(arr, len(self.jobs), flags, ctypes.byref(self._h)), "plan_create")
+
+    def launch(self):
+        with torch.cuda.device(self.device):
+            _check(lib().sgwb_plan_launch(self._h, _stream()), "plan_launch")
+
+    def describe(self) -> dict:
+        import json
+
+        buf = ctypes.create_string_buffer(8192)
+        _check(lib().sgwb_plan_describe(self._h, buf, len(buf)), "plan_describe")
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if self._h:
+            lib().sgwb_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+SGWB_EAGAIN = 1
+SGWB_EBUSY = -4
+
+
+@dataclass
+class Dataset:
+    """One baseline's resident folded day: C complex64 [nt][nf], w float32 [nt][nf],
+    H float32 [nf] covering absolute bins [k0, k0 + nf) of fgrid."""
+    C: torch.Tensor
+    w: torch.Tensor
+    H: torch.Tensor
+    fgrid: FGrid
+    k0: int
+    sites: tuple
+    tgrid: TGrid
+
+
+class Server:
+    """Continuous-batching query server (C++ worker thread inside libsgwb)."""
+
+    def __init__(self, datasets, slots: int = 4, hbm_budget_bytes: int = 0, queue_capacity: int = 0):
+        self.datasets = list(datasets)
+        arr = (_Dataset * len(self.datasets))()
+        for i, d in enumerate(self.datasets):
+            nt, nf = d.w.shape
+            _require(d.C, "C", torch.complex64, (nt, nf))
+            _require(d.w, "w", torch.float32, (nt, nf))
+            _require(d.H, "H", torch.float32, (nf,))
+            if d.C.stride(0) != d.w.stride(0):
+                raise SgwbError("C and w must share their row stride")
+            tg = _TGrid(int(d.tgrid.nt), float(d.tgrid.t0), float(d.tgrid.stride), float(d.tgrid.dur))
+            if d.tgrid.nt != nt:
+                raise SgwbError("tgrid.nt must match the rows of C")
+            arr[i] = _Dataset(d.C.data_ptr(), d.w.data_ptr(), d.w.stride(0), nf, _FGrid(d.fgrid.f0, d.fgrid.df),
+                              int(d.k0), d.H.data_ptr(), _baseline(d.sites), tg)
+        self._arr = arr
+        cfg = _ServerCfg(ctypes.cast(arr, ctypes.c_void_p), len(self.datasets), int(hbm_budget_bytes), int(slots),
+                         int(queue_capacity))
+        self.device = self.datasets[0].C.device
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            torch.cuda.synchronize()
+            _check(lib().sgwb_server_create(ctypes.byref(cfg), ctypes.byref(self._h)), "server_create")
+
+    def submit(self, dataset: int, nside: int, k_lo: int, k_hi: int) -> int:
+        """Queue a query; returns its ticket (raises on a bad query, returns -1 if the queue is full)."""
+        t = ctypes.c_uint64()
+        rc = lib().sgwb_server_submit(self._h, ctypes.byref(_Query(dataset, nside, k_lo, k_hi)), ctypes.byref(t))
+        if rc == SGWB_EBUSY:
+            return -1
+        _check(rc, "server_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """None while running; else a dict with status, npix and timestamps (seconds)."""
+        r = _Result()
+        rc = lib().sgwb_server_poll(self._h, ticket, ctypes.byref(r))
+        if rc == SGWB_EAGAIN:
+            return None
+        _check(rc, "server_poll")
+        return {"status": r.status, "npix": r.npix, "t_submit": r.t_submit_s, "t_start": r.t_start_s,
+                "t_done": r.t_done_s}
+
+    def fetch(self, ticket: int, npix: int):
+        """Copy a finished query's (Xbb, Gbb) into new device tensors."""
+        Xbb = torch.empty(npix, dtype=torch.float32, device=self.device)
+        Gbb = torch.empty_like(Xbb)
+        with torch.cuda.device(self.device):
+            _check(lib().sgwb_server_fetch(self._h, ticket, _ptr(Xbb), _ptr(Gbb), _stream()), "server_fetch")
+        return Xbb, Gbb
+
+    def release(self, ticket: int):
+        _check(lib().sgwb_server_release(self._h, ticket), "server_release")
+
+    def stats(self) -> dict:
+        import json
+
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib().sgwb_server_stats(self._h, buf, len(buf)), "server_stats")
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if self._h:
+            lib().sgwb_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def healpix_centres(nside: int, device=None):

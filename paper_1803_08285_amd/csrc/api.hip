@@ -1,5 +1,6 @@
 // C ABI of libsgwb: argument checks, host-side detector set-up, launches.
 #include <math.h>
+#include <stdlib.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -135,6 +136,26 @@ static int reduce_band_impl(const T *X, const T *Gam, const T *H, int32_t nf, in
                      "band kernel launch");
 }
 
+int check_maps_args_f32(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
+                        int64_t k0, const float *gamma, const double *tau, int32_t npix, uint32_t flags,
+                        MapArgs *a)
+{
+    return check_maps_args<float>(C, w, ldc, nt, nf, fg, k0, gamma, tau, npix, flags, a);
+}
+
+// Wave-tile shape of the single-call beam GEMM; SGWB_BEAM_SHAPE=2x4 or 4x4
+// overrides the default.
+static int default_beam_shape()
+{
+    static int shape = [] {
+        const char *e = getenv("SGWB_BEAM_SHAPE");
+        if (e && strcmp(e, "4x4") == 0) return kBeamShape4x4;
+        if (e && strcmp(e, "2x4") == 0) return kBeamShape2x4;
+        return kBeamShape2x4;
+    }();
+    return shape;
+}
+
 }  // namespace sgwb
 
 using namespace sgwb;
@@ -148,6 +169,8 @@ const char *sgwb_status_string(int status)
     case SGWB_EINVAL: return "invalid argument";
     case SGWB_ENOMEM: return "out of memory / workspace too small";
     case SGWB_EDEVICE: return "HIP device error";
+    case SGWB_EBUSY: return "server queue full";
+    case SGWB_EAGAIN: return "not finished yet";
     case SGWB_EUNSUPPORTED: return "unsupported device or option";
     default: return "unknown status";
     }
@@ -203,7 +226,7 @@ int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int3
         if (rc) return rc;
     }
     if (Gam) {
-        rc = check_hip(launch_beam_bf16x3(a, w, gamma, Gam, workspace, stream), "beam kernel launch");
+        rc = check_hip(launch_beam_bf16x3(a, w, gamma, Gam, workspace, default_beam_shape(), stream), "beam kernel launch");
         if (rc) return rc;
     }
     return SGWB_OK;

@@ -22,8 +22,6 @@ namespace sgwb {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kBlk = 32;  // rows/columns per MFMA block
-constexpr int kKs = 16;   // segments per MFMA K-step
 
 // float32 -> bfloat16 bits, round to nearest even (finite inputs).
 __device__ inline uint32_t bf16_bits(float x)
@@ -46,14 +44,6 @@ __device__ inline void split8(const float v[8], uint4 *hi, uint4 *lo)
     *lo = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16), l[6] | (l[7] << 16));
 }
 
-struct FragDims {
-    int64_t nblk;  // 32-wide blocks
-    int64_t nks;   // 16-deep K steps
-};
-__host__ __device__ inline FragDims frag_dims(int64_t n, int64_t nt)
-{
-    return FragDims{(n + kBlk - 1) / kBlk, (nt + kKs - 1) / kKs};
-}
 // Fragment array: [blk][ks][part 0 = hi, 1 = lo][64 lanes] of uint4.
 __host__ __device__ inline int64_t frag_index(int64_t blk, int64_t ks, int part, int lane, int64_t nks)
 {
@@ -90,16 +80,17 @@ __global__ __launch_bounds__(256) void prep_frag_kernel(const float *__restrict_
 }
 
 // Each wave computes a (WM x 32) x (WN x 32) tile of Gam; waves are independent
-// and read their operand fragments straight from L2 (the fragment arrays are
-// small: every fragment is reused by all waves of its tile row or column).
-// The next K-step's fragments are loaded while the current step's MFMAs run.
-constexpr int WM = 4, WN = 4;
-
+// and read their operand fragments straight from L2.  The next K-step's
+// fragments are loaded while the current step's MFMAs run, and the three
+// products of a K-step are issued part by part over all WM x WN accumulators so
+// that consecutive MFMAs never depend on each other.
+template <int WM, int WN>
 struct Frags {
     uint4 a[WM][2], b[WN][2];
 };
 
-__device__ inline void load_frags(Frags &f, const uint4 *__restrict__ Wf, const uint4 *__restrict__ Gf,
+template <int WM, int WN>
+__device__ inline void load_frags(Frags<WM, WN> &f, const uint4 *__restrict__ Wf, const uint4 *__restrict__ Gf,
                                   int64_t tm, int64_t tn, int64_t ks, const FragDims &fm, const FragDims &fn,
                                   int lane)
 {
@@ -124,7 +115,7 @@ __device__ inline void load_frags(Frags &f, const uint4 *__restrict__ Wf, const 
 // (each with its own L2), so workgroup b runs on XCD b % 8.  The tile grid is
 // cut into patches of kPatch x kPatch wave tiles; XCD x works through patches
 // x, x + 8, x + 16, ... and the 16 workgroups (64 waves) of a patch share its
-// 8 bin tiles and 8 pixel tiles through that XCD's L2.
+// bin tiles and pixel tiles through that XCD's L2.
 constexpr int kXcds = 8;
 constexpr int kPatch = 8;
 constexpr int kWavesPerWg = 4;
@@ -144,7 +135,7 @@ __device__ inline bool patch_tile(int64_t b, int w, int64_t tiles_m, int64_t til
     return *tm < tiles_m && *tn < tiles_n;
 }
 
-// Number of workgroups that covers every patch for the XCD-striped order.
+// Number of workgroups that covers every patch in the XCD-striped order.
 __host__ inline int64_t patch_grid(int64_t tiles_m, int64_t tiles_n)
 {
     const int64_t pm = (tiles_m + kPatch - 1) / kPatch, pn = (tiles_n + kPatch - 1) / kPatch;
@@ -153,19 +144,11 @@ __host__ inline int64_t patch_grid(int64_t tiles_m, int64_t tiles_n)
     return per_xcd * kWgPerPatch * kXcds;
 }
 
-__global__ __launch_bounds__(256) void beam_gemm_kernel(const uint4 *__restrict__ Wf,
-                                                         const uint4 *__restrict__ Gf, FragDims fm,
-                                                         FragDims fn, int32_t nf, int64_t ncol,
-                                                         int32_t npix, int64_t nside,
-                                                         float *__restrict__ Gam)
+template <int WM, int WN>
+__device__ inline void beam_wave_tile(const BJob &jb, int64_t tm, int64_t tn, int lane)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t tiles_m = (fm.nblk + WM - 1) / WM;
-    const int64_t tiles_n = (fn.nblk + WN - 1) / WN;
-    int64_t tm, tn;
-    if (!patch_tile(blockIdx.x, threadIdx.x >> 6, tiles_m, tiles_n, &tm, &tn)) return;
+    const FragDims fm = jb.fm, fn = jb.fn;
     const int64_t nks = fm.nks;
-
     f32x16 acc[WM][WN];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
@@ -174,22 +157,21 @@ __global__ __launch_bounds__(256) void beam_gemm_kernel(const uint4 *__restrict_
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-    Frags cur, nxt;
-    load_frags(cur, Wf, Gf, tm, tn, 0, fm, fn, lane);
+    Frags<WM, WN> cur, nxt;
+    load_frags<WM, WN>(cur, jb.Wf, jb.Gf, tm, tn, 0, fm, fn, lane);
     for (int64_t ks = 0; ks < nks; ++ks) {
-        if (ks + 1 < nks) load_frags(nxt, Wf, Gf, tm, tn, ks + 1, fm, fn, lane);
+        if (ks + 1 < nks) load_frags<WM, WN>(nxt, jb.Wf, jb.Gf, tm, tn, ks + 1, fm, fn, lane);
+        // lo.hi, then hi.lo, then hi.hi: smallest terms first, fixed order
 #pragma unroll
-        for (int i = 0; i < WM; ++i)
+        for (int part = 0; part < 3; ++part)
 #pragma unroll
-            for (int j = 0; j < WN; ++j) {
-                const bf16x8 ah = __builtin_bit_cast(bf16x8, cur.a[i][0]);
-                const bf16x8 al = __builtin_bit_cast(bf16x8, cur.a[i][1]);
-                const bf16x8 bh = __builtin_bit_cast(bf16x8, cur.b[j][0]);
-                const bf16x8 bl = __builtin_bit_cast(bf16x8, cur.b[j][1]);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[i][j], 0, 0, 0);
-            }
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j) {
+                    const bf16x8 av = __builtin_bit_cast(bf16x8, cur.a[i][part == 0 ? 1 : 0]);
+                    const bf16x8 bv = __builtin_bit_cast(bf16x8, cur.b[j][part == 1 ? 1 : 0]);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[i][j], 0, 0, 0);
+                }
         if (ks + 1 < nks) cur = nxt;
     }
 
@@ -198,20 +180,49 @@ __global__ __launch_bounds__(256) void beam_gemm_kernel(const uint4 *__restrict_
 #pragma unroll
     for (int j = 0; j < WN; ++j) {
         const int64_t n = (tn * WN + j) * kBlk + (lane & 31);
-        if (n >= ncol) continue;
+        if (n >= jb.ncol) continue;
         int64_t nB = -1;
-        if (nside > 0) nB = antipode_north(ring_of_north(n, nside), npix);
+        if (jb.nside > 0) nB = antipode_north(ring_of_north(n, jb.nside), jb.npix);
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t m = (tm * WM + i) * kBlk + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (m >= nf) continue;
-                float *row = Gam + m * (int64_t)npix;
+                if (m >= jb.nf) continue;
+                float *row = jb.Gam + m * (int64_t)jb.npix;
                 row[n] = acc[i][j][r];
                 if (nB >= 0) row[nB] = acc[i][j][r];
             }
         }
+    }
+}
+
+template <int WM, int WN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 2 ? 2 : 1))) void beam_gemm_kernel(BJob jb)
+{
+    const int64_t tiles_m = (jb.fm.nblk + WM - 1) / WM;
+    const int64_t tiles_n = (jb.fn.nblk + WN - 1) / WN;
+    int64_t tm, tn;
+    if (!patch_tile(blockIdx.x, threadIdx.x >> 6, tiles_m, tiles_n, &tm, &tn)) return;
+    beam_wave_tile<WM, WN>(jb, tm, tn, threadIdx.x & 63);
+}
+
+// Persistent multi-job form: workgroup g of the concatenated per-job patch
+// grids (each job's range starts at a multiple of 8 workgroups, so the XCD
+// striping of every job is kept when the grid size is a multiple of 8).
+template <int WM, int WN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 2 ? 2 : 1))) void beam_gemm_batched_kernel(const BJob *__restrict__ jobs, int32_t njobs,
+                                                                int64_t nwg)
+{
+    for (int64_t g = blockIdx.x; g < nwg; g += gridDim.x) {
+        int j = 0;
+        while (j + 1 < njobs && g >= jobs[j + 1].wg_begin) ++j;
+        const BJob &jb = jobs[j];
+        const int64_t tiles_m = (jb.fm.nblk + WM - 1) / WM;
+        const int64_t tiles_n = (jb.fn.nblk + WN - 1) / WN;
+        int64_t tm, tn;
+        if (patch_tile(g - jb.wg_begin, threadIdx.x >> 6, tiles_m, tiles_n, &tm, &tn))
+            beam_wave_tile<WM, WN>(jb, tm, tn, threadIdx.x & 63);
     }
 }
 
@@ -221,24 +232,71 @@ size_t beam_workspace_bytes(int32_t nt, int32_t nf, int32_t ncol)
     return (size_t)(fm.nblk + fn.nblk) * (size_t)fm.nks * 2 * 64 * sizeof(uint4);
 }
 
-hipError_t launch_beam_bf16x3(const MapArgs &a, const float *w, const float *gamma, float *Gam,
-                              void *work, hipStream_t s)
+void fill_bjob(BJob *jb, const MapArgs &a, const float *w, const float *gamma, float *Gam, void *work)
 {
     const bool pair = a.nside > 0;
-    const int64_t ncol = pair ? a.npix / 2 : a.npix;
-    const FragDims fm = frag_dims(a.nf, a.nt), fn = frag_dims(ncol, a.nt);
-    uint4 *Wf = reinterpret_cast<uint4 *>(work);
-    uint4 *Gf = Wf + fm.nblk * fm.nks * 2 * 64;
-    const int64_t nw = fm.nblk * fm.nks * 64, ng = fn.nblk * fn.nks * 64;
-    // the bins of this call start at column 0 of w (the caller offsets w by k0)
-    hipLaunchKernelGGL(prep_frag_kernel<false>, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, w,
-                       a.ldc, a.nt, (int64_t)a.nf, fm, Wf);
-    hipLaunchKernelGGL(prep_frag_kernel<true>, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, gamma,
-                       (int64_t)a.npix, a.nt, ncol, fn, Gf);
-    const int64_t grid = patch_grid((fm.nblk + WM - 1) / WM, (fn.nblk + WN - 1) / WN);
-    hipLaunchKernelGGL(beam_gemm_kernel, dim3((unsigned)grid), dim3(256), 0, s, Wf, Gf, fm, fn,
-                       a.nf, ncol, a.npix, pair ? a.nside : (int64_t)0, Gam);
+    jb->ncol = pair ? a.npix / 2 : a.npix;
+    jb->fm = frag_dims(a.nf, a.nt);
+    jb->fn = frag_dims(jb->ncol, a.nt);
+    jb->Wf = reinterpret_cast<uint4 *>(work);
+    jb->Gf = const_cast<uint4 *>(jb->Wf) + jb->fm.nblk * jb->fm.nks * 2 * 64;
+    jb->nf = a.nf;
+    jb->npix = a.npix;
+    jb->nside = pair ? a.nside : 0;
+    jb->Gam = Gam;
+    jb->w = w;
+    jb->gamma = gamma;
+    jb->ldw = a.ldc;
+    jb->nt = a.nt;
+    jb->wg_begin = 0;
+}
+
+int64_t bjob_workgroups(const BJob &jb, int shape)
+{
+    const int wm = shape == kBeamShape2x4 ? 2 : 4, wn = 4;
+    return patch_grid((jb.fm.nblk + wm - 1) / wm, (jb.fn.nblk + wn - 1) / wn);
+}
+
+hipError_t launch_beam_prep(const BJob &jb, hipStream_t s)
+{
+    const int64_t nw = jb.fm.nblk * jb.fm.nks * 64, ng = jb.fn.nblk * jb.fn.nks * 64;
+    hipLaunchKernelGGL(prep_frag_kernel<false>, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, jb.w, jb.ldw,
+                       jb.nt, (int64_t)jb.nf, jb.fm, const_cast<uint4 *>(jb.Wf));
+    hipLaunchKernelGGL(prep_frag_kernel<true>, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, jb.gamma,
+                       (int64_t)jb.npix, jb.nt, jb.ncol, jb.fn, const_cast<uint4 *>(jb.Gf));
     return hipGetLastError();
+}
+
+hipError_t launch_beam_gemm(const BJob &jb, int shape, hipStream_t s)
+{
+    const unsigned grid = (unsigned)bjob_workgroups(jb, shape);
+    if (shape == kBeamShape2x4)
+        hipLaunchKernelGGL((beam_gemm_kernel<2, 4>), dim3(grid), dim3(256), 0, s, jb);
+    else
+        hipLaunchKernelGGL((beam_gemm_kernel<4, 4>), dim3(grid), dim3(256), 0, s, jb);
+    return hipGetLastError();
+}
+
+hipError_t launch_beam_gemm_batched(const BJob *jobs_dev, int32_t njobs, int64_t nwg, int64_t grid, int shape,
+                                    hipStream_t s)
+{
+    if (shape == kBeamShape2x4)
+        hipLaunchKernelGGL((beam_gemm_batched_kernel<2, 4>), dim3((unsigned)grid), dim3(256), 0, s, jobs_dev, njobs,
+                           nwg);
+    else
+        hipLaunchKernelGGL((beam_gemm_batched_kernel<4, 4>), dim3((unsigned)grid), dim3(256), 0, s, jobs_dev, njobs,
+                           nwg);
+    return hipGetLastError();
+}
+
+hipError_t launch_beam_bf16x3(const MapArgs &a, const float *w, const float *gamma, float *Gam, void *work,
+                              int shape, hipStream_t s)
+{
+    BJob jb;
+    fill_bjob(&jb, a, w, gamma, Gam, work);
+    hipError_t e = launch_beam_prep(jb, s);
+    if (e != hipSuccess) return e;
+    return launch_beam_gemm(jb, shape, s);
 }
 
 // float64 path: one thread per (bin, pixel column), sequential sum over t.

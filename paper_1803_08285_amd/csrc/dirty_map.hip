@@ -107,23 +107,23 @@ __device__ inline void anchor4(double g, double x4, double *zr, double *zi)
     *zi = g * s;
 }
 
+// One tile: 256 pixel columns (coltile) x one S-bin strip (absolute index strip).
+// Called by every thread of a 256-thread workgroup; ys is the workgroup's LDS stage.
 template <typename T, bool PAIR>
-__global__ __launch_bounds__(256) void dirty_map_kernel(MapArgs a, int64_t strip0,
-                                                         const typename Cplx<T>::type *__restrict__ C,
-                                                         const T *__restrict__ w,
-                                                         const T *__restrict__ gamma,
-                                                         const double *__restrict__ tau,
-                                                         T *__restrict__ X)
+__device__ inline void dirty_map_tile(const MapArgs &a, int64_t strip, int64_t coltile,
+                                      const typename Cplx<T>::type *__restrict__ C, const T *__restrict__ w,
+                                      const T *__restrict__ gamma, const double *__restrict__ tau,
+                                      T *__restrict__ X,
+                                      typename Cplx<T>::type (*ys)[StripTraits<T>::S])
 {
     using C2 = typename Cplx<T>::type;
     constexpr int S = StripTraits<T>::S;
     constexpr int XTC = StripTraits<T>::XTC;
-    __shared__ C2 ys[XTC][S];
 
     const int64_t ncol = PAIR ? (int64_t)a.npix / 2 : (int64_t)a.npix;
-    const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t col = coltile * 256 + threadIdx.x;
     const bool active = col < ncol;
-    const int64_t kabs0 = (strip0 + (int64_t)blockIdx.y) * S;  // absolute first bin of the strip
+    const int64_t kabs0 = strip * S;                          // absolute first bin of the strip
     const int64_t c0 = kabs0 - a.k0;                           // its column in C (may be < 0)
     const double fa4 = 4.0 * (a.f0 + (double)kabs0 * a.df);   // anchor frequency, quarter turns
     const double two_pi_df = kTwoPi * a.df;
@@ -197,6 +197,79 @@ __global__ __launch_bounds__(256) void dirty_map_kernel(MapArgs a, int64_t strip
             row[col] = acc_a[j];
         }
     }
+}
+
+template <typename T, bool PAIR>
+__global__ __launch_bounds__(256) void dirty_map_kernel(MapArgs a, int64_t strip0,
+                                                         const typename Cplx<T>::type *__restrict__ C,
+                                                         const T *__restrict__ w,
+                                                         const T *__restrict__ gamma,
+                                                         const double *__restrict__ tau,
+                                                         T *__restrict__ X)
+{
+    __shared__ typename Cplx<T>::type ys[StripTraits<T>::XTC][StripTraits<T>::S];
+    dirty_map_tile<T, PAIR>(a, strip0 + (int64_t)blockIdx.y, blockIdx.x, C, w, gamma, tau, X, ys);
+}
+
+// Persistent multi-job form: workgroup b takes tiles b, b + grid, b + 2 grid, ...
+// of the concatenated tile list of all jobs (each job: its column tiles fastest
+// within a strip, or its strips fastest, as the plan chose).  A tile's result
+// does not depend on which workgroup computes it or when.  PAIR is uniform
+// over the job table (the plan launches one table per pairing).
+template <bool PAIR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void dirty_map_batched_kernel(
+    const XJob *__restrict__ jobs, int32_t njobs, int64_t ntiles)
+{
+    __shared__ float2 ys[StripTraits<float>::XTC][StripTraits<float>::S];
+    for (int64_t g = blockIdx.x; g < ntiles; g += gridDim.x) {
+        int j = 0;
+        while (j + 1 < njobs && g >= jobs[j + 1].tile_begin) ++j;
+        // read the job's fields as scalars (uniform over the workgroup)
+        const MapArgs a = jobs[j].a;
+        const int64_t local = g - jobs[j].tile_begin;
+        const int64_t ncoltiles = jobs[j].ncoltiles, nstrips = jobs[j].nstrips;
+        const int64_t strip0 = jobs[j].strip_first;
+        int64_t strip, coltile;
+        if (jobs[j].strip_major) {
+            strip = strip0 + local / ncoltiles;
+            coltile = local % ncoltiles;
+        } else {
+            coltile = local / nstrips;
+            strip = strip0 + local % nstrips;
+        }
+        const float2 *C = reinterpret_cast<const float2 *>(jobs[j].C);
+        dirty_map_tile<float, PAIR>(a, strip, coltile, C, jobs[j].w, jobs[j].gamma, jobs[j].tau, jobs[j].X, ys);
+    }
+}
+
+void fill_xjob(XJob *j, const MapArgs &a, const float *C, const float *w, const float *gamma, const double *tau,
+               float *X, bool strip_major)
+{
+    constexpr int S = StripTraits<float>::S;
+    j->a = a;
+    j->C = C;
+    j->w = w;
+    j->gamma = gamma;
+    j->tau = tau;
+    j->X = X;
+    j->strip_first = a.k0 / S;
+    j->nstrips = (a.k0 + a.nf - 1) / S - j->strip_first + 1;
+    const int64_t ncol = a.nside > 0 ? a.npix / 2 : a.npix;
+    j->ncoltiles = (ncol + 255) / 256;
+    j->strip_major = strip_major ? 1 : 0;
+    j->tile_begin = 0;
+}
+
+hipError_t launch_dirty_map_batched(const XJob *jobs_dev, int32_t njobs, int64_t ntiles, int64_t grid, bool pair,
+                                    hipStream_t s)
+{
+    if (pair)
+        hipLaunchKernelGGL(dirty_map_batched_kernel<true>, dim3((unsigned)grid), dim3(256), 0, s, jobs_dev, njobs,
+                           ntiles);
+    else
+        hipLaunchKernelGGL(dirty_map_batched_kernel<false>, dim3((unsigned)grid), dim3(256), 0, s, jobs_dev, njobs,
+                           ntiles);
+    return hipGetLastError();
 }
 
 template <typename T>

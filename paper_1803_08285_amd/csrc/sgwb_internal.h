@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "sgwb.h"
 
 namespace sgwb {
@@ -122,9 +124,57 @@ template <typename T>
 hipError_t launch_dirty_map(const MapArgs &a, const T *C, const T *w, const T *gamma,
                             const double *tau, T *X, hipStream_t s);
 
+// One job of the persistent multi-job dirty-map kernel (float32 path).
+struct XJob {
+    MapArgs a;
+    const float *C, *w, *gamma;
+    const double *tau;
+    float *X;
+    int64_t strip_first, nstrips, ncoltiles;
+    int64_t tile_begin;  // first global tile index of this job
+    int32_t strip_major; // 1: column tiles fastest within a strip
+};
+void fill_xjob(XJob *j, const MapArgs &a, const float *C, const float *w, const float *gamma, const double *tau,
+               float *X, bool strip_major);
+inline int64_t xjob_tiles(const XJob &j) { return j.nstrips * j.ncoltiles; }
+hipError_t launch_dirty_map_batched(const XJob *jobs_dev, int32_t njobs, int64_t ntiles, int64_t grid, bool pair,
+                                    hipStream_t s);
+
 size_t beam_workspace_bytes(int32_t nt, int32_t nf, int32_t ncol);
+
+// Split-bf16 beam GEMM.  Operand fragments: 32-wide blocks x 16-deep K-steps.
+constexpr int kBlk = 32;  // rows/columns per MFMA block
+constexpr int kKs = 16;   // segments per MFMA K-step
+struct FragDims {
+    int64_t nblk;  // 32-wide blocks
+    int64_t nks;   // 16-deep K steps
+};
+__host__ __device__ inline FragDims frag_dims(int64_t n, int64_t nt)
+{
+    return FragDims{(n + kBlk - 1) / kBlk, (nt + kKs - 1) / kKs};
+}
+// wave-tile shapes of the beam GEMM (blocks of 32 x 32 outputs per wave)
+constexpr int kBeamShape4x4 = 0;
+constexpr int kBeamShape2x4 = 1;
+struct BJob {
+    const uint4 *Wf, *Gf;  // fragment arrays in the job's workspace
+    FragDims fm, fn;
+    int32_t nf, npix;
+    int64_t ncol, nside;   // nside > 0: antipodal pairs
+    float *Gam;
+    const float *w, *gamma;  // prep inputs
+    int64_t ldw;
+    int32_t nt;
+    int64_t wg_begin;      // first workgroup of this job in a multi-job launch
+};
+void fill_bjob(BJob *jb, const MapArgs &a, const float *w, const float *gamma, float *Gam, void *work);
+int64_t bjob_workgroups(const BJob &jb, int shape);
+hipError_t launch_beam_prep(const BJob &jb, hipStream_t s);
+hipError_t launch_beam_gemm(const BJob &jb, int shape, hipStream_t s);
+hipError_t launch_beam_gemm_batched(const BJob *jobs_dev, int32_t njobs, int64_t nwg, int64_t grid, int shape,
+                                    hipStream_t s);
 hipError_t launch_beam_bf16x3(const MapArgs &a, const float *w, const float *gamma, float *Gam,
-                              void *work, hipStream_t s);
+                              void *work, int shape, hipStream_t s);
 hipError_t launch_beam_f64(const MapArgs &a, const double *w, const double *gamma, double *Gam,
                            hipStream_t s);
 
@@ -132,5 +182,21 @@ size_t band_workspace_bytes(int32_t npix, int32_t klo, int32_t khi);
 template <typename T>
 hipError_t launch_band(const T *X, const T *G, const T *H, int32_t nf, int32_t npix, int32_t klo,
                        int32_t khi, T *Xbb, T *Gbb, void *work, size_t work_bytes, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched plans and their autotuner
+// ---------------------------------------------------------------------------
+struct Tunables {
+    int x_strip_major = 1;    // dirty-map tiles: column tiles fastest within a strip
+    int x_grid_per_cu = 2;    // persistent dirty-map workgroups per compute unit
+    int beam_shape = kBeamShape2x4;
+    int beam_grid_per_cu = 4; // persistent beam workgroups per compute unit
+};
+bool tune_cache_load(const std::string &key, Tunables *t);
+void tune_cache_store(const std::string &key, const Tunables &t);
+std::string device_key();
+int check_maps_args_f32(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
+                        int64_t k0, const float *gamma, const double *tau, int32_t npix, uint32_t flags,
+                        MapArgs *a);
 
 }  // namespace sgwb

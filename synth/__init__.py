@@ -92,8 +92,8 @@ def workload(cfg: int, baseline: str = "AB") -> Workload:
         return Workload("full_band_nside32", "AB", 32, TGRID_FULL, FGrid(20.0, 1 / 32, 54592), 2, pix, amp)
     if cfg == 3:
         # Same data as workload 2: the source directions are the nside-32 pixel
-        # centres; at nside 64 they are injected with the nside-64 seeds of the
-        # pixel containing them (see ``nside_pixel_for``).
+        # centres; at nside 64 the caller injects them at the nearest nside-64
+        # centre.
         pix, amp = _sources(2, 12 * 32 * 32)
         return Workload("full_band_nside64", "AB", 64, TGRID_FULL, FGrid(20.0, 1 / 32, 54592), 2, pix, amp)
     raise ValueError(cfg)
@@ -168,3 +168,25 @@ def random_selection(seed: int, nrows: int, ncols: int, n_rows_sel: int, n_cols_
     r2 = np.tile(np.arange(nrows, dtype=np.int64), cols.size)
     c2 = np.repeat(cols, nrows)
     return np.concatenate([r1, r2]), np.concatenate([c1, c2])
+
+
+NSIDES_SERVED = (8, 16, 32, 64, 128)
+
+
+def serving_queries(rate_hz: float, duration_s: float, seed: int = 5, nf: int = 54592, max_band: int = 4096,
+                    ndatasets: int = 3):
+    """Poisson stream of map queries: arrival time (s), dataset index, nside,
+    band [k_lo, k_hi) with length uniform on 1..max_band and a uniform start."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t >= duration_s:
+            break
+        ds = int(rng.integers(0, ndatasets))
+        nside = int(NSIDES_SERVED[rng.integers(0, len(NSIDES_SERVED))])
+        length = int(rng.integers(1, max_band + 1))
+        lo = int(rng.integers(0, nf - length + 1))
+        out.append((t, ds, nside, lo, lo + length))
+    return out
