@@ -103,15 +103,25 @@ int sgwb_build_geometry_f64(const sgwb_baseline *bl /*host*/, int32_t nside,
  * antipodal symmetry that sgwb_build_geometry writes (npix = 12 nside^2);
  * the kernels then evaluate one phasor per antipodal pair and write both
  * pixels.  Without the flag any npix and any seeds are accepted.
- * X arithmetic: float32 accumulation, float64 phase reduction f_k tau at the
- * anchor bins, complex-rotation recurrence between anchors.
+ * X arithmetic, two forms with the same definition:
+ *   matrix cores (used with SGWB_MAPS_ANTIPODAL, df <= 0.0347 Hz and a
+ *   workspace of sgwb_make_maps_workspace_size() bytes): per 64-bin strip,
+ *   float64 phase reduction at the strip centre and a 5-term Jacobi-Anger
+ *   expansion of the phase across the strip, contracted on float16 MFMA with
+ *   hi + lo splits of the leading terms and float32 accumulation;
+ *   vector units (otherwise, with flag SGWB_MAPS_VALU_X, or with
+ *   SGWB_X_KERNEL=valu in the environment):
+ *   float64 phase reduction at anchor bins k = 0 mod 64 and a float32
+ *   complex-rotation recurrence between anchors.
  * Gam arithmetic: float32 inputs split into bfloat16 hi + lo, three MFMA
  * products (hi.hi + hi.lo + lo.hi), float32 accumulation.
  * Workspace: device memory of at least sgwb_make_maps_workspace_size() bytes,
- * 256-byte aligned, owned by the caller (NULL allowed when Gam is NULL).
+ * 256-byte aligned, owned by the caller (NULL allowed when Gam is NULL; the
+ * dirty map then uses the vector-unit form).
  * Errors: SGWB_EINVAL (null input, nt/nf/npix < 1, ldc < nf, k0 < 0, bad
  * grid, misaligned pointer), SGWB_ENOMEM (workspace too small).             */
 #define SGWB_MAPS_ANTIPODAL 1u
+#define SGWB_MAPS_VALU_X 2u /* use the vector-unit dirty map even where the matrix-core form applies */
 size_t sgwb_make_maps_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint32_t flags);
 int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf,
                    const sgwb_fgrid *fg /*host*/, int64_t k0, const float *gamma, const double *tau,

@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsgwb.so")
 
 SGWB_MAPS_ANTIPODAL = 1
+SGWB_MAPS_VALU_X = 2
 
 
 class SgwbError(RuntimeError):
@@ -223,13 +224,14 @@ def make_workspace(nt: int, nf: int, npix: int, antipodal: bool = True, device=N
 
 def make_maps(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamma: torch.Tensor,
               tau: torch.Tensor, antipodal: bool = True, want_x: bool = True, want_gamma: bool = True,
-              out=None, workspace: torch.Tensor | None = None):
+              out=None, workspace: torch.Tensor | None = None, x_kernel: str = "auto"):
     """Narrowband dirty map X and Fisher diagonal Gam, both [nf][npix].
 
     C: complex64 [nt][>= nf] (columns = bins k0 ..), or complex128 for the
     float64 path; w: float32/float64 [nt][same columns]; gamma [nt][npix] of the
     working precision; tau float64 [nt][npix].  Column slices of a wider array
     are accepted (rows may be strided, columns must be unit-stride).
+    x_kernel: "auto" (matrix cores where they apply) or "valu" (vector-unit recurrence).
     """
     f64 = C.dtype == torch.complex128
     rdt = torch.float64 if f64 else torch.float32
@@ -258,7 +260,9 @@ def make_maps(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamma: to
         if t is not None:
             _require(t, name, rdt, (nf, npix))
             _require_contig(t, name)
-    flags = SGWB_MAPS_ANTIPODAL if antipodal else 0
+    if x_kernel not in ("auto", "valu"):
+        raise SgwbError("x_kernel must be 'auto' or 'valu'")
+    flags = (SGWB_MAPS_ANTIPODAL if antipodal else 0) | (SGWB_MAPS_VALU_X if x_kernel == "valu" else 0)
     fg = _FGrid(float(fgrid.f0), float(fgrid.df))
     Cr = torch.view_as_real(C)
     with torch.cuda.device(dev):
@@ -266,14 +270,11 @@ def make_maps(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamma: to
             rc = lib().sgwb_make_maps_f64(_ptr(Cr), _ptr(w), int(w.stride(0)), nt, nf, ctypes.byref(fg), int(k0),
                                           _ptr(gamma), _ptr(tau), npix, flags, _ptr(X), _ptr(G), _stream())
         else:
-            ws = None
-            wsz = 0
-            if G is not None:
-                need = workspace_bytes(nt, nf, npix, antipodal)
-                if workspace is None:
-                    workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
-                ws = workspace
-                wsz = workspace.numel() * workspace.element_size()
+            need = workspace_bytes(nt, nf, npix, antipodal)
+            if workspace is None:
+                workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+            ws = workspace
+            wsz = workspace.numel() * workspace.element_size()
             rc = lib().sgwb_make_maps(_ptr(Cr), _ptr(w), int(w.stride(0)), nt, nf, ctypes.byref(fg), int(k0),
                                       _ptr(gamma), _ptr(tau), npix, flags, _ptr(X), _ptr(G), _ptr(ws), wsz,
                                       _stream())
@@ -349,6 +350,7 @@ class Job:
     Xbb: torch.Tensor | None = None
     Gbb: torch.Tensor | None = None
     antipodal: bool = True
+    x_kernel: str = "auto"
 
 
 class Plan:
@@ -375,7 +377,7 @@ class Plan:
             lo, hi = j.band if j.band is not None else (0, 0)
             arr[i] = _Job(j.C.data_ptr(), j.w.data_ptr(), j.w.stride(0), nt, nf, _FGrid(j.fgrid.f0, j.fgrid.df),
                           int(j.k0), j.gamma.data_ptr(), j.tau.data_ptr(), npix,
-                          SGWB_MAPS_ANTIPODAL if j.antipodal else 0,
+                          (SGWB_MAPS_ANTIPODAL if j.antipodal else 0) | (SGWB_MAPS_VALU_X if j.x_kernel == "valu" else 0),
                           j.X.data_ptr() if j.X is not None else None, j.G.data_ptr() if j.G is not None else None,
                           j.H.data_ptr() if j.H is not None else None, int(lo), int(hi),
                           j.Xbb.data_ptr() if j.Xbb is not None else None,

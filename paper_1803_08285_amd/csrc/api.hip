@@ -96,7 +96,7 @@ static int check_maps_args(const T *C, const T *w, int64_t ldc, int32_t nt, int3
     if (nt < 1 || nf < 1 || npix < 1) return set_error(SGWB_EINVAL, "make_maps: nt, nf, npix must be >= 1");
     if (ldc < nf) return set_error(SGWB_EINVAL, "make_maps: ldc %lld < nf %d", (long long)ldc, nf);
     if (k0 < 0) return set_error(SGWB_EINVAL, "make_maps: k0 < 0");
-    if (flags & ~SGWB_MAPS_ANTIPODAL) return set_error(SGWB_EINVAL, "make_maps: unknown flag bits");
+    if (flags & ~(SGWB_MAPS_ANTIPODAL | SGWB_MAPS_VALU_X)) return set_error(SGWB_EINVAL, "make_maps: unknown flag bits");
     int rc = check_grid(fg);
     if (rc) return rc;
     if (((uintptr_t)C % (2 * sizeof(T))) || ((uintptr_t)w % sizeof(T)) || ((uintptr_t)gamma % sizeof(T)) ||
@@ -156,6 +156,18 @@ static int default_beam_shape()
     return shape;
 }
 
+// Dirty-map kernel choice: SGWB_X_KERNEL=valu forces the vector-unit recurrence,
+// otherwise the matrix-core form runs where it applies.
+constexpr int kXKernelAuto = 0, kXKernelValu = 1;
+static int x_kernel_choice()
+{
+    static int k = [] {
+        const char *e = getenv("SGWB_X_KERNEL");
+        return (e && strcmp(e, "valu") == 0) ? kXKernelValu : kXKernelAuto;
+    }();
+    return k;
+}
+
 }  // namespace sgwb
 
 using namespace sgwb;
@@ -200,11 +212,16 @@ int sgwb_build_geometry_f64(const sgwb_baseline *bl, int32_t nside, const sgwb_t
     return build_geometry_impl<double>(bl, nside, tg, gamma, tau, stream);
 }
 
+static size_t up256(size_t n) { return (n + 255) / 256 * 256; }
+
 size_t sgwb_make_maps_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint32_t flags)
 {
     if (nt < 1 || nf < 1 || npix < 1) return 0;
     const int32_t ncol = (flags & SGWB_MAPS_ANTIPODAL) ? npix / 2 : npix;
-    return beam_workspace_bytes(nt, nf, ncol);
+    size_t n = up256(beam_workspace_bytes(nt, nf, ncol));
+    // room for the matrix-core dirty map (largest strip count over all k0)
+    if (flags & SGWB_MAPS_ANTIPODAL) n += up256(xm_workspace_bytes(63, nt, nf));
+    return n;
 }
 
 int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
@@ -214,15 +231,22 @@ int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int3
     MapArgs a;
     int rc = check_maps_args<float>(C, w, ldc, nt, nf, fg, k0, gamma, tau, npix, flags, &a);
     if (rc) return rc;
-    if (Gam) {
-        const size_t need = sgwb_make_maps_workspace_size(nt, nf, npix, flags);
-        if (!workspace || workspace_bytes < need)
-            return set_error(SGWB_ENOMEM, "make_maps: workspace of %zu bytes needed, %zu given", need,
-                             workspace ? workspace_bytes : (size_t)0);
-        if ((uintptr_t)workspace % 256) return set_error(SGWB_EINVAL, "make_maps: workspace not 256-byte aligned");
-    }
+    if (workspace && (uintptr_t)workspace % 256) return set_error(SGWB_EINVAL, "make_maps: workspace not 256-byte aligned");
+    const int32_t ncol = a.nside > 0 ? npix / 2 : npix;
+    const size_t beam_bytes = up256(beam_workspace_bytes(nt, nf, ncol));
+    if (Gam && (!workspace || workspace_bytes < beam_bytes))
+        return set_error(SGWB_ENOMEM, "make_maps: workspace of %zu bytes needed, %zu given",
+                         sgwb_make_maps_workspace_size(nt, nf, npix, flags), workspace ? workspace_bytes : (size_t)0);
     if (X) {
-        rc = check_hip(launch_dirty_map<float>(a, C, w, gamma, tau, X, stream), "dirty-map kernel launch");
+        const size_t xm_bytes = xm_workspace_bytes(k0, nt, nf);
+        const bool use_xm = !(flags & SGWB_MAPS_VALU_X) && x_kernel_choice() != kXKernelValu && xm_eligible(a) &&
+                            workspace && workspace_bytes >= beam_bytes + xm_bytes;
+        if (use_xm)
+            rc = check_hip(launch_dirty_map_mfma(a, C, w, gamma, tau, X, reinterpret_cast<char *>(workspace) + beam_bytes,
+                                                 stream),
+                           "dirty-map (matrix cores) launch");
+        else
+            rc = check_hip(launch_dirty_map<float>(a, C, w, gamma, tau, X, stream), "dirty-map kernel launch");
         if (rc) return rc;
     }
     if (Gam) {

@@ -34,6 +34,7 @@ __device__ inline float bf16_value(uint32_t b) { return __uint_as_float(b << 16)
 // Pack 8 values into hi and lo bf16 fragments.
 __device__ inline void split8(const float v[8], uint4 *hi, uint4 *lo)
 {
+#pragma clang fp contract(off)  // the residual uses the same rounded value as hi
     uint32_t h[8], l[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {

@@ -30,6 +30,10 @@ struct sgwb_plan {
     int64_t x_tiles = 0;
     int32_t nx_pair = 0;         // xjobs[0, nx_pair) use antipodal pairs
     int64_t x_tiles_pair = 0;    // tiles of those jobs
+    // dirty map on the matrix cores (jobs where that form applies)
+    std::vector<XmJob> xmjobs;
+    XmJob *d_xmjobs = nullptr;
+    int64_t xm_tiles = 0;
     // beam
     std::vector<BJob> bjobs;
     BJob *d_bjobs = nullptr;
@@ -37,8 +41,8 @@ struct sgwb_plan {
     // band
     std::vector<size_t> band_off;
     // memory
-    void *beam_ws = nullptr, *band_ws = nullptr;
-    size_t beam_bytes = 0, band_bytes = 0;
+    void *beam_ws = nullptr, *band_ws = nullptr, *xm_ws = nullptr;
+    size_t beam_bytes = 0, band_bytes = 0, xm_bytes = 0;
     Tunables tun;
     bool tuned = false, from_cache = false;
     std::vector<double> tune_ms;
@@ -87,6 +91,12 @@ static int upload_tables(sgwb_plan *p)
         t = 0;
     }
     p->x_tiles = p->x_tiles_pair + t;
+    int64_t tx = 0;
+    for (auto &x : p->xmjobs) {
+        x.tile_begin = tx;
+        tx += xmjob_tiles(x);
+    }
+    p->xm_tiles = tx;
     int64_t wg = 0;
     for (auto &b : p->bjobs) {
         b.wg_begin = wg;
@@ -97,6 +107,8 @@ static int upload_tables(sgwb_plan *p)
     hipError_t e = hipSuccess;
     if (!p->xjobs.empty())
         e = hipMemcpy(p->d_xjobs, p->xjobs.data(), p->xjobs.size() * sizeof(XJob), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !p->xmjobs.empty())
+        e = hipMemcpy(p->d_xmjobs, p->xmjobs.data(), p->xmjobs.size() * sizeof(XmJob), hipMemcpyHostToDevice);
     if (e == hipSuccess && !p->bjobs.empty())
         e = hipMemcpy(p->d_bjobs, p->bjobs.data(), p->bjobs.size() * sizeof(BJob), hipMemcpyHostToDevice);
     return check_hip(e, "plan: upload job tables");
@@ -109,6 +121,13 @@ static hipError_t enqueue(sgwb_plan *p, hipStream_t s, int parts)
     if (parts & 2) {
         for (auto &b : p->bjobs)
             if ((e = launch_beam_prep(b, s)) != hipSuccess) return e;
+    }
+    if ((parts & 1) && p->xm_tiles > 0) {
+        for (auto &x : p->xmjobs)
+            if ((e = launch_xm_prep(x, s)) != hipSuccess) return e;
+        const int64_t grid = std::min<int64_t>(p->xm_tiles, (int64_t)p->num_cus);
+        if ((e = launch_xm_batched(p->d_xmjobs, (int32_t)p->xmjobs.size(), p->xm_tiles, grid, s)) != hipSuccess)
+            return e;
     }
     if (parts & 1) {
         const int64_t cap = (int64_t)p->num_cus * p->tun.x_grid_per_cu;
@@ -178,6 +197,10 @@ std::string plan_signature(const sgwb_plan *p)
     char buf[96];
     for (const auto &x : p->xjobs) {
         snprintf(buf, sizeof buf, "x%lld.%d.%lld;", (long long)x.a.npix, x.a.nt, (long long)x.nstrips);
+        s += buf;
+    }
+    for (const auto &x : p->xmjobs) {
+        snprintf(buf, sizeof buf, "m%lld.%d.%lld;", (long long)x.x.a.npix, x.x.a.nt, (long long)x.x.nstrips);
         s += buf;
     }
     for (const auto &b : p->bjobs) {
@@ -255,6 +278,8 @@ static void plan_free(sgwb_plan *p)
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->cap) (void)hipStreamDestroy(p->cap);
     if (p->d_xjobs) (void)hipFree(p->d_xjobs);
+    if (p->d_xmjobs) (void)hipFree(p->d_xmjobs);
+    if (p->xm_ws) (void)hipFree(p->xm_ws);
     if (p->d_bjobs) (void)hipFree(p->d_bjobs);
     if (p->beam_ws) (void)hipFree(p->beam_ws);
     if (p->band_ws) (void)hipFree(p->band_ws);
@@ -283,10 +308,16 @@ int sgwb_plan_create(const sgwb_job *jobs, int32_t njobs, uint32_t flags, sgwb_p
     if (p->num_cus <= 0) p->num_cus = 256;
 
     // workspaces
-    std::vector<size_t> beam_off(njobs, 0);
+    std::vector<size_t> beam_off(njobs, 0), xm_off(njobs, 0);
+    std::vector<bool> use_xm(njobs, false);
     p->band_off.assign(njobs, 0);
     for (int i = 0; i < njobs; ++i) {
         const sgwb_job &j = p->jobs[i];
+        if (j.X && xm_eligible(p->args[i]) && !(j.flags & SGWB_MAPS_VALU_X)) {
+            use_xm[i] = true;
+            xm_off[i] = p->xm_bytes;
+            p->xm_bytes += (xm_workspace_bytes(j.k0, j.nt, j.nf) + 255) / 256 * 256;
+        }
         if (j.Gam) {
             beam_off[i] = p->beam_bytes;
             const int64_t ncol = p->args[i].nside > 0 ? j.npix / 2 : j.npix;
@@ -300,6 +331,7 @@ int sgwb_plan_create(const sgwb_job *jobs, int32_t njobs, uint32_t flags, sgwb_p
     hipError_t e = hipSuccess;
     if (p->beam_bytes) e = hipMalloc(&p->beam_ws, p->beam_bytes);
     if (e == hipSuccess && p->band_bytes) e = hipMalloc(&p->band_ws, p->band_bytes);
+    if (e == hipSuccess && p->xm_bytes) e = hipMalloc(&p->xm_ws, p->xm_bytes);
     if (e != hipSuccess) {
         rc = set_error(SGWB_ENOMEM, "plan_create: workspace allocation failed: %s", hipGetErrorString(e));
         plan_free(p);
@@ -313,7 +345,7 @@ int sgwb_plan_create(const sgwb_job *jobs, int32_t njobs, uint32_t flags, sgwb_p
         for (int i : order) {
             const sgwb_job &j = p->jobs[i];
             const bool pair = p->args[i].nside > 0;
-            if (j.X && pair == (pass == 0)) {
+            if (j.X && !use_xm[i] && pair == (pass == 0)) {
                 XJob x;
                 fill_xjob(&x, p->args[i], j.C, j.w, j.gamma, j.tau, j.X, true);
                 p->xjobs.push_back(x);
@@ -322,6 +354,11 @@ int sgwb_plan_create(const sgwb_job *jobs, int32_t njobs, uint32_t flags, sgwb_p
         }
     for (int i : order) {
         const sgwb_job &j = p->jobs[i];
+        if (use_xm[i]) {
+            XmJob x;
+            fill_xmjob(&x, p->args[i], j.C, j.w, j.gamma, j.tau, j.X, reinterpret_cast<char *>(p->xm_ws) + xm_off[i]);
+            p->xmjobs.push_back(x);
+        }
         if (j.Gam) {
             BJob b;
             fill_bjob(&b, p->args[i], j.w, j.gamma, j.Gam, reinterpret_cast<char *>(p->beam_ws) + beam_off[i]);
@@ -329,6 +366,7 @@ int sgwb_plan_create(const sgwb_job *jobs, int32_t njobs, uint32_t flags, sgwb_p
         }
     }
     if (!p->xjobs.empty()) e = hipMalloc(&p->d_xjobs, p->xjobs.size() * sizeof(XJob));
+    if (e == hipSuccess && !p->xmjobs.empty()) e = hipMalloc(&p->d_xmjobs, p->xmjobs.size() * sizeof(XmJob));
     if (e == hipSuccess && !p->bjobs.empty()) e = hipMalloc(&p->d_bjobs, p->bjobs.size() * sizeof(BJob));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -381,10 +419,10 @@ int sgwb_plan_describe(const sgwb_plan *p, char *buf, size_t len)
         ms += b;
     }
     int n = snprintf(buf, len,
-                     "{\"jobs\": %zu, \"x_tiles\": %lld, \"beam_workgroups\": %lld, \"x_strip_major\": %d, "
+                     "{\"jobs\": %zu, \"x_tiles\": %lld, \"xm_tiles\": %lld, \"beam_workgroups\": %lld, \"x_strip_major\": %d, "
                      "\"x_grid_per_cu\": %d, \"beam_shape\": \"%s\", \"beam_grid_per_cu\": %d, \"tuned\": %s, "
                      "\"from_cache\": %s, \"tune_ms\": [%s], \"graph\": %s, \"key\": \"%s\"}",
-                     p->jobs.size(), (long long)p->x_tiles, (long long)p->b_wgs, p->tun.x_strip_major,
+                     p->jobs.size(), (long long)p->x_tiles, (long long)p->xm_tiles, (long long)p->b_wgs, p->tun.x_strip_major,
                      p->tun.x_grid_per_cu, p->tun.beam_shape == kBeamShape2x4 ? "2x4" : "4x4", p->tun.beam_grid_per_cu,
                      p->tuned ? "true" : "false", p->from_cache ? "true" : "false", ms.c_str(),
                      p->exec ? "true" : "false", p->tune_key.c_str());

@@ -124,6 +124,34 @@ template <typename T>
 hipError_t launch_dirty_map(const MapArgs &a, const T *C, const T *w, const T *gamma,
                             const double *tau, T *X, hipStream_t s);
 
+// Matrix-core dirty map (float32, antipodal seeds, df <= ~1/32 Hz).
+bool xm_eligible(const MapArgs &a);
+size_t xm_workspace_bytes(int64_t k0, int32_t nt, int32_t nf);
+hipError_t launch_dirty_map_mfma(const MapArgs &a, const float *C, const float *w, const float *gamma,
+                                 const double *tau, float *X, void *work, hipStream_t s);
+struct XmArgs {
+    MapArgs a;
+    int64_t strip_first, nstrips, nchunks;
+    double eta_scale;  // 2 pi 31.5 df
+};
+// One job of the multi-job matrix-core dirty map: operands prepared per job,
+// one persistent launch over the (strip, pixel block) tiles of all jobs.
+struct XmJob {
+    XmArgs x;
+    const uint4 *A;  // data-side fragments (job workspace)
+    const int *e;    // per-bin scale exponents (job workspace)
+    const float *C, *w, *gamma;
+    const double *tau;
+    float *X;
+    int64_t npblocks;
+    int64_t tile_begin;
+};
+void fill_xmjob(XmJob *j, const MapArgs &a, const float *C, const float *w, const float *gamma, const double *tau,
+                float *X, void *work);
+int64_t xmjob_tiles(const XmJob &j);
+hipError_t launch_xm_prep(const XmJob &j, hipStream_t s);
+hipError_t launch_xm_batched(const XmJob *jobs_dev, int32_t njobs, int64_t ntiles, int64_t grid, hipStream_t s);
+
 // One job of the persistent multi-job dirty-map kernel (float32 path).
 struct XJob {
     MapArgs a;

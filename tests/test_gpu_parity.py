@@ -104,6 +104,49 @@ def test_maps_float32_vs_oracle(sg, oracle_mod, antipodal, bl, nside, nf, k0, nt
     assert eg <= G_TOL
 
 
+# df = 1/32 Hz: the matrix-core dirty map applies with antipodal seeds; the
+# vector-unit recurrence is forced with x_kernel="valu".  Both against the oracle.
+@pytest.mark.parametrize("x_kernel", ["auto", "valu"])
+@pytest.mark.parametrize("bl,nside,nf,k0,nt", [
+    ("AB", 8, 640, 0, 240),
+    ("AC", 16, 203, 37, 61),       # ragged strips and chunks, 1536 pairs = 6 workgroups
+    ("BC", 4, 130, 64 * 9 + 63, 17),
+    ("AC", 32, 64, 128, 33),       # exactly one strip, nt not a multiple of 16
+    ("AB", 1, 3, 5, 1),            # one segment, 6 pairs
+])
+def test_maps_df32_both_kernels_vs_oracle(sg, oracle_mod, x_kernel, bl, nside, nf, k0, nt):
+    f0, df = 20.0, 1.0 / 32.0
+    tg = synth.TGrid(nt, 0.0, 86164.0905 / nt, 86164.0905 / nt)
+    g, t = _geom(sg, bl, nside, tg)
+    f = freqs(f0, df, k0, nf)
+    C, w = make_csd(70 + nside, nt, f)
+    Xd, Gd = sg.make_maps(torch.from_numpy(C).cuda(), torch.from_numpy(w).cuda(), sg.FGrid(f0, df), k0, g, t,
+                          x_kernel=x_kernel)
+    torch.cuda.synchronize()
+    Xo, Go, S = oracle_mod.maps(C, w, f0, df, k0, g.cpu().numpy(), t.cpu().numpy(), with_scale=True)
+    ex, eg = x_error(Xd.cpu().numpy(), Xo, S), g_error(Gd.cpu().numpy(), Go)
+    print(f"{x_kernel}: X err {ex:.3e}  Gam err {eg:.3e}")
+    assert ex <= X_TOL
+    assert eg <= G_TOL
+
+
+def test_matrix_core_map_scale_extremes(sg, oracle_mod):
+    """Bins whose data differ by 2^40 in scale and a bin of zeros: the per-bin
+    float16 scaling keeps every bin within tolerance."""
+    nside, nt, nf, k0, f0, df = 8, 40, 128, 0, 20.0, 1.0 / 32.0
+    g, t = _geom(sg, "AB", nside, synth.TGrid(nt, 0.0, 2154.0, 2154.0))
+    f = freqs(f0, df, k0, nf)
+    C, w = make_csd(3, nt, f)
+    w = w * np.where(np.arange(nf) % 2 == 0, 2.0 ** -20, 2.0 ** 20).astype(np.float32)[None, :]
+    C[:, 7] = 0
+    Xd, _ = sg.make_maps(torch.from_numpy(C).cuda(), torch.from_numpy(w).cuda(), sg.FGrid(f0, df), k0, g, t)
+    Xo, Go, S = oracle_mod.maps(C, w, f0, df, k0, g.cpu().numpy(), t.cpu().numpy(), with_scale=True)
+    Xh = Xd.cpu().numpy()
+    assert np.all(Xh[7] == 0)
+    ok = S > 0
+    assert np.max(np.abs(Xh[ok] - Xo[ok]) / S[ok]) <= X_TOL
+
+
 def test_maps_float64_tiny_workload(sg, oracle_mod):
     """The tiny workload in float64: same kernels instantiated for double."""
     wl = synth.workload(1)

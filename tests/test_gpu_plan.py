@@ -14,13 +14,15 @@ from tests._cases import freqs, g_error, make_csd, x_error
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-JOBS = [  # baseline, nside, nt, k0, nf, band, antipodal pairing
-    ("AB", 16, 60, 0, 700, (0, 700), True),
-    ("AC", 8, 45, 100, 300, (13, 290), True),
-    ("BC", 4, 60, 1000, 130, (0, 130), False),
-    ("AB", 2, 7, 63, 2, (0, 2), True),
+JOBS = [  # baseline, nside, nt, k0, nf, band, antipodal pairing, df (1/32: matrix-core dirty map)
+    ("AB", 16, 60, 0, 700, (0, 700), True, 0.25),
+    ("AC", 8, 45, 100, 300, (13, 290), True, 0.25),
+    ("BC", 4, 60, 1000, 130, (0, 130), False, 0.25),
+    ("AB", 2, 7, 63, 2, (0, 2), True, 0.25),
+    ("AC", 16, 50, 197, 400, (3, 399), True, 1 / 32),
+    ("BC", 8, 33, 0, 64, (0, 64), True, 1 / 32),
 ]
-F0, DF = 20.0, 0.25
+F0 = 20.0
 
 
 @pytest.fixture(scope="module")
@@ -34,7 +36,7 @@ def sg():
 
 def _make_jobs(sg):
     jobs, refs, host = [], [], []
-    for i, (bl, nside, nt, k0, nf, band, anti) in enumerate(JOBS):
+    for i, (bl, nside, nt, k0, nf, band, anti, DF) in enumerate(JOBS):
         tg = sg.TGrid(nt, 0.0, 86164.0905 / nt, 86164.0905 / nt)
         g, t = sg.build_geometry(synth.baseline_sites(bl), nside, tg)
         f = freqs(F0, DF, k0, nf)
@@ -51,7 +53,7 @@ def _make_jobs(sg):
         Xr, Gr = sg.make_maps(Cd, wd, sg.FGrid(F0, DF), k0, g, t, antipodal=anti)
         Xbr, Gbr = sg.reduce_band(Xr, Gr, H, *band)
         refs.append((Xr, Gr, Xbr, Gbr))
-        host.append((C, w, g, t, k0))
+        host.append((C, w, g, t, k0, DF))
     torch.cuda.synchronize()
     return jobs, refs, host
 
@@ -112,7 +114,7 @@ def test_plan_against_oracle(sg, oracle_mod):
     plan = sg.Plan(jobs, autotune=False)
     plan.launch()
     torch.cuda.synchronize()
-    for j, (C, w, g, t, k0) in zip(jobs, host):
+    for j, (C, w, g, t, k0, DF) in zip(jobs, host):
         nf, npix = j.X.shape
         rows, cols = synth.random_selection(9, nf, npix, 3, 5)
         Xo, Go, S = oracle_mod.maps_at(C, w, F0, DF, k0, g.cpu().numpy(), t.cpu().numpy(), rows, cols)
