@@ -25,7 +25,10 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X published fp32 vector peak
-X_FLOPS_PER_TERM = 10            # complex rotation 6 + Re(y z) accumulation 4
+PEAK_F16_MFMA_TFLOPS = 2500.0    # MI355X published dense fp16/bf16 matrix peak
+X_FLOPS_PER_TERM = 10            # algorithmic: rotation 6 + Re(y z) accumulation 4 (vector form);
+                                 # the matrix form's 5-term contraction is also 10 flops per term
+X_MFMA_ISSUED_PER_TERM = 22      # matrix form as issued: 11 f16 products (hi/lo splits) x 2 flops
 CPU_BASELINE_TARGET_S = 15.0
 
 
@@ -326,6 +329,17 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     terms = tg.nt * fgd.nf * npix
     x_tflops = X_FLOPS_PER_TERM * terms / (t_x.mean() * 1e-3) / 1e12
+    matrix_form = fgd.df * 2 * 6.371e6 / 299792458.0 * 2 * np.pi * 31.5 <= 0.29  # where make_maps uses MFMA
+    if matrix_form:
+        roofline = {"bound": "mfma", "kernel": "xm_main_kernel (f16 MFMA dirty map)", "achieved": x_tflops,
+                    "peak": PEAK_F16_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": x_tflops / PEAK_F16_MFMA_TFLOPS,
+                    "traffic": None, "flops_per_term": X_FLOPS_PER_TERM, "launch_ms": float(t_x.mean()),
+                    "issued_tflops": X_MFMA_ISSUED_PER_TERM * terms / (t_x.mean() * 1e-3) / 1e12,
+                    "frac_vs_fp32_vector_peak": x_tflops / PEAK_FP32_VECTOR_TFLOPS}
+    else:
+        roofline = {"bound": "alu", "kernel": "dirty_map_kernel<float, pair>", "achieved": x_tflops,
+                    "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": x_tflops / PEAK_FP32_VECTOR_TFLOPS,
+                    "traffic": None, "flops_per_term": X_FLOPS_PER_TERM, "launch_ms": float(t_x.mean())}
 
     if args.copy_calib_mib:
         nbytes = args.copy_calib_mib << 20
@@ -358,10 +372,7 @@ def main():
         "config": {"workload": wl.name, "baseline": wl.baseline, "nt": tg.nt, "nf": fgd.nf, "nside": wl.nside,
                    "npix": npix, "f0_hz": fgd.f0, "df_hz": fgd.df, "terms_per_step": terms,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "kernel": "dirty_map_kernel<float, pair>",
-                     "achieved": x_tflops, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": x_tflops / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
-                     "flops_per_term": X_FLOPS_PER_TERM, "launch_ms": float(t_x.mean())},
+        "roofline": roofline,
         "phases_ms": {"dirty_map": float(t_x.mean()), "beam": float(t_g.mean()), "band": float(t_b.mean())},
         "latency_ms": {"p50": float(np.percentile(t_step, 50)), "p99": float(np.percentile(t_step, 99))},
         "cpu_baseline": cpu,
