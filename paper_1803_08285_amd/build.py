@@ -34,6 +34,8 @@ def flags() -> list[str]:
     return [
         f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # keep private arrays in registers (LDS placement would serialise prefetches)
+        "-mllvm", "-disable-promote-alloca-to-lds",
         "-I", INCLUDE, "-I", CSRC,
     ]
 

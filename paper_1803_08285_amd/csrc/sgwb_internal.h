@@ -219,6 +219,7 @@ struct Tunables {
     int x_grid_per_cu = 2;    // persistent dirty-map workgroups per compute unit
     int beam_shape = kBeamShape2x4;
     int beam_grid_per_cu = 4; // persistent beam workgroups per compute unit
+    int xm_grid_per_cu = 1;   // matrix-core dirty-map workgroups per compute unit (0: one per tile)
 };
 bool tune_cache_load(const std::string &key, Tunables *t);
 void tune_cache_store(const std::string &key, const Tunables &t);
