@@ -30,6 +30,34 @@ X_FLOPS_PER_TERM = 10            # algorithmic: rotation 6 + Re(y z) accumulatio
                                  # the matrix form's 5-term contraction is also 10 flops per term
 X_MFMA_ISSUED_PER_TERM = 22      # matrix form as issued: 11 f16 products (hi/lo splits) x 2 flops
 CPU_BASELINE_TARGET_S = 15.0
+# Sources of the matrix-core dirty-map kernel: a recorded HBM traffic figure is
+# reported only while these are unchanged since the counters were taken.
+X_KERNEL_SOURCES = ("paper_1803_08285_amd/csrc/dirty_map_mfma.hip", "paper_1803_08285_amd/csrc/sgwb_internal.h")
+
+
+def sources_sha256(paths):
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload: str):
+    """HBM bytes per launch of the dirty-map kernel from the committed counter
+    summary (FETCH_SIZE x2 + WRITE_SIZE x1, calibrated on a plain copy), or None
+    if there is none for this workload or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"kernels_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic_record: "):
+            rec = json.loads(line[len("traffic_record: "):])
+            if rec.get("source_sha256") == sources_sha256(X_KERNEL_SOURCES):
+                return rec
+    return None
 
 
 def log(msg):
@@ -331,11 +359,15 @@ def main():
     x_tflops = X_FLOPS_PER_TERM * terms / (t_x.mean() * 1e-3) / 1e12
     matrix_form = fgd.df * 2 * 6.371e6 / 299792458.0 * 2 * np.pi * 31.5 <= 0.29  # where make_maps uses MFMA
     if matrix_form:
+        rec = recorded_traffic(wl.name)
         roofline = {"bound": "mfma", "kernel": "xm_main_kernel (f16 MFMA dirty map)", "achieved": x_tflops,
                     "peak": PEAK_F16_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": x_tflops / PEAK_F16_MFMA_TFLOPS,
-                    "traffic": None, "flops_per_term": X_FLOPS_PER_TERM, "launch_ms": float(t_x.mean()),
+                    "traffic": rec["hbm_bytes"] if rec else None, "flops_per_term": X_FLOPS_PER_TERM,
+                    "launch_ms": float(t_x.mean()),
                     "issued_tflops": X_MFMA_ISSUED_PER_TERM * terms / (t_x.mean() * 1e-3) / 1e12,
                     "frac_vs_fp32_vector_peak": x_tflops / PEAK_FP32_VECTOR_TFLOPS}
+        if rec:
+            roofline["traffic_algorithmic_bytes"] = rec["algorithmic_bytes"]
     else:
         roofline = {"bound": "alu", "kernel": "dirty_map_kernel<float, pair>", "achieved": x_tflops,
                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": x_tflops / PEAK_FP32_VECTOR_TFLOPS,
