@@ -75,6 +75,10 @@ def _load():
         lib.orc_band.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp, dp, ctypes.c_int, ctypes.c_int,
                                  dp, dp]
         lib.orc_band.restype = None
+        lib.orc_fisher_overlap_at.argtypes = [ctypes.c_int, ctypes.c_long, ctypes.c_long, dp, dp, dp,
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_long, dp, dp,
+                                              ctypes.c_long, i64p, i64p, dp, dp, dp, ctypes.c_int]
+        lib.orc_fisher_overlap_at.restype = None
         _lib = lib
     return _lib
 
@@ -193,6 +197,43 @@ def maps_at(C, w, f0: float, df: float, k0: int, gamma, tau, cols, pix, nthreads
                         _dp(tau), n, cols.ctypes.data_as(i64p), pix.ctypes.data_as(i64p), _dp(X),
                         _dp(G), _dp(S), int(nthreads or default_threads()))
     return X, G, S
+
+
+def fisher_overlap_at(v, u, wn, f0: float, df: float, k0: int, gamma, tau, cols, pix,
+                      nthreads: int | None = None):
+    """Overlap-corrected Fisher diagonal (Sec. II.B, Eq. fwGamma with p = p') at the
+    selected (column, pixel) pairs: real part G, imaginary part Gi, scale S."""
+    v, u, wn = _f64(v), _f64(u), _f64(wn)
+    gamma = _f64(gamma)
+    tau = _f64(tau)
+    nt, nf = v.shape
+    assert u.shape == v.shape and wn.shape == v.shape
+    npix = gamma.shape[1]
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    assert cols.shape == pix.shape
+    if cols.size and (cols.min() < 0 or cols.max() >= nf or pix.min() < 0 or pix.max() >= npix):
+        raise IndexError("selection out of range")
+    n = cols.size
+    G = np.empty(n)
+    Gi = np.empty(n)
+    S = np.empty(n)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    _load().orc_fisher_overlap_at(nt, nf, npix, _dp(v), _dp(u), _dp(wn), float(f0), float(df), int(k0),
+                                  _dp(gamma), _dp(tau), n, cols.ctypes.data_as(i64p),
+                                  pix.ctypes.data_as(i64p), _dp(G), _dp(Gi), _dp(S),
+                                  int(nthreads or default_threads()))
+    return G, Gi, S
+
+
+def fisher_overlap(v, u, wn, f0: float, df: float, k0: int, gamma, tau, nthreads: int | None = None):
+    """Full overlap-corrected Fisher diagonal G[nf][npix] (and Gi, S)."""
+    nf = np.asarray(v).shape[1]
+    npix = np.asarray(gamma).shape[1]
+    cols = np.repeat(np.arange(nf, dtype=np.int64), npix)
+    pix = np.tile(np.arange(npix, dtype=np.int64), nf)
+    G, Gi, S = fisher_overlap_at(v, u, wn, f0, df, k0, gamma, tau, cols, pix, nthreads)
+    return G.reshape(nf, npix), Gi.reshape(nf, npix), S.reshape(nf, npix)
 
 
 def band(X, G, H, klo: int, khi: int):

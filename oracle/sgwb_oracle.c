@@ -29,6 +29,10 @@
  *     in Sec. III.A):  G(k,p) = sum_t w(t,k) gamma(t,p)^2
  *   - broadband (Sec. V, spectrum-weighted sum of narrowband maps):
  *       Xbb(p) = sum_k X(k,p),   Gbb(p) = sum_k H(f_k) G(k,p).
+ *   - Fisher diagonal with the overlapping-window neighbour terms (Sec. II.B,
+ *     Eq. fwGamma with p = p', folded series v, u, w):
+ *       G(k,p) = Re sum_t conj(K_t) [K_t v_t - K_{t-1} u_t - K_{t+1} w_t],
+ *       K_t = gamma(t,p) exp(+2 pi i f_k tau(t,p)), neighbours inside the day.
  */
 #include <math.h>
 #include <stdint.h>
@@ -258,5 +262,69 @@ void orc_band(int nf, long npix, const double *X, const double *G, const double 
         }
         Xbb[p] = xs;
         Gbb[p] = gs;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fisher diagonal with the overlapping-window neighbour terms (Sec. II.B,    */
+/* Eq. fwGamma with p = p'), straight from the definition:                    */
+/*   G(k,p) = sum_t conj(K_t) [ K_t v_t - K_{t-1} u_t - K_{t+1} w_t ],         */
+/*   K_t = gamma(t,p) exp(+2 pi i f_k tau(t,p)).                              */
+/* The folded day is a sequence of nt segments: segment 0 has no K_{-1} and  */
+/* segment nt - 1 no K_{nt} (u row 0 and w row nt - 1 are not used).  Returns  */
+/* the real part G, the imaginary part Gi (zero when u_t = w_{t-1}, as the     */
+/* folded series are) and the scale                                           */
+/*   S = sum_t |v_t| g_t^2 + |u_t| |g_t g_{t-1}| + |w_t| |g_t g_{t+1}|.        */
+/* v, u, w are [nt][ld]; column c is absolute bin k0 + c.                      */
+/* ------------------------------------------------------------------------ */
+static void overlap_term(int nt, long ld, long npix, const double *v, const double *u,
+                         const double *wn, double f, long col, const double *gamma,
+                         const double *tau, long p, double *G, double *Gi, double *S)
+{
+    double gr = 0.0, gi = 0.0, s = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        const double gt = gamma[(long)t * npix + p];
+        const double pt = 2.0 * ORC_PI * f * tau[(long)t * npix + p];
+        const double kr = gt * cos(pt), ki = gt * sin(pt); /* K_t */
+        /* bracket B = K_t v_t - K_{t-1} u_t - K_{t+1} w_t */
+        const double vt = v[(long)t * ld + col];
+        double br = kr * vt, bi = ki * vt;
+        s += fabs(vt) * gt * gt;
+        if (t >= 1) {
+            const double g1 = gamma[(long)(t - 1) * npix + p];
+            const double p1 = 2.0 * ORC_PI * f * tau[(long)(t - 1) * npix + p];
+            const double ut = u[(long)t * ld + col];
+            br -= g1 * cos(p1) * ut;
+            bi -= g1 * sin(p1) * ut;
+            s += fabs(ut) * fabs(gt * g1);
+        }
+        if (t + 1 < nt) {
+            const double g1 = gamma[(long)(t + 1) * npix + p];
+            const double p1 = 2.0 * ORC_PI * f * tau[(long)(t + 1) * npix + p];
+            const double wt = wn[(long)t * ld + col];
+            br -= g1 * cos(p1) * wt;
+            bi -= g1 * sin(p1) * wt;
+            s += fabs(wt) * fabs(gt * g1);
+        }
+        /* conj(K_t) * B */
+        gr += kr * br + ki * bi;
+        gi += kr * bi - ki * br;
+    }
+    *G = gr;
+    if (Gi) *Gi = gi;
+    if (S) *S = s;
+}
+
+/* Selected (column, pixel) elements of the overlap-corrected Fisher diagonal. */
+void orc_fisher_overlap_at(int nt, long ld, long npix, const double *v, const double *u,
+                           const double *wn, double f0, double df, long k0, const double *gamma,
+                           const double *tau, long nsel, const int64_t *cols, const int64_t *pix,
+                           double *G, double *Gi, double *S, int nthreads)
+{
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads > 0 ? nthreads : 1)
+    for (long i = 0; i < nsel; ++i) {
+        double f = f0 + (double)(k0 + cols[i]) * df;
+        overlap_term(nt, ld, npix, v, u, wn, f, cols[i], gamma, tau, pix[i], &G[i], Gi ? &Gi[i] : NULL,
+                     S ? &S[i] : NULL);
     }
 }

@@ -132,6 +132,23 @@ def weights(f, a_t):
     return np.outer(a_t, spectrum_H(f) / noise_psd(f) ** 2)
 
 
+# Neighbour weight of 50%-overlapping Hann windows (Sec. II.B).
+HANN_OVERLAP_W = 3.0 / 70.0
+
+
+def overlap_series(v, W: float = HANN_OVERLAP_W):
+    """Neighbour series u, w of a folded day in which every segment exists, from the
+    folded inverse variances v[nt][nf] (Sec. II.B): u_t = W (v_t + v_{t-1}) / 2 for
+    t >= 1 and w_t = W (v_t + v_{t+1}) / 2 for t <= nt - 2; zero where the neighbour
+    is missing (u row 0, w row nt - 1).  Then u_t = w_{t-1}."""
+    v = np.asarray(v, dtype=np.float64)
+    u = np.zeros_like(v)
+    w = np.zeros_like(v)
+    u[1:] = 0.5 * W * (v[1:] + v[:-1])
+    w[:-1] = 0.5 * W * (v[:-1] + v[1:])
+    return u, w
+
+
 def noise_csd(seed: int, nt: int, f, dtype=np.complex128):
     """Circular complex normal C(t,f) with E|C|^2 = P(f)^2."""
     rng = np.random.default_rng(seed)
