@@ -179,6 +179,121 @@ def bench_batched(args, torch, sg):
     print(json.dumps(out), flush=True)
 
 
+def bench_fisher_overlap(args, torch, sg):
+    """Overlap-corrected Fisher diagonal (neighbour terms of 50%-overlapping
+    windows) over the full band of one workload, against the plain diagonal."""
+    dev = torch.device("cuda:0")
+    wl = synth.workload(args.workload)
+    tg, fgd = wl.tgrid, wl.fgrid
+    npix = 12 * wl.nside ** 2
+    f = fgd.freqs()
+    g, t = sg.build_geometry(synth.baseline_sites(wl.baseline), wl.nside,
+                             sg.TGrid(tg.nt, tg.t0, tg.stride, tg.dur), device=dev)
+    v = synth.weights(f, synth.segment_scale(tg.nt, 7))
+    u, w = synth.overlap_series(v)
+    vd, ud, wd = (torch.from_numpy(a.astype(np.float32)).to(dev) for a in (v, u, w))
+    del v, u, w
+    G = torch.empty((fgd.nf, npix), dtype=torch.float32, device=dev)
+    ws = torch.empty(sg.fisher_overlap_workspace_bytes(tg.nt, fgd.nf, npix), dtype=torch.uint8, device=dev)
+    fg = sg.FGrid(fgd.f0, fgd.df)
+    C0 = torch.zeros((tg.nt, fgd.nf), dtype=torch.complex64, device=dev)
+    mws = sg.make_workspace(tg.nt, fgd.nf, npix, True, device=dev)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    t_ov = timed(lambda: sg.fisher_overlap(vd, ud, wd, fg, fgd.k0, g, t, out=G, workspace=ws), args.steps)
+    t_plain = timed(lambda: sg.make_maps(C0, vd, fg, fgd.k0, g, t, want_x=False, out=(None, G), workspace=mws),
+                    args.steps)
+    terms = tg.nt * fgd.nf * npix
+    log(f"overlap-corrected Fisher diagonal: {t_ov:.2f} ms; plain diagonal {t_plain:.2f} ms")
+    print(json.dumps({"metric": "overlap-corrected Fisher diagonal terms/s (t*f*pix)", "value": terms / (t_ov * 1e-3),
+                      "unit": "terms/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": t_ov,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                      "data": "synthetic", "config": {"workload": wl.name + "_fisher_overlap", "nt": tg.nt,
+                                                      "nf": fgd.nf, "npix": npix, "parallelism": "single GPU"},
+                      "plain_diagonal_ms": t_plain}), flush=True)
+
+
+def bench_folded(args, torch, sg):
+    """Folded pipeline over --days synthetic sidereal days of the full band: fold
+    (v, u, w, x), dirty map of x, overlap-corrected Fisher diagonal, band sums."""
+    dev = torch.device("cuda:0")
+    wl = synth.workload(args.workload)
+    tg, fgd = wl.tgrid, wl.fgrid
+    npix = 12 * wl.nside ** 2
+    nd, nt, nf = args.days, tg.nt, fgd.nf
+    f = torch.from_numpy(fgd.freqs()).to(dev)
+    gen = torch.Generator(device=dev).manual_seed(17)
+    # per-day inverse variances a_d H / P^2 and circular complex noise of variance P^2
+    P = (f / 100.0) ** -2 + 1.0 + (f / 500.0) ** 2
+    Hf = (f / 100.0) ** -3
+    a_d = torch.rand((nd, nt, 1), generator=gen, device=dev, dtype=torch.float64) + 0.5
+    sinv = (a_d * (Hf / P ** 2)).to(torch.float32)
+    C = torch.complex(torch.randn((nd, nt, nf), generator=gen, device=dev),
+                      torch.randn((nd, nt, nf), generator=gen, device=dev)) * (P / 2 ** 0.5).to(torch.float32)
+    present = torch.rand((nd, nt), generator=gen, device=dev) >= 0.02
+    g, t = sg.build_geometry(synth.baseline_sites(wl.baseline), wl.nside,
+                             sg.TGrid(tg.nt, tg.t0, tg.stride, tg.dur), device=dev)
+    fg = sg.FGrid(fgd.f0, fgd.df)
+    ones = torch.ones((nt, nf), dtype=torch.float32, device=dev)
+    Hs = Hf.to(torch.float32)
+    X = torch.empty((nf, npix), dtype=torch.float32, device=dev)
+    G = torch.empty_like(X)
+    Xbb = torch.empty(npix, dtype=torch.float32, device=dev)
+    Gbb = torch.empty_like(Xbb)
+    mws = sg.make_workspace(nt, nf, npix, True, device=dev)
+    fws = torch.empty(sg.fisher_overlap_workspace_bytes(nt, nf, npix), dtype=torch.uint8, device=dev)
+    folded = [torch.empty((nt, nf), dtype=torch.float32, device=dev) for _ in range(3)]
+    folded.append(torch.empty((nt, nf), dtype=torch.complex64, device=dev))
+
+    def step(evs=None):
+        if evs:
+            evs[0].record()
+        v, u, w, x = sg.fold(C, sinv, present, synth.HANN_OVERLAP_W, out=folded)
+        if evs:
+            evs[1].record()
+        sg.make_maps(x, ones, fg, fgd.k0, g, t, want_gamma=False, out=(X, None), workspace=mws)
+        if evs:
+            evs[2].record()
+        sg.fisher_overlap(v, u, w, fg, fgd.k0, g, t, out=G, workspace=fws)
+        if evs:
+            evs[3].record()
+        sg.reduce_band(X, G, Hs, 0, nf, out=(Xbb, Gbb))
+        if evs:
+            evs[4].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ph = {name: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs]))
+          for i, name in enumerate(("fold", "dirty_map", "fisher_overlap", "band"))}
+    in_bytes = nd * nt * nf * 12 + nd * nt
+    terms = nt * nf * npix
+    log(f"folded pipeline, {nd} days: {ms:.2f} ms per step, phases {ph}")
+    print(json.dumps({"metric": "folded-pipeline map terms/s (t*f*pix, X + overlap-corrected Gamma)",
+                      "value": terms / (ms * 1e-3), "unit": "terms/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": f"{wl.name}_folded_{nd}_days", "days": nd, "nt": nt, "nf": nf,
+                                 "npix": npix, "parallelism": "single GPU"},
+                      "phases_ms": ph, "fold_GBps": in_bytes / (ph["fold"] * 1e-3) / 1e9}), flush=True)
+
+
 def bench_serve(args, torch, sg):
     """Serving form: Poisson streams of map queries against three resident
     baselines, through the continuous-batching server and through the plain
@@ -288,6 +403,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched", action="store_true", help="batched plan of three uneven baseline jobs")
     ap.add_argument("--serve", action="store_true", help="Poisson query stream through the server")
+    ap.add_argument("--folded", action="store_true",
+                    help="fold --days synthetic days, then X, overlap-corrected Gamma and band sums")
+    ap.add_argument("--days", type=int, default=10)
+    ap.add_argument("--fisher-overlap", action="store_true",
+                    help="overlap-corrected Fisher diagonal over the full band of --workload")
     ap.add_argument("--rates", type=float, nargs="+", default=[25.0, 50.0, 100.0, 200.0])
     ap.add_argument("--duration", type=float, default=5.0)
     ap.add_argument("--slots", type=int, default=4)
@@ -311,6 +431,12 @@ def main():
         return
     if args.serve:
         bench_serve(args, torch, sg)
+        return
+    if args.fisher_overlap:
+        bench_fisher_overlap(args, torch, sg)
+        return
+    if args.folded:
+        bench_folded(args, torch, sg)
         return
     wl = synth.workload(args.workload)
     tg, fgd = wl.tgrid, wl.fgrid

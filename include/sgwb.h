@@ -128,6 +128,57 @@ int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int3
                    int32_t npix, uint32_t flags, float *X, float *Gam, void *workspace,
                    size_t workspace_bytes, hipStream_t stream);
 
+/* ---- folding: Sec. II.B (Eqs. eq_foldx, eq_foldgamma and the folded series
+ * of overlapping windows) ------------------------------------------------------
+ * The geometry repeats every sidereal day, so the data of ndays days, nt
+ * segments each, sum into one folded day.  Segment tau of day d is absolute
+ * segment a = d nt + tau; a segment contributes only if it has data
+ * (present[a] != 0); eps = W for a neighbour a - 1 or a + 1 that has data and
+ * 0 otherwise (the first segment of a day neighbours the previous day's last).
+ * With s = sigma^-2:
+ *   v(tau,k) = sum_d s_a
+ *   u(tau,k) = sum_d eps_{a-1} (s_a + s_{a-1}) / 2
+ *   w(tau,k) = sum_d eps_{a+1} (s_a + s_{a+1}) / 2
+ *   x(tau,k) = sum_d [ s_a C_a - eps_{a-1} (s_a + s_{a-1}) / 2 C_{a-1}
+ *                             - eps_{a+1} (s_a + s_{a+1}) / 2 C_{a+1} ]
+ * W = 3/70 for 50%-overlapping Hann windows.
+ * Inputs: C interleaved complex float32 [ndays][nt][ldc], sinv float32
+ * [ndays][nt][ldc] (columns = bins), present uint8 [ndays][nt] (device).
+ * Outputs: v, u, w float32 [nt][nf] and x interleaved complex float32 [nt][nf];
+ * sums in float64, rounded once.  x and v feed sgwb_make_maps as C and w
+ * (x with unit weights); v, u, w feed sgwb_fisher_overlap.
+ * Errors: SGWB_EINVAL (null pointer, ndays/nt/nf < 1, ldc < nf, W not finite or
+ * negative, misaligned pointer).                                              */
+int sgwb_fold(const float *C, const float *sinv, const uint8_t *present, int64_t ldc, int32_t ndays, int32_t nt,
+              int32_t nf, double W, float *v, float *u, float *w, float *x, hipStream_t stream);
+
+/* ---- overlap-corrected Fisher diagonal: Sec. II.B, Eq. fwGamma with p = p' -
+ * With 50%-overlapping windows the noise of neighbouring segments is
+ * correlated and the folded data carry three real series v, u, w; the
+ * per-bin Fisher diagonal is then
+ *   Gam(k,p) = Re sum_t conj(K_t) [ K_t v(t,k) - K_{t-1} u(t,k) - K_{t+1} w(t,k) ],
+ *   K_t = gamma(t,p) exp(+2 pi i f_k tau(t,p)),
+ * i.e. sum_t v gamma_t^2 minus, for every pair of consecutive segments,
+ * (u(t+1,k) + w(t,k)) gamma_t gamma_{t+1} cos 2 pi f_k (tau_{t+1} - tau_t).
+ * The folded day is periodic (the geometry repeats every sidereal day):
+ * segment nt - 1 is followed by segment 0, whose u row carries the pairs that
+ * cross a day boundary (zero for data of a single day).
+ * Inputs: v, u, w float32 [nt][ldc] (column c = bin k0 + c, ldc >= nf);
+ * gamma float32, tau float64 [nt][npix] as for sgwb_make_maps, same flags.
+ * Output: Gam float32 [nf][npix] (overwritten).
+ * Arithmetic: the v term on the matrix cores as the split-bf16 beam GEMM; the
+ * neighbour terms as a dirty map over the nt - 1 segment pairs (same forms and
+ * tolerances as X in sgwb_make_maps, on the matrix cores where they apply).
+ * Workspace: at least sgwb_fisher_overlap_workspace_size() bytes, 256-byte
+ * aligned, owned by the caller.
+ * Errors: SGWB_EINVAL (null pointer, nt/nf/npix < 1, ldc < nf, k0 < 0, bad grid
+ * or flags, misaligned pointer), SGWB_ENOMEM (workspace too small).          */
+size_t sgwb_fisher_overlap_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint32_t flags);
+int sgwb_fisher_overlap(const float *v, const float *u, const float *w, int64_t ldc, int32_t nt, int32_t nf,
+                        const sgwb_fgrid *fg /*host*/, int64_t k0, const float *gamma, const double *tau,
+                        int32_t npix, uint32_t flags, float *Gam, void *workspace, size_t workspace_bytes,
+                        hipStream_t stream);
+
 /* float64 variant of the same definition (all inputs and outputs double; Gam
  * accumulated in float64 on the vector units; no workspace).                  */
 int sgwb_make_maps_f64(const double *C, const double *w, int64_t ldc, int32_t nt, int32_t nf,

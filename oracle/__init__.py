@@ -79,6 +79,9 @@ def _load():
                                               ctypes.c_double, ctypes.c_double, ctypes.c_long, dp, dp,
                                               ctypes.c_long, i64p, i64p, dp, dp, dp, ctypes.c_int]
         lib.orc_fisher_overlap_at.restype = None
+        lib.orc_fold.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_long, dp, dp,
+                                 ctypes.POINTER(ctypes.c_ubyte), ctypes.c_double, dp, dp, dp, dp]
+        lib.orc_fold.restype = None
         _lib = lib
     return _lib
 
@@ -202,7 +205,8 @@ def maps_at(C, w, f0: float, df: float, k0: int, gamma, tau, cols, pix, nthreads
 def fisher_overlap_at(v, u, wn, f0: float, df: float, k0: int, gamma, tau, cols, pix,
                       nthreads: int | None = None):
     """Overlap-corrected Fisher diagonal (Sec. II.B, Eq. fwGamma with p = p') at the
-    selected (column, pixel) pairs: real part G, imaginary part Gi, scale S."""
+    selected (column, pixel) pairs: real part G, imaginary part Gi, scale S.  The
+    folded day is periodic: segment 0's predecessor is segment nt - 1."""
     v, u, wn = _f64(v), _f64(u), _f64(wn)
     gamma = _f64(gamma)
     tau = _f64(tau)
@@ -234,6 +238,26 @@ def fisher_overlap(v, u, wn, f0: float, df: float, k0: int, gamma, tau, nthreads
     pix = np.tile(np.arange(npix, dtype=np.int64), nf)
     G, Gi, S = fisher_overlap_at(v, u, wn, f0, df, k0, gamma, tau, cols, pix, nthreads)
     return G.reshape(nf, npix), Gi.reshape(nf, npix), S.reshape(nf, npix)
+
+
+def fold(C, s, present, W: float):
+    """Folded series (Sec. II.B) from per-day data: C complex [ndays][nt][nf],
+    s = sigma^-2 [ndays][nt][nf], present bool [ndays][nt].  Returns v, u, w
+    [nt][nf] and complex x [nt][nf]."""
+    s = _f64(s)
+    ndays, nt, nf = s.shape
+    Cv = np.ascontiguousarray(np.asarray(C, dtype=np.complex128)).reshape(ndays * nt, nf)
+    Cv = np.ascontiguousarray(Cv.view(np.float64))
+    pres = np.ascontiguousarray(np.asarray(present, dtype=np.uint8))
+    assert pres.shape == (ndays, nt)
+    v = np.empty((nt, nf))
+    u = np.empty((nt, nf))
+    w = np.empty((nt, nf))
+    x = np.empty((nt, nf), dtype=np.complex128)
+    xv = x.view(np.float64)
+    _load().orc_fold(ndays, nt, nf, nf, _dp(Cv), _dp(s), pres.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)),
+                     float(W), _dp(v), _dp(u), _dp(w), _dp(xv))
+    return v, u, w, x
 
 
 def band(X, G, H, klo: int, khi: int):

@@ -32,7 +32,10 @@
  *   - Fisher diagonal with the overlapping-window neighbour terms (Sec. II.B,
  *     Eq. fwGamma with p = p', folded series v, u, w):
  *       G(k,p) = Re sum_t conj(K_t) [K_t v_t - K_{t-1} u_t - K_{t+1} w_t],
- *       K_t = gamma(t,p) exp(+2 pi i f_k tau(t,p)), neighbours inside the day.
+ *       K_t = gamma(t,p) exp(+2 pi i f_k tau(t,p)), the day periodic in t;
+ *   - folding (Sec. II.B): v, u, w, x summed over days from per-segment CSD C,
+ *     inverse variances s = sigma^-2 and presence flags, in absolute time
+ *     (the neighbour of a day's first segment is the previous day's last one).
  */
 #include <math.h>
 #include <stdint.h>
@@ -270,10 +273,10 @@ void orc_band(int nf, long npix, const double *X, const double *G, const double 
 /* Eq. fwGamma with p = p'), straight from the definition:                    */
 /*   G(k,p) = sum_t conj(K_t) [ K_t v_t - K_{t-1} u_t - K_{t+1} w_t ],         */
 /*   K_t = gamma(t,p) exp(+2 pi i f_k tau(t,p)).                              */
-/* The folded day is a sequence of nt segments: segment 0 has no K_{-1} and  */
-/* segment nt - 1 no K_{nt} (u row 0 and w row nt - 1 are not used).  Returns  */
-/* the real part G, the imaginary part Gi (zero when u_t = w_{t-1}, as the     */
-/* folded series are) and the scale                                           */
+/* The folded day is periodic (the geometry repeats every sidereal day):      */
+/* segment 0's predecessor is segment nt - 1 and segment nt - 1's successor   */
+/* is segment 0.  Returns the real part G, the imaginary part Gi (zero when    */
+/* u_t = w_{t-1}, as the folded series are) and the scale                     */
 /*   S = sum_t |v_t| g_t^2 + |u_t| |g_t g_{t-1}| + |w_t| |g_t g_{t+1}|.        */
 /* v, u, w are [nt][ld]; column c is absolute bin k0 + c.                      */
 /* ------------------------------------------------------------------------ */
@@ -290,17 +293,19 @@ static void overlap_term(int nt, long ld, long npix, const double *v, const doub
         const double vt = v[(long)t * ld + col];
         double br = kr * vt, bi = ki * vt;
         s += fabs(vt) * gt * gt;
-        if (t >= 1) {
-            const double g1 = gamma[(long)(t - 1) * npix + p];
-            const double p1 = 2.0 * ORC_PI * f * tau[(long)(t - 1) * npix + p];
+        {
+            const int tp = t >= 1 ? t - 1 : nt - 1; /* predecessor, periodic */
+            const double g1 = gamma[(long)tp * npix + p];
+            const double p1 = 2.0 * ORC_PI * f * tau[(long)tp * npix + p];
             const double ut = u[(long)t * ld + col];
             br -= g1 * cos(p1) * ut;
             bi -= g1 * sin(p1) * ut;
             s += fabs(ut) * fabs(gt * g1);
         }
-        if (t + 1 < nt) {
-            const double g1 = gamma[(long)(t + 1) * npix + p];
-            const double p1 = 2.0 * ORC_PI * f * tau[(long)(t + 1) * npix + p];
+        {
+            const int tn = t + 1 < nt ? t + 1 : 0; /* successor, periodic */
+            const double g1 = gamma[(long)tn * npix + p];
+            const double p1 = 2.0 * ORC_PI * f * tau[(long)tn * npix + p];
             const double wt = wn[(long)t * ld + col];
             br -= g1 * cos(p1) * wt;
             bi -= g1 * sin(p1) * wt;
@@ -327,4 +332,50 @@ void orc_fisher_overlap_at(int nt, long ld, long npix, const double *v, const do
         overlap_term(nt, ld, npix, v, u, wn, f, cols[i], gamma, tau, pix[i], &G[i], Gi ? &Gi[i] : NULL,
                      S ? &S[i] : NULL);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Folding (Sec. II.B): ndays days of nt segments, absolute segment a = d nt + */
+/* tau.  Per present segment a and bin, with eps = W when the neighbour a +- 1 */
+/* exists and is present (0 otherwise):                                       */
+/*   v_tau += s_a                                                             */
+/*   u_tau += eps_{a-1} (s_a + s_{a-1}) / 2,  w_tau += eps_{a+1} (s_a + s_{a+1}) / 2 */
+/*   x_tau += s_a C_a - eps_{a-1} (s_a + s_{a-1}) / 2 C_{a-1}                  */
+/*                    - eps_{a+1} (s_a + s_{a+1}) / 2 C_{a+1}                  */
+/* C interleaved complex [ndays][nt][ld], s [ndays][nt][ld], present           */
+/* [ndays][nt] (nonzero = data); outputs v, u, w [nt][nf], x complex [nt][nf].  */
+/* ------------------------------------------------------------------------ */
+void orc_fold(int ndays, int nt, int nf, long ld, const double *C, const double *sv,
+              const unsigned char *present, double W, double *v, double *u, double *w, double *x)
+{
+    const long nseg = (long)ndays * nt;
+    for (int tau = 0; tau < nt; ++tau)
+        for (int c = 0; c < nf; ++c) {
+            double vs = 0.0, us = 0.0, ws = 0.0, xr = 0.0, xi = 0.0;
+            for (int d = 0; d < ndays; ++d) {
+                const long a = (long)d * nt + tau;
+                if (!present[a]) continue;
+                const double sa = sv[a * ld + c];
+                vs += sa;
+                xr += sa * C[2 * (a * ld + c)];
+                xi += sa * C[2 * (a * ld + c) + 1];
+                if (a - 1 >= 0 && present[a - 1]) {
+                    const double e = 0.5 * W * (sa + sv[(a - 1) * ld + c]);
+                    us += e;
+                    xr -= e * C[2 * ((a - 1) * ld + c)];
+                    xi -= e * C[2 * ((a - 1) * ld + c) + 1];
+                }
+                if (a + 1 < nseg && present[a + 1]) {
+                    const double e = 0.5 * W * (sa + sv[(a + 1) * ld + c]);
+                    ws += e;
+                    xr -= e * C[2 * ((a + 1) * ld + c)];
+                    xi -= e * C[2 * ((a + 1) * ld + c) + 1];
+                }
+            }
+            v[(long)tau * nf + c] = vs;
+            u[(long)tau * nf + c] = us;
+            w[(long)tau * nf + c] = ws;
+            x[2 * ((long)tau * nf + c)] = xr;
+            x[2 * ((long)tau * nf + c) + 1] = xi;
+        }
 }

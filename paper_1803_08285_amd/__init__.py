@@ -87,6 +87,10 @@ _SIGNATURES = {
                         ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_make_maps_f64": ([_VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
                             ctypes.c_uint32, _VP, _VP, _VP], ctypes.c_int),
+    "sgwb_fold": ([_VP, _VP, _VP, _I64, _I32, _I32, _I32, ctypes.c_double, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+    "sgwb_fisher_overlap_workspace_size": ([_I32, _I32, _I32, ctypes.c_uint32], ctypes.c_size_t),
+    "sgwb_fisher_overlap": ([_VP, _VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
+                             ctypes.c_uint32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_reduce_band_workspace_size": ([_I32, _I32, _I32], ctypes.c_size_t),
     "sgwb_reduce_band": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_reduce_band_f64": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
@@ -280,6 +284,85 @@ def make_maps(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamma: to
                                       _stream())
     _check(rc, "make_maps")
     return X, G
+
+
+def fold(C: torch.Tensor, sinv: torch.Tensor, present: torch.Tensor, W: float, out=None):
+    """Fold ndays sidereal days into one (Sec. II.B): C complex64 [ndays][nt][>= nf],
+    sinv float32 [ndays][nt][same columns], present bool/uint8 [ndays][nt].
+    Returns v, u, w float32 [nt][nf] and x complex64 [nt][nf]."""
+    if C.dim() != 3 or sinv.dim() != 3:
+        raise SgwbError("C and sinv must be 3-D [ndays][nt][bins]")
+    ndays, nt, nf = sinv.shape
+    if C.dtype != torch.complex64 or tuple(C.shape) != (ndays, nt, nf):
+        raise SgwbError("C must be complex64 with the shape of sinv")
+    if sinv.dtype != torch.float32:
+        raise SgwbError("sinv must be float32")
+    for name, t in (("C", C), ("sinv", sinv)):
+        if t.stride(2) != 1 or t.stride(0) != nt * t.stride(1):
+            raise SgwbError(f"{name}: rows must be contiguous segments with unit-stride bins")
+    if C.stride(1) != sinv.stride(1):
+        raise SgwbError("C and sinv must share their row stride")
+    if tuple(present.shape) != (ndays, nt):
+        raise SgwbError("present must be [ndays][nt]")
+    dev = sinv.device
+    if C.device != dev or present.device != dev:
+        raise SgwbError("all tensors must be on the same device")
+    pres = present.to(torch.uint8).contiguous()
+    if out is None:
+        v = torch.empty((nt, nf), dtype=torch.float32, device=dev)
+        u = torch.empty_like(v)
+        w = torch.empty_like(v)
+        x = torch.empty((nt, nf), dtype=torch.complex64, device=dev)
+    else:
+        v, u, w, x = out
+    for name, t, dt in (("v", v, torch.float32), ("u", u, torch.float32), ("w", w, torch.float32),
+                        ("x", x, torch.complex64)):
+        _require(t, name, dt, (nt, nf))
+        _require_contig(t, name)
+    with torch.cuda.device(dev):
+        rc = lib().sgwb_fold(_ptr(torch.view_as_real(C)), _ptr(sinv), _ptr(pres), int(sinv.stride(1)), ndays, nt, nf,
+                             float(W), _ptr(v), _ptr(u), _ptr(w), _ptr(torch.view_as_real(x)), _stream())
+    _check(rc, "fold")
+    return v, u, w, x
+
+
+def fisher_overlap_workspace_bytes(nt: int, nf: int, npix: int, antipodal: bool = True) -> int:
+    return int(lib().sgwb_fisher_overlap_workspace_size(nt, nf, npix, SGWB_MAPS_ANTIPODAL if antipodal else 0))
+
+
+def fisher_overlap(v: torch.Tensor, u: torch.Tensor, wn: torch.Tensor, fgrid: FGrid, k0: int,
+                   gamma: torch.Tensor, tau: torch.Tensor, antipodal: bool = True, out=None,
+                   workspace: torch.Tensor | None = None, x_kernel: str = "auto"):
+    """Overlap-corrected Fisher diagonal Gam [nf][npix] (Sec. II.B, Eq. fwGamma with
+    p = p'): v, u, wn float32 [nt][>= nf] folded series sharing one row stride."""
+    nt, nf = v.shape
+    npix = gamma.shape[1]
+    for name, t in (("v", v), ("u", u), ("w", wn)):
+        _require(t, name, torch.float32, (nt, nf))
+        if t.stride(0) != v.stride(0):
+            raise SgwbError("v, u and w must share their row stride")
+    _require(gamma, "gamma", torch.float32, (nt, npix))
+    _require(tau, "tau", torch.float64, (nt, npix))
+    _require_contig(gamma, "gamma")
+    _require_contig(tau, "tau")
+    if x_kernel not in ("auto", "valu"):
+        raise SgwbError("x_kernel must be 'auto' or 'valu'")
+    dev = v.device
+    G = out if out is not None else torch.empty((nf, npix), dtype=torch.float32, device=dev)
+    _require(G, "Gam", torch.float32, (nf, npix))
+    _require_contig(G, "Gam")
+    flags = (SGWB_MAPS_ANTIPODAL if antipodal else 0) | (SGWB_MAPS_VALU_X if x_kernel == "valu" else 0)
+    fg = _FGrid(float(fgrid.f0), float(fgrid.df))
+    with torch.cuda.device(dev):
+        if workspace is None:
+            need = fisher_overlap_workspace_bytes(nt, nf, npix, antipodal)
+            workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        wsz = workspace.numel() * workspace.element_size()
+        rc = lib().sgwb_fisher_overlap(_ptr(v), _ptr(u), _ptr(wn), int(v.stride(0)), nt, nf, ctypes.byref(fg),
+                                       int(k0), _ptr(gamma), _ptr(tau), npix, flags, _ptr(G), _ptr(workspace),
+                                       wsz, _stream())
+    _check(rc, "fisher_overlap")
+    return G
 
 
 def band_workspace_bytes(npix: int, k_lo: int, k_hi: int) -> int:

@@ -87,12 +87,13 @@ static int check_grid(const sgwb_fgrid *fg)
     return SGWB_OK;
 }
 
+// C may be null only for callers that read no CSD (c_optional).
 template <typename T>
 static int check_maps_args(const T *C, const T *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
                            int64_t k0, const T *gamma, const double *tau, int32_t npix, uint32_t flags,
-                           MapArgs *a)
+                           MapArgs *a, bool c_optional = false)
 {
-    if (!C || !w || !gamma || !tau) return set_error(SGWB_EINVAL, "make_maps: null input pointer");
+    if ((!C && !c_optional) || !w || !gamma || !tau) return set_error(SGWB_EINVAL, "make_maps: null input pointer");
     if (nt < 1 || nf < 1 || npix < 1) return set_error(SGWB_EINVAL, "make_maps: nt, nf, npix must be >= 1");
     if (ldc < nf) return set_error(SGWB_EINVAL, "make_maps: ldc %lld < nf %d", (long long)ldc, nf);
     if (k0 < 0) return set_error(SGWB_EINVAL, "make_maps: k0 < 0");
@@ -254,6 +255,57 @@ int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int3
         if (rc) return rc;
     }
     return SGWB_OK;
+}
+
+size_t sgwb_fisher_overlap_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint32_t flags)
+{
+    if (nt < 1 || nf < 1 || npix < 1) return 0;
+    const int32_t ncol = (flags & SGWB_MAPS_ANTIPODAL) ? npix / 2 : npix;
+    size_t n = up256(beam_workspace_bytes(nt, nf, ncol)) + up256(pair_workspace_bytes(nt, nf, npix));
+    if (flags & SGWB_MAPS_ANTIPODAL) n += up256(xm_workspace_bytes(63, nt, nf));
+    return n;
+}
+
+int sgwb_fisher_overlap(const float *v, const float *u, const float *wn, int64_t ldc, int32_t nt, int32_t nf,
+                        const sgwb_fgrid *fg, int64_t k0, const float *gamma, const double *tau, int32_t npix,
+                        uint32_t flags, float *Gam, void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    if (!Gam) return set_error(SGWB_EINVAL, "fisher_overlap: null Gam");
+    if (!u || !wn) return set_error(SGWB_EINVAL, "fisher_overlap: null neighbour series");
+    if (((uintptr_t)u % 4) || ((uintptr_t)wn % 4)) return set_error(SGWB_EINVAL, "fisher_overlap: misaligned input");
+    // v plays the role of w; no CSD is read
+    MapArgs a;
+    int rc = check_maps_args<float>(nullptr, v, ldc, nt, nf, fg, k0, gamma, tau, npix, flags, &a, true);
+    if (rc) return rc;
+    if (!workspace || (uintptr_t)workspace % 256) return set_error(SGWB_EINVAL, "fisher_overlap: workspace null or not 256-byte aligned");
+    const int32_t ncol = a.nside > 0 ? npix / 2 : npix;
+    const size_t beam_bytes = up256(beam_workspace_bytes(nt, nf, ncol));
+    const size_t pair_bytes = up256(pair_workspace_bytes(nt, nf, npix));
+    if (workspace_bytes < beam_bytes + pair_bytes)
+        return set_error(SGWB_ENOMEM, "fisher_overlap: workspace of %zu bytes needed, %zu given",
+                         sgwb_fisher_overlap_workspace_size(nt, nf, npix, flags), workspace_bytes);
+    char *ws = reinterpret_cast<char *>(workspace);
+    rc = check_hip(launch_beam_bf16x3(a, v, gamma, Gam, ws, default_beam_shape(), stream), "beam kernel launch");
+    if (rc) return rc;
+    const bool use_xm = !(flags & SGWB_MAPS_VALU_X) && x_kernel_choice() != kXKernelValu && xm_eligible(a) &&
+                        workspace_bytes >= beam_bytes + pair_bytes + xm_workspace_bytes(k0, nt, nf);
+    return check_hip(launch_fisher_neighbours(a, u, wn, gamma, tau, Gam, ws + beam_bytes,
+                                              ws + beam_bytes + pair_bytes, use_xm, stream),
+                     "fisher neighbour-term launch");
+}
+
+int sgwb_fold(const float *C, const float *sinv, const uint8_t *present, int64_t ldc, int32_t ndays, int32_t nt,
+              int32_t nf, double W, float *v, float *u, float *w, float *x, hipStream_t stream)
+{
+    if (!C || !sinv || !present || !v || !u || !w || !x) return set_error(SGWB_EINVAL, "fold: null pointer");
+    if (ndays < 1 || nt < 1 || nf < 1) return set_error(SGWB_EINVAL, "fold: ndays, nt, nf must be >= 1");
+    if (ldc < nf) return set_error(SGWB_EINVAL, "fold: ldc %lld < nf %d", (long long)ldc, nf);
+    if (!std::isfinite(W) || W < 0.0) return set_error(SGWB_EINVAL, "fold: W must be finite and >= 0");
+    if (((uintptr_t)C % 8) || ((uintptr_t)sinv % 4) || ((uintptr_t)x % 8) || ((uintptr_t)v % 4) ||
+        ((uintptr_t)u % 4) || ((uintptr_t)w % 4))
+        return set_error(SGWB_EINVAL, "fold: misaligned pointer");
+    if ((int64_t)nt + 7 >= 8LL * 65535) return set_error(SGWB_EINVAL, "fold: nt too large");
+    return check_hip(launch_fold(C, sinv, present, ldc, ndays, nt, nf, W, v, u, w, x, stream), "fold kernel launch");
 }
 
 int sgwb_make_maps_f64(const double *C, const double *w, int64_t ldc, int32_t nt, int32_t nf,

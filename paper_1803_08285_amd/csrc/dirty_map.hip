@@ -146,10 +146,14 @@ __device__ inline void dirty_map_tile(const MapArgs &a, int64_t strip, int64_t c
             y.y = T(0);
             if (tt < tn && c >= 0 && c < a.nf) {
                 const int64_t off = (int64_t)(tc + tt) * a.ldc + c;
-                const C2 cv = C[off];
                 const T wv = w[off];
-                y.x = wv * cv.x;
-                y.y = wv * cv.y;
+                if (a.unit_c) {
+                    y.x = wv;
+                } else {
+                    const C2 cv = C[off];
+                    y.x = wv * cv.x;
+                    y.y = wv * cv.y;
+                }
             }
             ys[tt][kk] = y;
         }
@@ -191,10 +195,11 @@ __device__ inline void dirty_map_tile(const MapArgs &a, int64_t strip, int64_t c
         if (c < 0 || c >= a.nf) continue;
         T *row = X + c * (int64_t)a.npix;
         if (PAIR) {
-            row[col] = acc_a[j] - acc_b[j];
-            row[colB] = acc_a[j] + acc_b[j];
+            const T xa = acc_a[j] - acc_b[j], xb = acc_a[j] + acc_b[j];
+            row[col] = a.accumulate ? row[col] + xa : xa;
+            row[colB] = a.accumulate ? row[colB] + xb : xb;
         } else {
-            row[col] = acc_a[j];
+            row[col] = a.accumulate ? row[col] + acc_a[j] : acc_a[j];
         }
     }
 }

@@ -119,10 +119,22 @@ struct MapArgs {
     int32_t nt, nf, npix;
     int64_t nside;      // > 0 when the antipodal pairing is used
     double f0, df;
+    int32_t unit_c = 0;      // C is not read: C = 1 + 0i, so y = w (real data)
+    int32_t accumulate = 0;  // add the dirty map to X instead of writing it
 };
 template <typename T>
 hipError_t launch_dirty_map(const MapArgs &a, const T *C, const T *w, const T *gamma,
                             const double *tau, T *X, hipStream_t s);
+
+// Folding of several sidereal days into one (float32 in and out, float64 sums).
+hipError_t launch_fold(const float *C, const float *sv, const uint8_t *present, int64_t ldc, int32_t ndays, int32_t nt,
+                       int32_t nf, double W, float *v, float *u, float *w, float *x, hipStream_t s);
+
+// Neighbour terms of the overlap-corrected Fisher diagonal, added into Gam.
+size_t pair_workspace_bytes(int32_t nt, int32_t nf, int32_t npix);
+hipError_t launch_fisher_neighbours(const MapArgs &a, const float *u, const float *wn, const float *gamma,
+                                    const double *tau, float *Gam, void *pair_ws, void *xm_ws, bool use_xm,
+                                    hipStream_t s);
 
 // Matrix-core dirty map (float32, antipodal seeds, df <= ~1/32 Hz).
 bool xm_eligible(const MapArgs &a);

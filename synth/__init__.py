@@ -137,16 +137,21 @@ HANN_OVERLAP_W = 3.0 / 70.0
 
 
 def overlap_series(v, W: float = HANN_OVERLAP_W):
-    """Neighbour series u, w of a folded day in which every segment exists, from the
-    folded inverse variances v[nt][nf] (Sec. II.B): u_t = W (v_t + v_{t-1}) / 2 for
+    """Neighbour series u, w of a single day in which every segment exists, from
+    the inverse variances v[nt][nf] (Sec. II.B): u_t = W (v_t + v_{t-1}) / 2 for
     t >= 1 and w_t = W (v_t + v_{t+1}) / 2 for t <= nt - 2; zero where the neighbour
-    is missing (u row 0, w row nt - 1).  Then u_t = w_{t-1}."""
+    is missing (u row 0, w row nt - 1: no previous or next day).  Then u_t = w_{t-1}."""
     v = np.asarray(v, dtype=np.float64)
     u = np.zeros_like(v)
     w = np.zeros_like(v)
     u[1:] = 0.5 * W * (v[1:] + v[:-1])
     w[:-1] = 0.5 * W * (v[:-1] + v[1:])
     return u, w
+
+
+def day_presence(seed: int, ndays: int, nt: int, p_missing: float = 0.05):
+    """Segments with data [ndays][nt] (True), a seeded fraction missing at random."""
+    return np.random.default_rng(seed).random((ndays, nt)) >= p_missing
 
 
 def noise_csd(seed: int, nt: int, f, dtype=np.complex128):

@@ -67,3 +67,40 @@ def test_host_side_validation_rejects_before_any_device_work():
     rc = L.sgwb_make_maps(dummy, dummy, 8, 10, 8, ctypes.byref(bad), 0, dummy, dummy, 768, 1, dummy, None, None, 0,
                           None)
     assert rc == -1
+
+
+def test_fisher_overlap_validation_on_the_host():
+    import paper_1803_08285_amd as sg
+
+    L = sg.lib()
+    fg = sg._FGrid(20.0, 1 / 32)
+    d = ctypes.c_void_p(256)
+    # null neighbour series with nt >= 2
+    rc = L.sgwb_fisher_overlap(d, None, d, 8, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1, d, d, 1 << 30, None)
+    assert rc == -1 and b"neighbour" in L.sgwb_last_error()
+    # no output
+    rc = L.sgwb_fisher_overlap(d, d, d, 8, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1, None, d, 1 << 30, None)
+    assert rc == -1
+    # ldc < nf
+    rc = L.sgwb_fisher_overlap(d, d, d, 4, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1, d, d, 1 << 30, None)
+    assert rc == -1 and b"ldc" in L.sgwb_last_error()
+    # workspace too small
+    rc = L.sgwb_fisher_overlap(d, d, d, 8, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1, d, d, 256, None)
+    assert rc == -2
+    # sizes grow with the number of segments
+    one = L.sgwb_fisher_overlap_workspace_size(1, 8, 768, 1)
+    two = L.sgwb_fisher_overlap_workspace_size(2, 8, 768, 1)
+    assert 0 < one < two
+
+
+def test_fold_validation_on_the_host():
+    import paper_1803_08285_amd as sg
+
+    L = sg.lib()
+    d = ctypes.c_void_p(256)
+    rc = L.sgwb_fold(d, None, d, 8, 2, 10, 8, 0.05, d, d, d, d, None)
+    assert rc == -1 and b"null" in L.sgwb_last_error()
+    rc = L.sgwb_fold(d, d, d, 4, 2, 10, 8, 0.05, d, d, d, d, None)
+    assert rc == -1 and b"ldc" in L.sgwb_last_error()
+    rc = L.sgwb_fold(d, d, d, 8, 2, 10, 8, float("nan"), d, d, d, d, None)
+    assert rc == -1 and b"W" in L.sgwb_last_error()

@@ -21,11 +21,9 @@ def _series(seed, nt, nf, symmetric=True):
     v = rng.uniform(0.5, 2.0, (nt, nf))
     if symmetric:
         u, w = synth.overlap_series(v)
-    else:
+    else:  # unrelated series, nonzero wrap entries u[0], w[-1]
         u = rng.uniform(-0.1, 0.1, (nt, nf))
         w = rng.uniform(-0.1, 0.1, (nt, nf))
-        u[0] = 0.0
-        w[-1] = 0.0
     return v, u, w
 
 
@@ -42,8 +40,9 @@ def test_no_neighbours_is_the_plain_diagonal(oracle_mod):
 
 @pytest.mark.parametrize("symmetric", [True, False])
 def test_matches_tridiagonal_quadratic_form(oracle_mod, symmetric):
-    """Gamma_pp = K_p^H M K_p with the tridiagonal M = diag(v) - sub(u) - super(w)
-    (the paper's matrix form of the neighbour terms), by NumPy complex algebra."""
+    """Gamma_pp = K_p^H M K_p with the periodic tridiagonal M = diag(v) - sub(u) -
+    super(w), corners -u_0 and -w_{nt-1} (the folded day repeats), by NumPy
+    complex algebra."""
     nt, nf, nside, k0 = 17, 5, 2, 40
     g, t = _geometry(oracle_mod, nside, nt, 5000.0)
     v, u, w = _series(2, nt, nf, symmetric)
@@ -51,6 +50,8 @@ def test_matches_tridiagonal_quadratic_form(oracle_mod, symmetric):
     f = freqs(F0, DF, k0, nf)
     for k in range(nf):
         M = np.diag(v[:, k]) - np.diag(u[1:, k], -1) - np.diag(w[:-1, k], 1)
+        M[0, -1] -= u[0, k]
+        M[-1, 0] -= w[-1, k]
         K = g * np.exp(2j * np.pi * f[k] * t)  # [nt][npix]
         quad = np.einsum("tp,ts,sp->p", K.conj(), M, K)
         np.testing.assert_allclose(G[k], quad.real, rtol=1e-11, atol=1e-12 * np.abs(quad).max())
@@ -73,7 +74,9 @@ def test_static_delays_closed_form(oracle_mod):
     t_static = np.repeat(t[:1], nt, axis=0)
     v, u, w = _series(4, nt, nf, symmetric=False)
     G, _, _ = oracle_mod.fisher_overlap(v, u, w, F0, DF, 7, g, t_static)
-    ref = v.T @ g ** 2 - u[1:].T @ (g[1:] * g[:-1]) - w[:-1].T @ (g[:-1] * g[1:])
+    gp = np.roll(g, 1, axis=0)   # predecessor, periodic
+    gn = np.roll(g, -1, axis=0)  # successor, periodic
+    ref = v.T @ g ** 2 - u.T @ (g * gp) - w.T @ (g * gn)
     np.testing.assert_allclose(G, ref, rtol=1e-12)
 
 
