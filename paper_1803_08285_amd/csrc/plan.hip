@@ -125,10 +125,8 @@ static hipError_t enqueue(sgwb_plan *p, hipStream_t s, int parts)
     if ((parts & 1) && p->xm_tiles > 0) {
         for (auto &x : p->xmjobs)
             if ((e = launch_xm_prep(x, s)) != hipSuccess) return e;
-        const int64_t grid = p->tun.xm_grid_per_cu > 0
-                                 ? std::min<int64_t>(p->xm_tiles, (int64_t)p->num_cus * p->tun.xm_grid_per_cu)
-                                 : p->xm_tiles;
-        if ((e = launch_xm_batched(p->d_xmjobs, (int32_t)p->xmjobs.size(), p->xm_tiles, grid, s)) != hipSuccess)
+        const int64_t grid = xm_batched_grid(p->xmjobs.data(), (int32_t)p->xmjobs.size());
+        if ((e = launch_xm_batched(p->d_xmjobs, (int32_t)p->xmjobs.size(), grid, s)) != hipSuccess)
             return e;
     }
     if (parts & 1) {
@@ -245,23 +243,6 @@ int autotune_plan(sgwb_plan *p, bool tune)
                     best.x_grid_per_cu = g;
                 }
             }
-    }
-    if (!p->xmjobs.empty()) {
-        best_ms = 1e30;
-        Tunables xb = best;
-        for (int g : {1, 2, 0}) {
-            Tunables c = best;
-            c.xm_grid_per_cu = g;
-            if ((rc = plan_set_tunables(p, c))) return rc;
-            const double ms = time_parts(p, s, 1, 1);
-            if (ms < 0) return check_hip(hipGetLastError(), "autotune: matrix-core dirty-map launch");
-            p->tune_ms.push_back(ms);
-            if (ms < best_ms) {
-                best_ms = ms;
-                xb.xm_grid_per_cu = g;
-            }
-        }
-        best = xb;
     }
     if (!p->bjobs.empty()) {
         best_ms = 1e30;
@@ -439,10 +420,10 @@ int sgwb_plan_describe(const sgwb_plan *p, char *buf, size_t len)
     }
     int n = snprintf(buf, len,
                      "{\"jobs\": %zu, \"x_tiles\": %lld, \"xm_tiles\": %lld, \"beam_workgroups\": %lld, \"x_strip_major\": %d, "
-                     "\"x_grid_per_cu\": %d, \"beam_shape\": \"%s\", \"beam_grid_per_cu\": %d, \"xm_grid_per_cu\": %d, \"tuned\": %s, "
+                     "\"x_grid_per_cu\": %d, \"beam_shape\": \"%s\", \"beam_grid_per_cu\": %d, \"tuned\": %s, "
                      "\"from_cache\": %s, \"tune_ms\": [%s], \"graph\": %s, \"key\": \"%s\"}",
                      p->jobs.size(), (long long)p->x_tiles, (long long)p->xm_tiles, (long long)p->b_wgs, p->tun.x_strip_major,
-                     p->tun.x_grid_per_cu, p->tun.beam_shape == kBeamShape2x4 ? "2x4" : "4x4", p->tun.beam_grid_per_cu, p->tun.xm_grid_per_cu,
+                     p->tun.x_grid_per_cu, p->tun.beam_shape == kBeamShape2x4 ? "2x4" : "4x4", p->tun.beam_grid_per_cu,
                      p->tuned ? "true" : "false", p->from_cache ? "true" : "false", ms.c_str(),
                      p->exec ? "true" : "false", p->tune_key.c_str());
     if (n < 0 || (size_t)n >= len) return set_error(SGWB_ENOMEM, "plan_describe: buffer too small");

@@ -147,11 +147,12 @@ struct XmArgs {
     double eta_scale;  // 2 pi 31.5 df
 };
 // One job of the multi-job matrix-core dirty map: operands prepared per job,
-// one persistent launch over the (strip, pixel block) tiles of all jobs.
+// one launch over the (strip, pixel block) tiles of all jobs.
 struct XmJob {
     XmArgs x;
     const uint4 *A;  // data-side fragments (job workspace)
     const int *e;    // per-bin scale exponents (job workspace)
+    double *tmax;    // largest |tau| of the job's seeds (job workspace, written by the prep)
     const float *C, *w, *gamma;
     const double *tau;
     float *X;
@@ -162,7 +163,8 @@ void fill_xmjob(XmJob *j, const MapArgs &a, const float *C, const float *w, cons
                 float *X, void *work);
 int64_t xmjob_tiles(const XmJob &j);
 hipError_t launch_xm_prep(const XmJob &j, hipStream_t s);
-hipError_t launch_xm_batched(const XmJob *jobs_dev, int32_t njobs, int64_t ntiles, int64_t grid, hipStream_t s);
+hipError_t launch_xm_batched(const XmJob *jobs_dev, int32_t njobs, int64_t grid, hipStream_t s);
+int64_t xm_batched_grid(const XmJob *jobs, int32_t njobs);  // host job copies
 
 // One job of the persistent multi-job dirty-map kernel (float32 path).
 struct XJob {
@@ -231,7 +233,6 @@ struct Tunables {
     int x_grid_per_cu = 2;    // persistent dirty-map workgroups per compute unit
     int beam_shape = kBeamShape2x4;
     int beam_grid_per_cu = 4; // persistent beam workgroups per compute unit
-    int xm_grid_per_cu = 1;   // matrix-core dirty-map workgroups per compute unit (0: one per tile)
 };
 bool tune_cache_load(const std::string &key, Tunables *t);
 void tune_cache_store(const std::string &key, const Tunables &t);

@@ -21,6 +21,7 @@ JOBS = [  # baseline, nside, nt, k0, nf, band, antipodal pairing, df (1/32: matr
     ("AB", 2, 7, 63, 2, (0, 2), True, 0.25),
     ("AC", 16, 50, 197, 400, (3, 399), True, 1 / 32),
     ("BC", 8, 33, 0, 64, (0, 64), True, 1 / 32),
+    ("AB", 8, 40, 70, 200, (1, 199), True, 1 / 32),  # short baseline: the four-term matrix-core form
 ]
 F0 = 20.0
 
