@@ -304,7 +304,7 @@ int sgwb_fold(const float *C, const float *sinv, const uint8_t *present, int64_t
     if (((uintptr_t)C % 8) || ((uintptr_t)sinv % 4) || ((uintptr_t)x % 8) || ((uintptr_t)v % 4) ||
         ((uintptr_t)u % 4) || ((uintptr_t)w % 4))
         return set_error(SGWB_EINVAL, "fold: misaligned pointer");
-    if ((int64_t)nt + 7 >= 8LL * 65535) return set_error(SGWB_EINVAL, "fold: nt too large");
+    if (nt > 65535) return set_error(SGWB_EINVAL, "fold: nt > 65535 segments per day");
     return check_hip(launch_fold(C, sinv, present, ldc, ndays, nt, nf, W, v, u, w, x, stream), "fold kernel launch");
 }
 
