@@ -82,6 +82,10 @@ def _load():
         lib.orc_fold.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_long, dp, dp,
                                  ctypes.POINTER(ctypes.c_ubyte), ctypes.c_double, dp, dp, dp, dp]
         lib.orc_fold.restype = None
+        lib.orc_network_sum.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp]
+        lib.orc_network_sum.restype = None
+        lib.orc_contract.argtypes = [ctypes.c_int, ctypes.c_long, dp, ctypes.c_int, i64p, dp]
+        lib.orc_contract.restype = None
         _lib = lib
     return _lib
 
@@ -258,6 +262,33 @@ def fold(C, s, present, W: float):
     _load().orc_fold(ndays, nt, nf, nf, _dp(Cv), _dp(s), pres.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)),
                      float(W), _dp(v), _dp(u), _dp(w), _dp(xv))
     return v, u, w, x
+
+
+def network_sum(maps):
+    """Element-wise sum over baselines of equally shaped maps (sequence of arrays)."""
+    arr = np.ascontiguousarray(np.stack([_f64(m) for m in maps]))
+    nmaps = arr.shape[0]
+    out = np.empty(arr.shape[1:])
+    _load().orc_network_sum(nmaps, int(out.size), _dp(arr), _dp(out))
+    return out
+
+
+def contract(M, pix=None):
+    """Per-row sum of M[nf][npix] over the pixel set pix (all pixels if None)."""
+    M = _f64(M)
+    if M.ndim == 1:
+        M = M[None, :]
+    nf, npix = M.shape
+    out = np.empty(nf)
+    if pix is None:
+        _load().orc_contract(nf, npix, _dp(M), -1, None, _dp(out))
+    else:
+        pix = np.ascontiguousarray(pix, dtype=np.int64)
+        if pix.size and (pix.min() < 0 or pix.max() >= npix):
+            raise IndexError("pixel out of range")
+        _load().orc_contract(nf, npix, _dp(M), int(pix.size), pix.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                             _dp(out))
+    return out
 
 
 def band(X, G, H, klo: int, khi: int):

@@ -379,3 +379,34 @@ void orc_fold(int ndays, int nt, int nf, long ld, const double *C, const double 
             x[2 * ((long)tau * nf + c) + 1] = xi;
         }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Network sum over baselines (the sum over I of Eq. eq:narrowband): the      */
+/* element-wise sum of nmaps maps of n values, in map order.                  */
+/* ------------------------------------------------------------------------ */
+void orc_network_sum(int nmaps, long n, const double *maps, double *out)
+{
+    for (long i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int m = 0; m < nmaps; ++m) acc += maps[(long)m * n + i];
+        out[i] = acc;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Directed and isotropic contractions (Sec. V): per row k of a map M[nf][npix] */
+/* the sum over the pixels of a set (the pixels that contain a source), or     */
+/* over all pixels when nsel < 0; HEALPix pixels have equal area, so no        */
+/* weights.                                                                   */
+/* ------------------------------------------------------------------------ */
+void orc_contract(int nf, long npix, const double *M, int nsel, const int64_t *pix, double *out)
+{
+    for (int k = 0; k < nf; ++k) {
+        double acc = 0.0;
+        if (nsel < 0)
+            for (long p = 0; p < npix; ++p) acc += M[(long)k * npix + p];
+        else
+            for (int j = 0; j < nsel; ++j) acc += M[(long)k * npix + pix[j]];
+        out[k] = acc;
+    }
+}
