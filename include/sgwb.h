@@ -128,6 +128,26 @@ int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int3
                    int32_t npix, uint32_t flags, float *X, float *Gam, void *workspace,
                    size_t workspace_bytes, hipStream_t stream);
 
+/* ---- network sum: the sum over baselines I of Eq. eq:narrowband ------------
+ * out[i] = sum_{m < nmaps} maps[m][i] for i < n: the narrowband (or broadband)
+ * maps X or Gam of several baselines with one pixelisation and band, added
+ * element-wise (float64 sums in map order, rounded once).
+ * maps: host array of nmaps device pointers (1 <= nmaps <= 32); out may alias
+ * none of them.  Errors: SGWB_EINVAL (null pointer, nmaps or n out of range).  */
+int sgwb_network_sum(const float *const *maps /*host array of device pointers*/, int32_t nmaps, int64_t n,
+                     float *out, hipStream_t stream);
+
+/* ---- directed and isotropic contractions: Sec. V -------------------------
+ * A directed search adds the values of the pixels that contain the source; the
+ * isotropic search adds all pixels (HEALPix pixels have equal area: no
+ * weights).  out[k] = sum_{j < nsel} M[k][pix[j]] for each of the nf rows of
+ * M [nf][npix] (narrowband maps, or nf = 1 for a broadband map); pix = NULL
+ * sums all npix pixels.  pix is a device array of int32 RING indices that the
+ * caller keeps in range [0, npix).  float64 sums in a fixed order, rounded once.
+ * Errors: SGWB_EINVAL (null M or out, nf/npix < 1, nsel < 0, misaligned pix). */
+int sgwb_contract_pixels(const float *M, int32_t nf, int32_t npix, const int32_t *pix, int32_t nsel, float *out,
+                         hipStream_t stream);
+
 /* ---- folding: Sec. II.B (Eqs. eq_foldx, eq_foldgamma and the folded series
  * of overlapping windows) ------------------------------------------------------
  * The geometry repeats every sidereal day, so the data of ndays days, nt

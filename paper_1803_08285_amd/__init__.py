@@ -87,6 +87,8 @@ _SIGNATURES = {
                         ctypes.c_uint32, _VP, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_make_maps_f64": ([_VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
                             ctypes.c_uint32, _VP, _VP, _VP], ctypes.c_int),
+    "sgwb_network_sum": ([ctypes.POINTER(ctypes.c_void_p), _I32, _I64, _VP, _VP], ctypes.c_int),
+    "sgwb_contract_pixels": ([_VP, _I32, _I32, _VP, _I32, _VP, _VP], ctypes.c_int),
     "sgwb_fold": ([_VP, _VP, _VP, _I64, _I32, _I32, _I32, ctypes.c_double, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
     "sgwb_fisher_overlap_workspace_size": ([_I32, _I32, _I32, ctypes.c_uint32], ctypes.c_size_t),
     "sgwb_fisher_overlap": ([_VP, _VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
@@ -284,6 +286,47 @@ def make_maps(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamma: to
                                       _stream())
     _check(rc, "make_maps")
     return X, G
+
+
+def network_sum(maps, out=None):
+    """Element-wise sum of float32 maps of several baselines (same shape), in order."""
+    maps = list(maps)
+    if not maps:
+        raise SgwbError("network_sum: no maps")
+    shape, dev = tuple(maps[0].shape), maps[0].device
+    for i, m in enumerate(maps):
+        _require(m, f"maps[{i}]", torch.float32, shape)
+        _require_contig(m, f"maps[{i}]")
+    out = torch.empty(shape, dtype=torch.float32, device=dev) if out is None else out
+    _require(out, "out", torch.float32, shape)
+    _require_contig(out, "out")
+    arr = (ctypes.c_void_p * len(maps))(*[m.data_ptr() for m in maps])
+    with torch.cuda.device(dev):
+        rc = lib().sgwb_network_sum(arr, len(maps), int(out.numel()), _ptr(out), _stream())
+    _check(rc, "network_sum")
+    return out
+
+
+def contract_pixels(M: torch.Tensor, pix: torch.Tensor | None = None, out=None):
+    """Per-row sum of M [nf][npix] (or a broadband map [npix]) over the pixel set
+    pix (int tensor of RING indices on the device; None = all pixels: isotropic)."""
+    M2 = M if M.dim() == 2 else M.reshape(1, -1)
+    nf, npix = M2.shape
+    _require(M2, "M", torch.float32, (nf, npix))
+    _require_contig(M2, "M")
+    p = None
+    nsel = 0
+    if pix is not None:
+        p = pix.to(device=M.device, dtype=torch.int32).contiguous()
+        nsel = int(p.numel())
+        if nsel and (int(p.min()) < 0 or int(p.max()) >= npix):
+            raise SgwbError("contract_pixels: pixel index out of range")
+    out = torch.empty(nf, dtype=torch.float32, device=M.device) if out is None else out
+    with torch.cuda.device(M.device):
+        rc = lib().sgwb_contract_pixels(_ptr(M2), nf, npix, _ptr(p) if p is not None else None, nsel, _ptr(out),
+                                        _stream())
+    _check(rc, "contract_pixels")
+    return out
 
 
 def fold(C: torch.Tensor, sinv: torch.Tensor, present: torch.Tensor, W: float, out=None):

@@ -308,6 +308,31 @@ int sgwb_fold(const float *C, const float *sinv, const uint8_t *present, int64_t
     return check_hip(launch_fold(C, sinv, present, ldc, ndays, nt, nf, W, v, u, w, x, stream), "fold kernel launch");
 }
 
+int sgwb_network_sum(const float *const *maps, int32_t nmaps, int64_t n, float *out, hipStream_t stream)
+{
+    if (!maps || !out) return set_error(SGWB_EINVAL, "network_sum: null pointer");
+    if (nmaps < 1 || nmaps > kMaxNetworkMaps)
+        return set_error(SGWB_EINVAL, "network_sum: nmaps must be 1..%d", kMaxNetworkMaps);
+    if (n < 1) return set_error(SGWB_EINVAL, "network_sum: n must be >= 1");
+    MapList l{};
+    l.n = nmaps;
+    for (int32_t m = 0; m < nmaps; ++m) {
+        if (!maps[m]) return set_error(SGWB_EINVAL, "network_sum: map %d is null", m);
+        l.p[m] = maps[m];
+    }
+    return check_hip(launch_network_sum(l, n, out, stream), "network-sum kernel launch");
+}
+
+int sgwb_contract_pixels(const float *M, int32_t nf, int32_t npix, const int32_t *pix, int32_t nsel, float *out,
+                         hipStream_t stream)
+{
+    if (!M || !out) return set_error(SGWB_EINVAL, "contract_pixels: null pointer");
+    if (nf < 1 || npix < 1) return set_error(SGWB_EINVAL, "contract_pixels: nf, npix must be >= 1");
+    if (pix && nsel < 0) return set_error(SGWB_EINVAL, "contract_pixels: nsel < 0");
+    if ((uintptr_t)pix % 4) return set_error(SGWB_EINVAL, "contract_pixels: misaligned pixel list");
+    return check_hip(launch_contract(M, nf, npix, pix, pix ? nsel : 0, out, stream), "contraction kernel launch");
+}
+
 int sgwb_make_maps_f64(const double *C, const double *w, int64_t ldc, int32_t nt, int32_t nf,
                        const sgwb_fgrid *fg, int64_t k0, const double *gamma, const double *tau, int32_t npix,
                        uint32_t flags, double *X, double *Gam, hipStream_t stream)

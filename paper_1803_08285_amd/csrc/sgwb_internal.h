@@ -126,6 +126,16 @@ template <typename T>
 hipError_t launch_dirty_map(const MapArgs &a, const T *C, const T *w, const T *gamma,
                             const double *tau, T *X, hipStream_t s);
 
+// Network sums and pixel contractions.
+constexpr int kMaxNetworkMaps = 32;
+struct MapList {
+    const float *p[kMaxNetworkMaps];
+    int32_t n;
+};
+hipError_t launch_network_sum(const MapList &l, int64_t n, float *out, hipStream_t s);
+hipError_t launch_contract(const float *M, int32_t nf, int32_t npix, const int32_t *pix, int32_t nsel, float *out,
+                           hipStream_t s);
+
 // Folding of several sidereal days into one (float32 in and out, float64 sums).
 hipError_t launch_fold(const float *C, const float *sv, const uint8_t *present, int64_t ldc, int32_t ndays, int32_t nt,
                        int32_t nf, double W, float *v, float *u, float *w, float *x, hipStream_t s);

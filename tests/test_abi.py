@@ -104,3 +104,19 @@ def test_fold_validation_on_the_host():
     assert rc == -1 and b"ldc" in L.sgwb_last_error()
     rc = L.sgwb_fold(d, d, d, 8, 2, 10, 8, float("nan"), d, d, d, d, None)
     assert rc == -1 and b"W" in L.sgwb_last_error()
+
+
+def test_network_sum_and_contraction_validation_on_the_host():
+    import paper_1803_08285_amd as sg
+
+    L = sg.lib()
+    d = ctypes.c_void_p(256)
+    arr = (ctypes.c_void_p * 2)(256, None)
+    rc = L.sgwb_network_sum(arr, 2, 100, d, None)
+    assert rc == -1 and b"map 1" in L.sgwb_last_error()
+    rc = L.sgwb_network_sum(arr, 0, 100, d, None)
+    assert rc == -1
+    rc = L.sgwb_contract_pixels(d, 0, 768, None, 0, d, None)
+    assert rc == -1
+    rc = L.sgwb_contract_pixels(d, 4, 768, d, -3, d, None)
+    assert rc == -1 and b"nsel" in L.sgwb_last_error()
