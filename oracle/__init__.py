@@ -86,6 +86,10 @@ def _load():
         lib.orc_network_sum.restype = None
         lib.orc_contract.argtypes = [ctypes.c_int, ctypes.c_long, dp, ctypes.c_int, i64p, dp]
         lib.orc_contract.restype = None
+        lib.orc_fisher_full.argtypes = [ctypes.c_int, ctypes.c_long, ctypes.c_long, dp, dp, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_long, ctypes.c_int, ctypes.c_int, dp, dp, dp,
+                                        ctypes.c_int]
+        lib.orc_fisher_full.restype = None
         _lib = lib
     return _lib
 
@@ -289,6 +293,41 @@ def contract(M, pix=None):
         _load().orc_contract(nf, npix, _dp(M), int(pix.size), pix.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                              _dp(out))
     return out
+
+
+def fisher_full(w, H, f0: float, df: float, k0: int, klo: int, khi: int, gamma, tau, nthreads: int | None = None):
+    """Full Fisher matrix of the bins [klo, khi) (Eq. eq_fisher, broadband H
+    weighting of Sec. V): G[npix][npix]."""
+    w, H, gamma, tau = _f64(w), _f64(H), _f64(gamma), _f64(tau)
+    nt, nf = w.shape
+    npix = gamma.shape[1]
+    if not (0 <= klo <= khi <= nf):
+        raise IndexError("band out of range")
+    G = np.empty((npix, npix))
+    _load().orc_fisher_full(nt, nf, npix, _dp(w), _dp(H), float(f0), float(df), int(k0), int(klo), int(khi),
+                            _dp(gamma), _dp(tau), _dp(G), int(nthreads or default_threads()))
+    return G
+
+
+def cg(A, b, niter: int):
+    """Conjugate gradient for A x = b from x = 0, exactly niter iterations (the
+    clean-map solver of the footnote to Eq. eq_ML_linear); float64 NumPy."""
+    A = np.asarray(A, dtype=np.float64)
+    x = np.zeros_like(np.asarray(b, dtype=np.float64))
+    r = np.array(b, dtype=np.float64)
+    p = r.copy()
+    rr = r @ r
+    for _ in range(niter):
+        if rr == 0.0:
+            break
+        Ap = A @ p
+        alpha = rr / (p @ Ap)
+        x += alpha * p
+        r -= alpha * Ap
+        rr_new = r @ r
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return x
 
 
 def band(X, G, H, klo: int, khi: int):

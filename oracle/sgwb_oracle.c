@@ -410,3 +410,34 @@ void orc_contract(int nf, long npix, const double *M, int nsel, const int64_t *p
         out[k] = acc;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Full Fisher information matrix of a band (Eq. eq_fisher; the broadband     */
+/* spectral weighting of Sec. V as for the diagonal):                         */
+/*   G(p,p') = sum_{c in [clo,chi)} H_c sum_t w(t,c) Re[conj(K_p) K_p'],        */
+/*   K_p = gamma(t,p) exp(+2 pi i f_c tau(t,p))                                 */
+/*         => gamma_p gamma_p' cos 2 pi f_c (tau_p - tau_p').                  */
+/* w is [nt][ld] (column c = bin k0 + c), H is indexed by column; G[npix][npix]. */
+/* OpenMP over rows.                                                          */
+/* ------------------------------------------------------------------------ */
+void orc_fisher_full(int nt, long ld, long npix, const double *w, const double *H, double f0, double df,
+                     long k0, int clo, int chi, const double *gamma, const double *tau, double *G,
+                     int nthreads)
+{
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+    for (long p = 0; p < npix; ++p)
+        for (long q = 0; q < npix; ++q) {
+            double acc = 0.0;
+            for (int c = clo; c < chi; ++c) {
+                const double f = f0 + (double)(k0 + c) * df;
+                double s = 0.0;
+                for (int t = 0; t < nt; ++t) {
+                    const double gp = gamma[(long)t * npix + p], gq = gamma[(long)t * npix + q];
+                    const double d = tau[(long)t * npix + p] - tau[(long)t * npix + q];
+                    s += w[(long)t * ld + c] * gp * gq * cos(2.0 * ORC_PI * f * d);
+                }
+                acc += H[c] * s;
+            }
+            G[p * npix + q] = acc;
+        }
+}
