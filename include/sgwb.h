@@ -199,6 +199,52 @@ int sgwb_fisher_overlap(const float *v, const float *u, const float *w, int64_t 
                         int32_t npix, uint32_t flags, float *Gam, void *workspace, size_t workspace_bytes,
                         hipStream_t stream);
 
+/* ---- full Fisher matrix of a band: Eq. eq_fisher, broadband H weighting of
+ * Sec. V ----------------------------------------------------------------------
+ * For separable weights w(t,c) = a(t) b(c) (a per-segment noise factor times a
+ * per-bin spectral factor, which is how w = H / P^2 factors when the noise
+ * spectrum is stationary across segments):
+ *   G(p,q) = sum_{c in [clo,chi)} H(c) sum_t a(t) b(c) gamma(t,p) gamma(t,q)
+ *              cos 2 pi f_{k0+c} (tau(t,p) - tau(t,q))
+ *          = sum_t a(t) gamma(t,p) gamma(t,q) Wd(tau(t,p) - tau(t,q)),
+ *   Wd(D)  = sum_{c in [clo,chi)} H(c) b(c) cos 2 pi f_{k0+c} D.
+ * Its diagonal is the band sum of the per-bin diagonal Gam (sgwb_reduce_band's
+ * Gbb for the same w).
+ * Inputs (device): a float32 [nt]; b, H float32 [nf] (column c = bin k0 + c);
+ * gamma float32, tau float64 [nt][npix] as for sgwb_make_maps (no antipodal
+ * pairing: every pixel is a row and a column).  0 <= clo < chi <= nf.
+ * Output: G float32 [npix][npix] row-major, symmetric (overwritten).
+ * Arithmetic: Wd and its derivative tabulated once per call in float64 on 64
+ * points per period of the highest band frequency over |D| <= 4 R_earth / c
+ * and stored as float32; each (t, p, q) term interpolates the table (cubic
+ * Hermite, relative error < 2.4e-7 of sum |H b|), with D formed in float64;
+ * float32 accumulation over t.  Delays beyond the Earth bound clamp to the
+ * table's ends.
+ * Workspace: at least sgwb_fisher_full_workspace_size() bytes, 256-byte
+ * aligned, owned by the caller.
+ * Errors: SGWB_EINVAL (null pointer, nt/nf/npix < 1, band out of range, bad
+ * grid, misaligned pointer, more than 2^31 - 1 matrix tiles), SGWB_ENOMEM
+ * (workspace too small).                                                     */
+size_t sgwb_fisher_full_workspace_size(const sgwb_fgrid *fg /*host*/, int64_t k0, int32_t chi);
+int sgwb_fisher_full(const float *a, const float *b, const float *H, int32_t nf, const sgwb_fgrid *fg /*host*/,
+                     int64_t k0, int32_t clo, int32_t chi, const float *gamma, const double *tau, int32_t nt,
+                     int32_t npix, float *G, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ---- clean map: Eq. eq_ML_linear and its footnote ---------------------------
+ * The maximum-likelihood map P solves G P = X; G is poorly conditioned, so the
+ * clean map is the conjugate-gradient iterate after niter steps from P = 0
+ * (niter = 0 gives P = 0; a step whose residual or curvature is exactly zero
+ * leaves P unchanged).  G float32 [n][n] symmetric positive semi-definite, X
+ * float32 [n] (device); P float32 [n] (overwritten).  Vectors, dot products
+ * and the matrix-vector products run in float64 with fixed-order sums; the
+ * step scalars stay on the device (no host synchronisation).
+ * Workspace: at least sgwb_clean_map_workspace_size() bytes, 256-byte aligned.
+ * Errors: SGWB_EINVAL (null pointer, n < 1, niter < 0, misaligned pointer),
+ * SGWB_ENOMEM (workspace too small).                                          */
+size_t sgwb_clean_map_workspace_size(int32_t n);
+int sgwb_clean_map_cg(const float *G, const float *X, int32_t n, int32_t niter, float *P, void *workspace,
+                      size_t workspace_bytes, hipStream_t stream);
+
 /* float64 variant of the same definition (all inputs and outputs double; Gam
  * accumulated in float64 on the vector units; no workspace).                  */
 int sgwb_make_maps_f64(const double *C, const double *w, int64_t ldc, int32_t nt, int32_t nf,

@@ -93,6 +93,11 @@ _SIGNATURES = {
     "sgwb_fisher_overlap_workspace_size": ([_I32, _I32, _I32, ctypes.c_uint32], ctypes.c_size_t),
     "sgwb_fisher_overlap": ([_VP, _VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
                              ctypes.c_uint32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
+    "sgwb_fisher_full_workspace_size": ([ctypes.POINTER(_FGrid), _I64, _I32], ctypes.c_size_t),
+    "sgwb_fisher_full": ([_VP, _VP, _VP, _I32, ctypes.POINTER(_FGrid), _I64, _I32, _I32, _VP, _VP, _I32, _I32, _VP,
+                          _VP, ctypes.c_size_t, _VP], ctypes.c_int),
+    "sgwb_clean_map_workspace_size": ([_I32], ctypes.c_size_t),
+    "sgwb_clean_map_cg": ([_VP, _VP, _I32, _I32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_reduce_band_workspace_size": ([_I32, _I32, _I32], ctypes.c_size_t),
     "sgwb_reduce_band": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_reduce_band_f64": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
@@ -406,6 +411,63 @@ def fisher_overlap(v: torch.Tensor, u: torch.Tensor, wn: torch.Tensor, fgrid: FG
                                        wsz, _stream())
     _check(rc, "fisher_overlap")
     return G
+
+
+def fisher_full_workspace_bytes(fgrid: FGrid, k0: int, khi: int) -> int:
+    fg = _FGrid(float(fgrid.f0), float(fgrid.df))
+    return int(lib().sgwb_fisher_full_workspace_size(ctypes.byref(fg), int(k0), int(khi)))
+
+
+def fisher_full(a: torch.Tensor, b: torch.Tensor, H: torch.Tensor, fgrid: FGrid, k0: int, klo: int, khi: int,
+                gamma: torch.Tensor, tau: torch.Tensor, out=None, workspace: torch.Tensor | None = None):
+    """Full Fisher matrix G [npix][npix] of the bins [klo, khi) (Eq. eq_fisher,
+    broadband H weighting of Sec. V) for separable weights w(t,c) = a[t] b[c]:
+    a float32 [nt], b and H float32 [nf] (column c = bin k0 + c)."""
+    nt, npix = gamma.shape
+    nf = b.shape[0]
+    _require(a, "a", torch.float32, (nt,))
+    _require(b, "b", torch.float32, (nf,))
+    _require(H, "H", torch.float32, (nf,))
+    _require(gamma, "gamma", torch.float32, (nt, npix))
+    _require(tau, "tau", torch.float64, (nt, npix))
+    for name, t in (("a", a), ("b", b), ("H", H), ("gamma", gamma), ("tau", tau)):
+        _require_contig(t, name)
+    dev = gamma.device
+    G = out if out is not None else torch.empty((npix, npix), dtype=torch.float32, device=dev)
+    _require(G, "G", torch.float32, (npix, npix))
+    _require_contig(G, "G")
+    fg = _FGrid(float(fgrid.f0), float(fgrid.df))
+    with torch.cuda.device(dev):
+        if workspace is None:
+            need = fisher_full_workspace_bytes(fgrid, k0, khi) if 0 < khi else 0
+            workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        wsz = workspace.numel() * workspace.element_size()
+        rc = lib().sgwb_fisher_full(_ptr(a), _ptr(b), _ptr(H), nf, ctypes.byref(fg), int(k0), int(klo), int(khi),
+                                    _ptr(gamma), _ptr(tau), nt, npix, _ptr(G), _ptr(workspace), wsz, _stream())
+    _check(rc, "fisher_full")
+    return G
+
+
+def clean_map_cg(G: torch.Tensor, X: torch.Tensor, niter: int, out=None, workspace: torch.Tensor | None = None):
+    """Clean map (Eq. eq_ML_linear and its footnote): niter conjugate-gradient
+    steps on G P = X from P = 0; G float32 [n][n], X float32 [n]."""
+    n = X.shape[0]
+    _require(G, "G", torch.float32, (n, n))
+    _require(X, "X", torch.float32, (n,))
+    _require_contig(G, "G")
+    _require_contig(X, "X")
+    dev = X.device
+    P = out if out is not None else torch.empty(n, dtype=torch.float32, device=dev)
+    _require(P, "P", torch.float32, (n,))
+    _require_contig(P, "P")
+    with torch.cuda.device(dev):
+        if workspace is None:
+            workspace = torch.empty(max(int(lib().sgwb_clean_map_workspace_size(n)), 256), dtype=torch.uint8,
+                                    device=dev)
+        wsz = workspace.numel() * workspace.element_size()
+        rc = lib().sgwb_clean_map_cg(_ptr(G), _ptr(X), n, int(niter), _ptr(P), _ptr(workspace), wsz, _stream())
+    _check(rc, "clean_map_cg")
+    return P
 
 
 def band_workspace_bytes(npix: int, k_lo: int, k_hi: int) -> int:

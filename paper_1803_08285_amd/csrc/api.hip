@@ -333,6 +333,58 @@ int sgwb_contract_pixels(const float *M, int32_t nf, int32_t npix, const int32_t
     return check_hip(launch_contract(M, nf, npix, pix, pix ? nsel : 0, out, stream), "contraction kernel launch");
 }
 
+size_t sgwb_fisher_full_workspace_size(const sgwb_fgrid *fg, int64_t k0, int32_t chi)
+{
+    if (!fg || !std::isfinite(fg->f0_hz) || !std::isfinite(fg->df_hz) || fg->df_hz <= 0.0 || k0 < 0 || chi < 1)
+        return 0;
+    return fisher_full_workspace_bytes(fg->f0_hz + (double)(k0 + chi - 1) * fg->df_hz);
+}
+
+int sgwb_fisher_full(const float *a, const float *b, const float *H, int32_t nf, const sgwb_fgrid *fg, int64_t k0,
+                     int32_t clo, int32_t chi, const float *gamma, const double *tau, int32_t nt, int32_t npix,
+                     float *G, void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    if (!a || !b || !H || !fg || !gamma || !tau || !G) return set_error(SGWB_EINVAL, "fisher_full: null pointer");
+    if (nt < 1 || nf < 1 || npix < 1) return set_error(SGWB_EINVAL, "fisher_full: nt, nf, npix must be >= 1");
+    if (!(0 <= clo && clo < chi && chi <= nf))
+        return set_error(SGWB_EINVAL, "fisher_full: band [%d, %d) not inside [0, %d)", clo, chi, nf);
+    if (!std::isfinite(fg->f0_hz) || !std::isfinite(fg->df_hz) || fg->df_hz <= 0.0 || fg->f0_hz < 0.0 || k0 < 0)
+        return set_error(SGWB_EINVAL, "fisher_full: bad frequency grid");
+    if (((uintptr_t)a % 4) || ((uintptr_t)b % 4) || ((uintptr_t)H % 4) || ((uintptr_t)gamma % 4) ||
+        ((uintptr_t)tau % 8) || ((uintptr_t)G % 4))
+        return set_error(SGWB_EINVAL, "fisher_full: misaligned pointer");
+    const int64_t ntile = ((int64_t)npix + 63) / 64;
+    if (ntile * (ntile + 1) / 2 > 0x7fffffff) return set_error(SGWB_EINVAL, "fisher_full: npix too large");
+    if (!workspace || (uintptr_t)workspace % 256)
+        return set_error(SGWB_EINVAL, "fisher_full: workspace null or not 256-byte aligned");
+    const size_t need = sgwb_fisher_full_workspace_size(fg, k0, chi);
+    if (workspace_bytes < need)
+        return set_error(SGWB_ENOMEM, "fisher_full: workspace of %zu bytes needed, %zu given", need, workspace_bytes);
+    return check_hip(launch_fisher_full(a, b, H, clo, chi, fg->f0_hz, fg->df_hz, k0, gamma, tau, nt, npix, G,
+                                        workspace, stream),
+                     "full Fisher launch");
+}
+
+size_t sgwb_clean_map_workspace_size(int32_t n)
+{
+    return n < 1 ? 0 : cg_workspace_bytes(n);
+}
+
+int sgwb_clean_map_cg(const float *G, const float *X, int32_t n, int32_t niter, float *P, void *workspace,
+                      size_t workspace_bytes, hipStream_t stream)
+{
+    if (!G || !X || !P) return set_error(SGWB_EINVAL, "clean_map_cg: null pointer");
+    if (n < 1 || niter < 0) return set_error(SGWB_EINVAL, "clean_map_cg: n must be >= 1 and niter >= 0");
+    if (((uintptr_t)G % 4) || ((uintptr_t)X % 4) || ((uintptr_t)P % 4))
+        return set_error(SGWB_EINVAL, "clean_map_cg: misaligned pointer");
+    if (!workspace || (uintptr_t)workspace % 256)
+        return set_error(SGWB_EINVAL, "clean_map_cg: workspace null or not 256-byte aligned");
+    if (workspace_bytes < cg_workspace_bytes(n))
+        return set_error(SGWB_ENOMEM, "clean_map_cg: workspace of %zu bytes needed, %zu given",
+                         cg_workspace_bytes(n), workspace_bytes);
+    return check_hip(launch_clean_map_cg(G, X, n, niter, P, workspace, stream), "clean-map launch");
+}
+
 int sgwb_make_maps_f64(const double *C, const double *w, int64_t ldc, int32_t nt, int32_t nf,
                        const sgwb_fgrid *fg, int64_t k0, const double *gamma, const double *tau, int32_t npix,
                        uint32_t flags, double *X, double *Gam, hipStream_t stream)

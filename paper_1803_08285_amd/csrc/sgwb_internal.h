@@ -136,6 +136,15 @@ hipError_t launch_network_sum(const MapList &l, int64_t n, float *out, hipStream
 hipError_t launch_contract(const float *M, int32_t nf, int32_t npix, const int32_t *pix, int32_t nsel, float *out,
                            hipStream_t s);
 
+// full Fisher matrix of a band for separable weights, and its CG clean map
+size_t fisher_full_workspace_bytes(double f_max);
+hipError_t launch_fisher_full(const float *a, const float *b, const float *H, int32_t clo, int32_t chi, double f0,
+                              double df, int64_t k0, const float *gamma, const double *tau, int32_t nt, int32_t npix,
+                              float *G, void *work, hipStream_t s);
+size_t cg_workspace_bytes(int32_t n);
+hipError_t launch_clean_map_cg(const float *G, const float *X, int32_t n, int32_t niter, float *P, void *work,
+                               hipStream_t s);
+
 // Folding of several sidereal days into one (float32 in and out, float64 sums).
 hipError_t launch_fold(const float *C, const float *sv, const uint8_t *present, int64_t ldc, int32_t ndays, int32_t nt,
                        int32_t nf, double W, float *v, float *u, float *w, float *x, hipStream_t s);

@@ -120,3 +120,40 @@ def test_network_sum_and_contraction_validation_on_the_host():
     assert rc == -1
     rc = L.sgwb_contract_pixels(d, 4, 768, d, -3, d, None)
     assert rc == -1 and b"nsel" in L.sgwb_last_error()
+
+
+def test_fisher_full_and_clean_map_validation_on_the_host():
+    import paper_1803_08285_amd as sg
+
+    L = sg.lib()
+    fg = sg._FGrid(20.0, 1 / 32)
+    d = ctypes.c_void_p(256)
+    big = 1 << 30
+    # band outside the columns
+    rc = L.sgwb_fisher_full(d, d, d, 10, ctypes.byref(fg), 0, 4, 11, d, d, 8, 768, d, d, big, None)
+    assert rc == -1 and b"band" in L.sgwb_last_error()
+    rc = L.sgwb_fisher_full(d, d, d, 10, ctypes.byref(fg), 0, 5, 5, d, d, 8, 768, d, d, big, None)
+    assert rc == -1
+    # null output
+    rc = L.sgwb_fisher_full(d, d, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, None, d, big, None)
+    assert rc == -1
+    # misaligned tau (float64)
+    rc = L.sgwb_fisher_full(d, d, d, 10, ctypes.byref(fg), 0, 0, 10, d, ctypes.c_void_p(260), 8, 768, d, d, big,
+                            None)
+    assert rc == -1 and b"misaligned" in L.sgwb_last_error()
+    # workspace too small; the table grows with the top frequency of the band
+    rc = L.sgwb_fisher_full(d, d, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, d, d, 256, None)
+    assert rc == -2
+    low = L.sgwb_fisher_full_workspace_size(ctypes.byref(fg), 0, 10)
+    high = L.sgwb_fisher_full_workspace_size(ctypes.byref(fg), 50000, 10)
+    assert 0 < low < high
+    bad = sg._FGrid(20.0, 0.0)
+    assert L.sgwb_fisher_full_workspace_size(ctypes.byref(bad), 0, 10) == 0
+    # clean map
+    rc = L.sgwb_clean_map_cg(d, d, 0, 5, d, d, big, None)
+    assert rc == -1
+    rc = L.sgwb_clean_map_cg(d, d, 10, -1, d, d, big, None)
+    assert rc == -1
+    rc = L.sgwb_clean_map_cg(d, d, 10, 5, d, d, 8, None)
+    assert rc == -2
+    assert L.sgwb_clean_map_workspace_size(0) == 0 < L.sgwb_clean_map_workspace_size(10)

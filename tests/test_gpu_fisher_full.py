@@ -1,0 +1,160 @@
+"""Full Fisher matrix of a band (Eq. eq_fisher, broadband H weighting of Sec. V)
+and the conjugate-gradient clean map (Eq. eq_ML_linear and its footnote) on the
+GPU against the FP64 oracle, through the C ABI.
+
+Tolerance of G: max |G_gpu - G_oracle| / S <= 1e-5 with
+S(p,q) = sum_c |H b| sum_t a |gamma_p gamma_q| (the same scale as the dirty
+map's bound: each term of the band sum is bounded by it).  Budget: cubic Hermite
+interpolation of the delay table (< 2.4e-7 S), float32 table entries and
+interpolation arithmetic (a few 1e-7 S), float32 accumulation over the
+segments (~ sqrt(nt) 6e-8 S).  The oracle entry G(p,q) depends only on pixels
+p and q, so at sizes where the whole oracle matrix is slow it is evaluated on a
+sampled pixel subset.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests._cases import freqs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+F0 = 20.0
+CASES = [  # baseline, nside, npix used (None: all), nt, k0, nf, band, df
+    ("AB", 2, None, 24, 10, 40, (0, 40), 0.25),         # one ragged tile (48 pixels)
+    ("AC", 4, None, 40, 100, 64, (5, 60), 0.25),        # 3 x 3 tiles, sub-band
+    ("BC", 4, 150, 33, 0, 30, (0, 30), 1.0),            # ragged multi-tile (150 = 2 x 64 + 22)
+    ("AB", 8, None, 60, 53000, 64, (0, 64), 1 / 32),    # top of the band (1.68 kHz), 12 x 12 tiles
+    ("AC", 2, None, 7, 63, 2, (1, 2), 0.25),            # single bin, tiny day
+]
+
+
+@pytest.fixture(scope="module")
+def sg():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_1803_08285_amd as sg
+
+    return sg
+
+
+def _inputs(sg, bl, nside, npix_used, nt, k0, nf, df, seed):
+    tg = sg.TGrid(nt, 0.0, 86164.0905 / nt, 86164.0905 / nt)
+    g, t = sg.build_geometry(synth.baseline_sites(bl), nside, tg)
+    if npix_used is not None:
+        g, t = g[:, :npix_used].contiguous(), t[:, :npix_used].contiguous()
+    f = freqs(F0, df, k0, nf)
+    a = synth.segment_scale(nt, seed).astype(np.float32)
+    b = (synth.spectrum_H(f) / synth.noise_psd(f) ** 2).astype(np.float32)
+    H = synth.spectrum_H(f).astype(np.float32)
+    return g, t, a, b, H
+
+
+def _scale(a, b, H, klo, khi, gh):
+    """S(p,q) = sum_c |H b| sum_t a |gamma_p gamma_q|."""
+    hb = np.abs(H[klo:khi].astype(np.float64) * b[klo:khi].astype(np.float64)).sum()
+    ag = np.abs(gh) * a.astype(np.float64)[:, None]
+    return hb * (ag.T @ np.abs(gh))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-{c[1]}-{c[2]}-{c[4]}-{c[7]}" for c in CASES])
+def test_fisher_full_vs_oracle(sg, oracle_mod, case):
+    bl, nside, npix_used, nt, k0, nf, (klo, khi), df = case
+    g, t, a, b, H = _inputs(sg, bl, nside, npix_used, nt, k0, nf, df, 21)
+    ad, bd, Hd = (torch.from_numpy(x).cuda() for x in (a, b, H))
+    G = sg.fisher_full(ad, bd, Hd, sg.FGrid(F0, df), k0, klo, khi, g, t)
+    torch.cuda.synchronize()
+    Gg = G.cpu().numpy().astype(np.float64)
+    gh, th = g.cpu().numpy().astype(np.float64), t.cpu().numpy()
+    npix = gh.shape[1]
+    sel = np.arange(npix) if npix <= 200 else np.sort(np.random.default_rng(4).choice(npix, 40, replace=False))
+    w = np.outer(a.astype(np.float64), b.astype(np.float64))
+    Go = oracle_mod.fisher_full(w, H.astype(np.float64), F0, df, k0, klo, khi, gh[:, sel], th[:, sel])
+    S = _scale(a, b, H, klo, khi, gh[:, sel])
+    err = np.abs(Gg[np.ix_(sel, sel)] - Go) / S
+    assert np.max(err) <= 1e-5
+    assert np.array_equal(Gg, Gg.T)  # both triangles written from one value
+
+
+def test_fisher_full_diagonal_is_the_band_summed_diagonal(sg):
+    """diag G = Gbb of the per-bin diagonal (same separable w) reduced over the band."""
+    nt, nside, k0, nf, df, klo, khi = 48, 8, 200, 96, 1 / 32, 7, 90
+    g, t, a, b, H = _inputs(sg, "AB", nside, None, nt, k0, nf, df, 22)
+    ad, bd, Hd = (torch.from_numpy(x).cuda() for x in (a, b, H))
+    G = sg.fisher_full(ad, bd, Hd, sg.FGrid(F0, df), k0, klo, khi, g, t)
+    w = (ad[:, None] * bd[None, :]).contiguous()
+    C = torch.zeros((nt, nf), dtype=torch.complex64, device="cuda")
+    _, Gk = sg.make_maps(C, w, sg.FGrid(F0, df), k0, g, t, antipodal=False)
+    _, Gbb = sg.reduce_band(None, Gk, Hd, klo, khi)
+    torch.cuda.synchronize()
+    d = torch.diagonal(G).double().cpu().numpy()
+    ref = Gbb.double().cpu().numpy()
+    assert np.max(np.abs(d - ref) / ref) <= 1e-4  # split-bf16 beam bound on the per-bin diagonal
+
+
+def test_noise_free_sky_gives_x_equal_g_p(sg):
+    """C = K P without noise (Eq. eq_CSD_conv): the broadband dirty map of the GPU
+    path equals the GPU's full Fisher matrix times the injected sky."""
+    nt, nside, k0, nf, df = 40, 4, 100, 64, 0.25
+    g, t, a, b, H = _inputs(sg, "AC", nside, None, nt, k0, nf, df, 23)
+    npix = g.shape[1]
+    f = freqs(F0, df, k0, nf)
+    gh, th = g.cpu().numpy().astype(np.float64), t.cpu().numpy()
+    rng = np.random.default_rng(8)
+    P = np.zeros(npix)
+    P[rng.choice(npix, 4, replace=False)] = rng.uniform(0.5, 2.0, 4)
+    C = np.zeros((nt, nf), dtype=np.complex128)
+    for p in np.nonzero(P)[0]:
+        synth.add_point_source(C, f, P[p], gh[:, p], th[:, p])
+    ad, bd, Hd = (torch.from_numpy(x).cuda() for x in (a, b, H))
+    w = (ad[:, None] * bd[None, :]).contiguous()
+    Cd = torch.from_numpy(C.astype(np.complex64)).cuda()
+    X, Gk = sg.make_maps(Cd, w, sg.FGrid(F0, df), k0, g, t, antipodal=False)
+    Xbb, _ = sg.reduce_band(X, Gk, Hd, 0, nf)
+    G = sg.fisher_full(ad, bd, Hd, sg.FGrid(F0, df), k0, 0, nf, g, t)
+    torch.cuda.synchronize()
+    lhs = Xbb.double().cpu().numpy()
+    rhs = G.double().cpu().numpy() @ P
+    assert np.max(np.abs(lhs - rhs)) <= 1e-4 * np.max(np.abs(lhs))
+
+
+@pytest.mark.parametrize("n,niter", [(48, 10), (300, 25), (1000, 12), (5, 0)])
+def test_clean_map_cg_vs_oracle(sg, oracle_mod, n, niter):
+    rng = np.random.default_rng(n)
+    M = rng.standard_normal((n, n + 7))
+    A = (M @ M.T / n + 0.05 * np.eye(n)).astype(np.float32)
+    A = np.triu(A) + np.triu(A, 1).T  # exactly symmetric in float32
+    X = rng.standard_normal(n).astype(np.float32)
+    P = sg.clean_map_cg(torch.from_numpy(A).cuda(), torch.from_numpy(X).cuda(), niter)
+    torch.cuda.synchronize()
+    Pg = P.double().cpu().numpy()
+    Po = oracle_mod.cg(A.astype(np.float64), X.astype(np.float64), niter)
+    if niter == 0:
+        assert np.all(Pg == 0.0)
+        return
+    assert np.linalg.norm(Pg - Po) <= 1e-6 * np.linalg.norm(Po)
+
+
+def test_clean_map_cg_on_the_fisher_matrix(sg, oracle_mod):
+    """CG on the GPU's own (singular, semi-definite) full Fisher matrix with a
+    dirty map in its range, X = G P for a few point sources: same iterate as the
+    oracle's CG on the same matrix (15 steps: rounding differences between two
+    float64 CGs stay near 1e-13 there and grow past 20 steps on this matrix), and
+    the residual falls."""
+    nt, nside, k0, nf, df = 40, 4, 100, 64, 0.25
+    g, t, a, b, H = _inputs(sg, "AB", nside, None, nt, k0, nf, df, 24)
+    ad, bd, Hd = (torch.from_numpy(x).cuda() for x in (a, b, H))
+    G = sg.fisher_full(ad, bd, Hd, sg.FGrid(F0, df), k0, 0, nf, g, t)
+    torch.cuda.synchronize()
+    Gh = G.double().cpu().numpy()
+    rng = np.random.default_rng(8)
+    Pin = np.zeros(Gh.shape[0])
+    Pin[rng.choice(Gh.shape[0], 4, replace=False)] = rng.uniform(0.5, 2.0, 4)
+    Xh = (Gh @ Pin).astype(np.float32)
+    P = sg.clean_map_cg(G, torch.from_numpy(Xh).cuda(), 15)
+    torch.cuda.synchronize()
+    Pg = P.double().cpu().numpy()
+    Po = oracle_mod.cg(Gh, Xh.astype(np.float64), 15)
+    assert np.linalg.norm(Pg - Po) <= 1e-6 * np.linalg.norm(Po)
+    assert np.linalg.norm(Gh @ Pg - Xh) <= 0.05 * np.linalg.norm(Xh)
