@@ -215,17 +215,19 @@ int sgwb_fisher_overlap(const float *v, const float *u, const float *w, int64_t 
  * pairing: every pixel is a row and a column).  0 <= clo < chi <= nf.
  * Output: G float32 [npix][npix] row-major, symmetric (overwritten).
  * Arithmetic: Wd and its derivative tabulated once per call in float64 on 64
- * points per period of the highest band frequency over |D| <= 4 R_earth / c
- * and stored as float32; each (t, p, q) term interpolates the table (cubic
- * Hermite, relative error < 2.4e-7 of sum |H b|), with D formed in float64;
- * float32 accumulation over t.  Delays beyond the Earth bound clamp to the
- * table's ends.
- * Workspace: at least sgwb_fisher_full_workspace_size() bytes, 256-byte
- * aligned, owned by the caller.
- * Errors: SGWB_EINVAL (null pointer, nt/nf/npix < 1, band out of range, bad
- * grid, misaligned pointer, more than 2^31 - 1 matrix tiles), SGWB_ENOMEM
- * (workspace too small).                                                     */
-size_t sgwb_fisher_full_workspace_size(const sgwb_fgrid *fg /*host*/, int64_t k0, int32_t chi);
+ * points per period of the highest band frequency over 0 <= D <= 4 R_earth / c,
+ * turned into the float32 cubic Hermite interpolant of each interval (relative
+ * error < 2.4e-7 of sum |H b|); delays enter as 32-bit fixed-point table
+ * coordinates (resolution 2^-17 of a table step below 3 kHz, 2^-14 at the
+ * 24 kHz limit), so tau_p - tau_q is exact and G exactly symmetric; float32
+ * accumulation over t.  Delays are clamped to |tau| <= 2 R_earth / c.
+ * Workspace: at least sgwb_fisher_full_workspace_size() bytes (0 for
+ * arguments out of range), 256-byte aligned, owned by the caller.
+ * Errors: SGWB_EINVAL (null pointer, nt/nf/npix < 1, band out of range or
+ * reaching above 24 kHz, bad grid, misaligned pointer, more than 2^31 - 1
+ * matrix tiles), SGWB_ENOMEM (workspace too small).                          */
+size_t sgwb_fisher_full_workspace_size(const sgwb_fgrid *fg /*host*/, int64_t k0, int32_t chi, int32_t nt,
+                                       int32_t npix);
 int sgwb_fisher_full(const float *a, const float *b, const float *H, int32_t nf, const sgwb_fgrid *fg /*host*/,
                      int64_t k0, int32_t clo, int32_t chi, const float *gamma, const double *tau, int32_t nt,
                      int32_t npix, float *G, void *workspace, size_t workspace_bytes, hipStream_t stream);

@@ -93,7 +93,7 @@ _SIGNATURES = {
     "sgwb_fisher_overlap_workspace_size": ([_I32, _I32, _I32, ctypes.c_uint32], ctypes.c_size_t),
     "sgwb_fisher_overlap": ([_VP, _VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
                              ctypes.c_uint32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
-    "sgwb_fisher_full_workspace_size": ([ctypes.POINTER(_FGrid), _I64, _I32], ctypes.c_size_t),
+    "sgwb_fisher_full_workspace_size": ([ctypes.POINTER(_FGrid), _I64, _I32, _I32, _I32], ctypes.c_size_t),
     "sgwb_fisher_full": ([_VP, _VP, _VP, _I32, ctypes.POINTER(_FGrid), _I64, _I32, _I32, _VP, _VP, _I32, _I32, _VP,
                           _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_clean_map_workspace_size": ([_I32], ctypes.c_size_t),
@@ -413,9 +413,9 @@ def fisher_overlap(v: torch.Tensor, u: torch.Tensor, wn: torch.Tensor, fgrid: FG
     return G
 
 
-def fisher_full_workspace_bytes(fgrid: FGrid, k0: int, khi: int) -> int:
+def fisher_full_workspace_bytes(fgrid: FGrid, k0: int, khi: int, nt: int, npix: int) -> int:
     fg = _FGrid(float(fgrid.f0), float(fgrid.df))
-    return int(lib().sgwb_fisher_full_workspace_size(ctypes.byref(fg), int(k0), int(khi)))
+    return int(lib().sgwb_fisher_full_workspace_size(ctypes.byref(fg), int(k0), int(khi), int(nt), int(npix)))
 
 
 def fisher_full(a: torch.Tensor, b: torch.Tensor, H: torch.Tensor, fgrid: FGrid, k0: int, klo: int, khi: int,
@@ -439,7 +439,7 @@ def fisher_full(a: torch.Tensor, b: torch.Tensor, H: torch.Tensor, fgrid: FGrid,
     fg = _FGrid(float(fgrid.f0), float(fgrid.df))
     with torch.cuda.device(dev):
         if workspace is None:
-            need = fisher_full_workspace_bytes(fgrid, k0, khi) if 0 < khi else 0
+            need = fisher_full_workspace_bytes(fgrid, k0, khi, nt, npix)
             workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
         wsz = workspace.numel() * workspace.element_size()
         rc = lib().sgwb_fisher_full(_ptr(a), _ptr(b), _ptr(H), nf, ctypes.byref(fg), int(k0), int(klo), int(khi),

@@ -333,11 +333,14 @@ int sgwb_contract_pixels(const float *M, int32_t nf, int32_t npix, const int32_t
     return check_hip(launch_contract(M, nf, npix, pix, pix ? nsel : 0, out, stream), "contraction kernel launch");
 }
 
-size_t sgwb_fisher_full_workspace_size(const sgwb_fgrid *fg, int64_t k0, int32_t chi)
+size_t sgwb_fisher_full_workspace_size(const sgwb_fgrid *fg, int64_t k0, int32_t chi, int32_t nt, int32_t npix)
 {
-    if (!fg || !std::isfinite(fg->f0_hz) || !std::isfinite(fg->df_hz) || fg->df_hz <= 0.0 || k0 < 0 || chi < 1)
+    if (!fg || !std::isfinite(fg->f0_hz) || !std::isfinite(fg->df_hz) || fg->df_hz <= 0.0 || k0 < 0 || chi < 1 ||
+        nt < 1 || npix < 1)
         return 0;
-    return fisher_full_workspace_bytes(fg->f0_hz + (double)(k0 + chi - 1) * fg->df_hz);
+    const double f_max = fg->f0_hz + (double)(k0 + chi - 1) * fg->df_hz;
+    if (!fisher_full_band_ok(f_max)) return 0;
+    return fisher_full_workspace_bytes(f_max, nt, npix);
 }
 
 int sgwb_fisher_full(const float *a, const float *b, const float *H, int32_t nf, const sgwb_fgrid *fg, int64_t k0,
@@ -350,6 +353,8 @@ int sgwb_fisher_full(const float *a, const float *b, const float *H, int32_t nf,
         return set_error(SGWB_EINVAL, "fisher_full: band [%d, %d) not inside [0, %d)", clo, chi, nf);
     if (!std::isfinite(fg->f0_hz) || !std::isfinite(fg->df_hz) || fg->df_hz <= 0.0 || fg->f0_hz < 0.0 || k0 < 0)
         return set_error(SGWB_EINVAL, "fisher_full: bad frequency grid");
+    if (!fisher_full_band_ok(fg->f0_hz + (double)(k0 + chi - 1) * fg->df_hz))
+        return set_error(SGWB_EINVAL, "fisher_full: band reaches above 24 kHz");
     if (((uintptr_t)a % 4) || ((uintptr_t)b % 4) || ((uintptr_t)H % 4) || ((uintptr_t)gamma % 4) ||
         ((uintptr_t)tau % 8) || ((uintptr_t)G % 4))
         return set_error(SGWB_EINVAL, "fisher_full: misaligned pointer");
@@ -357,7 +362,7 @@ int sgwb_fisher_full(const float *a, const float *b, const float *H, int32_t nf,
     if (ntile * (ntile + 1) / 2 > 0x7fffffff) return set_error(SGWB_EINVAL, "fisher_full: npix too large");
     if (!workspace || (uintptr_t)workspace % 256)
         return set_error(SGWB_EINVAL, "fisher_full: workspace null or not 256-byte aligned");
-    const size_t need = sgwb_fisher_full_workspace_size(fg, k0, chi);
+    const size_t need = sgwb_fisher_full_workspace_size(fg, k0, chi, nt, npix);
     if (workspace_bytes < need)
         return set_error(SGWB_ENOMEM, "fisher_full: workspace of %zu bytes needed, %zu given", need, workspace_bytes);
     return check_hip(launch_fisher_full(a, b, H, clo, chi, fg->f0_hz, fg->df_hz, k0, gamma, tau, nt, npix, G,

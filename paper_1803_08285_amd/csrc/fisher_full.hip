@@ -4,31 +4,45 @@
 //   G(p,q) = sum_{k in band} H_k sum_t w(t,k) gamma_p gamma_q cos 2 pi f_k (tau_p - tau_q)
 //          = sum_t a_t gamma_p(t) gamma_q(t) W(tau_p(t) - tau_q(t)),
 //   W(D)   = sum_{k in band} H_k b_k cos 2 pi f_k D.
-// Route (not the paper's): the band sum is done once, into a table of W and
+// Route (not the paper's): the band sum is done once, in float64, into W and
 // its derivative on a grid of delay differences D_j = j delta >= 0 (W is even)
-// with 64 points per period of the band's highest frequency, up to 4 R / c; the
-// matrix then costs one cubic Hermite interpolation per (t, p, q)
-// (relative error below (2 pi / 64)^4 / 384 = 2.4e-7).  Delay differences are
-// taken in float64 before the table index is formed.
+// with 64 points per period of the band's highest frequency, up to 4 R / c, and
+// from those into the cubic Hermite interpolant of each interval (relative
+// error below (2 pi / 64)^4 / 384 = 2.4e-7 of sum |H b|).  Delays become 32-bit
+// fixed-point table coordinates (17 fraction bits below 3 kHz), so a delay
+// difference is an exact integer: its high bits pick the interval, its low
+// bits the position in it, and (p,q) and (q,p) do the same arithmetic.
+#include <cstdlib>
+#include <cstring>
+
 #include "sgwb_internal.h"
 
 namespace sgwb {
 
 constexpr int kFt = 64;      // matrix tile edge
 constexpr int kFtSeg = 16;   // segments staged per step
-constexpr double kTableMaxDelay = 4.0 * kEarthRadius / kLightSpeed;  // |tau_p - tau_q| bound on the Earth
+constexpr int kFracBitsMax = 17;  // fixed-point fraction bits of a delay in table steps
+constexpr int kFracBitsMin = 14;
+constexpr uint32_t kDelayBias = 1u << 30;
+constexpr double kMaxDelay = 2.0 * kEarthRadius / kLightSpeed;  // |tau| bound on the Earth
 
-void fisher_table_geometry(double f_max, double *delta, int32_t *J)
+// Table step, number of intervals J (|tau_p - tau_q| / delta < J - 1) and the
+// fraction bits that keep |tau| / delta 2^fb + 2^30 inside 31 bits.
+void fisher_table_geometry(double f_max, double *delta, int32_t *J, int32_t *fb)
 {
     *delta = 1.0 / (64.0 * std::max(f_max, 1e-3));
-    *J = (int32_t)std::ceil(kTableMaxDelay / *delta) + 2;  // entries 0..J
+    *J = (int32_t)std::ceil(2.0 * kMaxDelay / *delta) + 2;
+    int32_t b = kFracBitsMax;
+    while (b > 0 && (kMaxDelay / *delta + 1.0) * std::ldexp(1.0, b) >= (double)kDelayBias) --b;
+    *fb = b;
 }
 
-// Table entry j: (W(D_j), delta dW/dD (D_j)), phases reduced in float64 at every
-// 64th bin and advanced by a float64 rotation in between.
+// Pass 1, entry j <= J: W(D_j) and delta dW/dD (D_j) in float64, D_j = j delta.
+// Phases are reduced in float64 at every 64th bin and advanced by a float64
+// rotation in between.
 __global__ __launch_bounds__(256) void delay_table_kernel(const float *__restrict__ H, const float *__restrict__ b,
                                                           int32_t clo, int32_t chi, double f0, double df, int64_t k0,
-                                                          double delta, int32_t J, float2 *__restrict__ table)
+                                                          double delta, int32_t J, double2 *__restrict__ wd)
 {
     const int32_t j = blockIdx.x * 256 + threadIdx.x;
     if (j > J) return;
@@ -46,13 +60,40 @@ __global__ __launch_bounds__(256) void delay_table_kernel(const float *__restric
             const double hb = (double)H[c] * (double)b[c];
             const double f = f0 + (double)(k0 + c) * df;
             sw += hb * zr;
-            sd -= hb * 2.0 * M_PI * f * zi;
+            sd -= hb * kTwoPi * f * zi;
             const double nr = zr * er - zi * ei, ni = zr * ei + zi * er;
             zr = nr;
             zi = ni;
         }
     }
-    table[j] = make_float2((float)sw, (float)(sd * delta));
+    wd[j] = make_double2(sw, sd * delta);
+}
+
+// Pass 2, interval j < J: the cubic Hermite interpolant of W on [D_j, D_j+1]
+// written as a polynomial in x = 1 + s, s in [0, 1) the position inside the
+// interval (x is what the assembly kernel builds from the fraction bits).
+__global__ __launch_bounds__(256) void delay_cubic_kernel(const double2 *__restrict__ wd, int32_t J,
+                                                          float4 *__restrict__ cub)
+{
+    const int32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= J) return;
+    const double2 a = wd[j], b = wd[j + 1];
+    // polynomial in s
+    const double c0 = a.x, c1 = a.y, c2 = 3.0 * (b.x - a.x) - 2.0 * a.y - b.y, c3 = 2.0 * (a.x - b.x) + a.y + b.y;
+    // re-expanded around s = x - 1
+    cub[j] = make_float4((float)(c0 - c1 + c2 - c3), (float)(c1 - 2.0 * c2 + 3.0 * c3), (float)(c2 - 3.0 * c3),
+                         (float)c3);
+}
+
+// Delays as biased fixed-point table coordinates: U = round(tau / delta 2^fb) + 2^30,
+// tau clamped to the Earth bound, so that |U_p - U_q| >> fb < J - 1.
+__global__ __launch_bounds__(256) void fixed_delay_kernel(const double *__restrict__ tau, int64_t n, double scale,
+                                                          uint32_t *__restrict__ U)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double t = fmin(fmax(tau[i], -kMaxDelay), kMaxDelay);
+    U[i] = (uint32_t)((int64_t)llrint(t * scale) + (int64_t)kDelayBias);
 }
 
 // Upper-triangle tile k of an n x n tile grid: row r, column c >= r.
@@ -66,19 +107,30 @@ __device__ __forceinline__ void tri_tile(int64_t k, int64_t n, int64_t &r, int64
     c = r + (k - start(r));
 }
 
-__global__ __launch_bounds__(256) void fisher_full_kernel(const float *__restrict__ a, const float *__restrict__ gamma,
-                                                          const double *__restrict__ tau, int32_t nt, int32_t npix,
-                                                          const float2 *__restrict__ table, int32_t J, double inv_delta,
+__device__ __forceinline__ uint32_t abs_diff(uint32_t x, uint32_t y)
+{
+    uint32_t d;
+    asm("v_sad_u32 %0, %1, %2, 0" : "=v"(d) : "v"(x), "v"(y));
+    return d;
+}
+
+// G tile (r, c) of the upper triangle; 256 threads, 4 x 4 entries each.  Per
+// (t, p, q): |U_p - U_q| gives the table interval (high bits) and the position
+// in it (low fb bits, placed in the mantissa of x in [1, 2)); three FMAs
+// evaluate the cubic, two more weight and accumulate it.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void fisher_full_kernel(const float *__restrict__ a, const float *__restrict__ gamma,
+                                                          const uint32_t *__restrict__ U, int32_t nt, int32_t npix,
+                                                          const float4 *__restrict__ cub, int32_t fb,
                                                           float *__restrict__ G)
 {
     __shared__ float gP[kFtSeg][kFt], gQ[kFtSeg][kFt];
-    __shared__ double tP[kFtSeg][kFt], tQ[kFtSeg][kFt];
+    __shared__ uint32_t uP[kFtSeg][kFt], uQ[kFtSeg][kFt];
     const int64_t nT = (npix + kFt - 1) / kFt;
     int64_t tr, tc;
     tri_tile(blockIdx.x, nT, tr, tc);
     const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
     float acc[4][4] = {};
-    const int jmax = J - 1;
+    const char *cb = reinterpret_cast<const char *>(cub);
     for (int t0 = 0; t0 < nt; t0 += kFtSeg) {
         __syncthreads();
         for (int e = threadIdx.x; e < kFtSeg * kFt; e += 256) {
@@ -87,30 +139,41 @@ __global__ __launch_bounds__(256) void fisher_full_kernel(const float *__restric
             const bool ok = t < nt;
             const float at = ok ? a[t] : 0.0f;
             gP[tt][i] = ok && p < npix ? at * gamma[(int64_t)t * npix + p] : 0.0f;
-            tP[tt][i] = ok && p < npix ? tau[(int64_t)t * npix + p] : 0.0;
+            uP[tt][i] = ok && p < npix ? U[(int64_t)t * npix + p] : kDelayBias;
             gQ[tt][i] = ok && q < npix ? gamma[(int64_t)t * npix + q] : 0.0f;
-            tQ[tt][i] = ok && q < npix ? tau[(int64_t)t * npix + q] : 0.0;
+            uQ[tt][i] = ok && q < npix ? U[(int64_t)t * npix + q] : kDelayBias;
         }
         __syncthreads();
         const int tn = min(kFtSeg, nt - t0);
         for (int tt = 0; tt < tn; ++tt) {
+            float gp[4], gq[4];
+            uint32_t up[4], uq[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float gp = gP[tt][ty * 4 + i];
-                const double tp = tP[tt][ty * 4 + i];
+                gp[i] = gP[tt][ty * 4 + i];
+                up[i] = uP[tt][ty * 4 + i];
+                gq[i] = gQ[tt][tx * 4 + i];
+                uq[i] = uQ[tt][tx * 4 + i];
+            }
+            // all sixteen table reads in flight before the first is used
+            float4 c[4][4];
+            float x[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
-                    // |D| makes (p,q) and (q,p) the same arithmetic
-                    const double u = fabs(tp - tQ[tt][tx * 4 + jj]) * inv_delta;
-                    const int k = min((int)u, jmax);
-                    const float s = fminf((float)(u - (double)k), 1.0f);
-                    const float2 w0 = table[k], w1 = table[k + 1];
-                    const float s2 = s * s, s3 = s2 * s;
-                    const float W = (2.0f * s3 - 3.0f * s2 + 1.0f) * w0.x + (s3 - 2.0f * s2 + s) * w0.y +
-                                    (3.0f * s2 - 2.0f * s3) * w1.x + (s3 - s2) * w1.y;
-                    acc[i][jj] = fmaf(gp * gQ[tt][tx * 4 + jj], W, acc[i][jj]);
+                    const uint32_t d = abs_diff(up[i], uq[jj]);
+                    c[i][jj] = *reinterpret_cast<const float4 *>(cb + ((size_t)(d >> fb) << 4));
+                    x[i][jj] = __uint_as_float(((d << (23 - fb)) & 0x007fffffu) | 0x3f800000u);
                 }
-            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const float4 cc = c[i][jj];
+                    const float W = fmaf(fmaf(fmaf(cc.w, x[i][jj], cc.z), x[i][jj], cc.y), x[i][jj], cc.x);
+                    acc[i][jj] = fmaf(gp[i] * gq[jj], W, acc[i][jj]);
+                }
         }
     }
 #pragma unroll
@@ -126,12 +189,128 @@ __global__ __launch_bounds__(256) void fisher_full_kernel(const float *__restric
         }
 }
 
-size_t fisher_full_workspace_bytes(double f_max)
+// LDS-resident form: one 512-thread workgroup per compute unit copies the
+// whole cubic table into LDS (up to 10240 intervals = 160 KiB, enough for
+// bands up to 1.88 kHz) and then walks the upper-triangle tiles persistently,
+// two at a time (one per 256-thread half, halves independent).  Inputs come
+// from global memory into registers one segment ahead.
+constexpr int kLdsTable = 10240;
+
+__global__ __launch_bounds__(512) void fisher_full_lds_kernel(const float *__restrict__ a,
+                                                               const float *__restrict__ gamma,
+                                                               const uint32_t *__restrict__ U, int32_t nt,
+                                                               int32_t npix, const float4 *__restrict__ cub,
+                                                               int32_t J, int32_t fb, int64_t ntiles,
+                                                               float *__restrict__ G)
+{
+    __shared__ float4 tab[kLdsTable];
+    for (int j = threadIdx.x; j < J; j += 512) tab[j] = cub[j];
+    __syncthreads();
+    const char *tb = reinterpret_cast<const char *>(tab);
+    const int half = threadIdx.x >> 8, lt = threadIdx.x & 255;
+    const int ty = lt / 16, tx = lt % 16;
+    const int64_t nT = (npix + kFt - 1) / kFt;
+    for (int64_t k = (int64_t)blockIdx.x * 2 + half; k < ntiles; k += (int64_t)gridDim.x * 2) {
+        int64_t tr, tc;
+        tri_tile(k, nT, tr, tc);
+        int32_t pi[4], qi[4];
+        bool pv[4], qv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t p = tr * kFt + ty * 4 + i, q = tc * kFt + tx * 4 + i;
+            pv[i] = p < npix;
+            qv[i] = q < npix;
+            pi[i] = (int32_t)(pv[i] ? p : npix - 1);
+            qi[i] = (int32_t)(qv[i] ? q : npix - 1);
+        }
+        float acc[4][4] = {};
+        float gp[4], gq[4];
+        uint32_t up[4], uq[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            gp[i] = pv[i] ? a[0] * gamma[pi[i]] : 0.0f;
+            up[i] = U[pi[i]];
+            gq[i] = qv[i] ? gamma[qi[i]] : 0.0f;
+            uq[i] = U[qi[i]];
+        }
+        for (int t = 0; t < nt; ++t) {
+            // next segment's inputs (the last iteration re-reads segment nt - 1)
+            const int tn = min(t + 1, nt - 1);
+            const int64_t o = (int64_t)tn * npix;
+            const float an = a[tn];
+            float gpn[4], gqn[4];
+            uint32_t upn[4], uqn[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                gpn[i] = gamma[o + pi[i]];
+                upn[i] = U[o + pi[i]];
+                gqn[i] = gamma[o + qi[i]];
+                uqn[i] = U[o + qi[i]];
+            }
+            float4 c[4][4];
+            float x[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const uint32_t d = abs_diff(up[i], uq[jj]);
+                    c[i][jj] = *reinterpret_cast<const float4 *>(tb + ((d >> fb) << 4));
+                    x[i][jj] = __uint_as_float(((d << (23 - fb)) & 0x007fffffu) | 0x3f800000u);
+                }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const float4 cc = c[i][jj];
+                    const float W = fmaf(fmaf(fmaf(cc.w, x[i][jj], cc.z), x[i][jj], cc.y), x[i][jj], cc.x);
+                    acc[i][jj] = fmaf(gp[i] * gq[jj], W, acc[i][jj]);
+                }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                gp[i] = pv[i] ? an * gpn[i] : 0.0f;
+                up[i] = upn[i];
+                gq[i] = qv[i] ? gqn[i] : 0.0f;
+                uq[i] = uqn[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int64_t p = tr * kFt + ty * 4 + i, q = tc * kFt + tx * 4 + jj;
+                if (pv[i] && q < npix && (tr != tc || p <= q)) {
+                    G[p * npix + q] = acc[i][jj];
+                    G[q * npix + p] = acc[i][jj];
+                }
+            }
+    }
+}
+
+bool fisher_full_band_ok(double f_max)
 {
     double delta;
-    int32_t J;
-    fisher_table_geometry(f_max, &delta, &J);
-    return (size_t)(J + 1) * sizeof(float2);
+    int32_t J, fb;
+    fisher_table_geometry(f_max, &delta, &J, &fb);
+    return fb >= kFracBitsMin;
+}
+
+// SGWB_FISHER_TABLE=global keeps the table in global memory (both forms give
+// bitwise the same matrix).
+static bool fisher_full_table_in_lds()
+{
+    const char *e = std::getenv("SGWB_FISHER_TABLE");
+    return !(e && std::strcmp(e, "global") == 0);
+}
+
+static size_t up256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+size_t fisher_full_workspace_bytes(double f_max, int32_t nt, int32_t npix)
+{
+    double delta;
+    int32_t J, fb;
+    fisher_table_geometry(f_max, &delta, &J, &fb);
+    return up256((size_t)(J + 1) * sizeof(double2)) + up256((size_t)J * sizeof(float4)) +
+           up256((size_t)nt * npix * sizeof(uint32_t));
 }
 
 hipError_t launch_fisher_full(const float *a, const float *b, const float *H, int32_t clo, int32_t chi, double f0,
@@ -140,15 +319,35 @@ hipError_t launch_fisher_full(const float *a, const float *b, const float *H, in
 {
     const double f_max = f0 + (double)(k0 + chi - 1) * df;
     double delta;
-    int32_t J;
-    fisher_table_geometry(f_max, &delta, &J);
-    float2 *table = reinterpret_cast<float2 *>(work);
+    int32_t J, fb;
+    fisher_table_geometry(f_max, &delta, &J, &fb);
+    if (fb < kFracBitsMin) return hipErrorInvalidValue;
+    char *w = reinterpret_cast<char *>(work);
+    double2 *wd = reinterpret_cast<double2 *>(w);
+    w += up256((size_t)(J + 1) * sizeof(double2));
+    float4 *cub = reinterpret_cast<float4 *>(w);
+    w += up256((size_t)J * sizeof(float4));
+    uint32_t *U = reinterpret_cast<uint32_t *>(w);
     hipLaunchKernelGGL(delay_table_kernel, dim3((unsigned)((J + 1 + 255) / 256)), dim3(256), 0, s, H, b, clo, chi,
-                       f0, df, k0, delta, J, table);
+                       f0, df, k0, delta, J, wd);
+    hipLaunchKernelGGL(delay_cubic_kernel, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, s, wd, J, cub);
+    const int64_t n = (int64_t)nt * npix;
+    hipLaunchKernelGGL(fixed_delay_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tau, n,
+                       std::ldexp(1.0, fb) / delta, U);
     const int64_t nT = (npix + kFt - 1) / kFt, ntiles = nT * (nT + 1) / 2;
     if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fisher_full_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, a, gamma, tau, nt, npix, table, J,
-                       1.0 / delta, G);
+    if (J <= kLdsTable && fisher_full_table_in_lds()) {
+        int dev = 0, cus = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        const int64_t grid = std::min<int64_t>(cus, (ntiles + 1) / 2);
+        hipLaunchKernelGGL(fisher_full_lds_kernel, dim3((unsigned)grid), dim3(512), 0, s, a, gamma, U, nt, npix,
+                           cub, J, fb, ntiles, G);
+    } else {
+        hipLaunchKernelGGL(fisher_full_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, a, gamma, U, nt, npix, cub,
+                           fb, G);
+    }
     return hipGetLastError();
 }
 

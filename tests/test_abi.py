@@ -144,11 +144,16 @@ def test_fisher_full_and_clean_map_validation_on_the_host():
     # workspace too small; the table grows with the top frequency of the band
     rc = L.sgwb_fisher_full(d, d, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, d, d, 256, None)
     assert rc == -2
-    low = L.sgwb_fisher_full_workspace_size(ctypes.byref(fg), 0, 10)
-    high = L.sgwb_fisher_full_workspace_size(ctypes.byref(fg), 50000, 10)
-    assert 0 < low < high
+    low = L.sgwb_fisher_full_workspace_size(ctypes.byref(fg), 0, 10, 8, 768)
+    high = L.sgwb_fisher_full_workspace_size(ctypes.byref(fg), 50000, 10, 8, 768)
+    more = L.sgwb_fisher_full_workspace_size(ctypes.byref(fg), 50000, 10, 9, 768)
+    assert 0 < low < high < more
     bad = sg._FGrid(20.0, 0.0)
-    assert L.sgwb_fisher_full_workspace_size(ctypes.byref(bad), 0, 10) == 0
+    assert L.sgwb_fisher_full_workspace_size(ctypes.byref(bad), 0, 10, 8, 768) == 0
+    # the fixed-point delays cover bands up to 24 kHz
+    assert L.sgwb_fisher_full_workspace_size(ctypes.byref(fg), 32 * 30000, 10, 8, 768) == 0
+    rc = L.sgwb_fisher_full(d, d, d, 10, ctypes.byref(fg), 32 * 30000, 0, 10, d, d, 8, 768, d, d, big, None)
+    assert rc == -1 and b"24 kHz" in L.sgwb_last_error()
     # clean map
     rc = L.sgwb_clean_map_cg(d, d, 0, 5, d, d, big, None)
     assert rc == -1
