@@ -223,6 +223,65 @@ def bench_fisher_overlap(args, torch, sg):
                       "plain_diagonal_ms": t_plain}), flush=True)
 
 
+PEAK_LDS_TBPS = 256 * 128 * 2.4e9 / 1e12  # 256 CUs x 128 B/clk of LDS reads x 2.4 GHz
+FISHER_TABLE_BYTES_PER_TERM = 16          # one float4 cubic per (t, p, q) term
+
+
+def bench_fisher_full(args, torch, sg):
+    """Full Fisher matrix of the whole band (Eq. eq_fisher, separable weights) and
+    --cg-iters conjugate-gradient steps towards the clean map, for one folded day
+    of --workload; the dirty map comes from make_maps + reduce_band (untimed)."""
+    dev = torch.device("cuda:0")
+    wl = synth.workload(args.workload)
+    tg, fgd = wl.tgrid, wl.fgrid
+    npix = 12 * wl.nside ** 2
+    inp = make_inputs(sg, torch, wl, dev)
+    f = fgd.freqs()
+    a = torch.from_numpy(synth.segment_scale(tg.nt, wl.nonstationary_seed).astype(np.float32)).to(dev)
+    b = torch.from_numpy((synth.spectrum_H(f) / synth.noise_psd(f) ** 2).astype(np.float32)).to(dev)
+    fg = sg.FGrid(fgd.f0, fgd.df)
+    X, Gk = sg.make_maps(inp["C"], inp["w"], fg, fgd.k0, inp["gamma"], inp["tau"], antipodal=True)
+    Xbb, _ = sg.reduce_band(X, Gk, inp["H"], 0, fgd.nf)
+    del X, Gk
+    G = torch.empty((npix, npix), dtype=torch.float32, device=dev)
+    ws = torch.empty(sg.fisher_full_workspace_bytes(fg, fgd.k0, fgd.nf, tg.nt, npix), dtype=torch.uint8, device=dev)
+    P = torch.empty(npix, dtype=torch.float32, device=dev)
+
+    def full():
+        sg.fisher_full(a, b, inp["H"], fg, fgd.k0, 0, fgd.nf, inp["gamma"], inp["tau"], out=G, workspace=ws)
+
+    def clean():
+        sg.clean_map_cg(G, Xbb, args.cg_iters, out=P)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    t_full = timed(full, args.steps)
+    t_cg = timed(clean, args.steps)
+    resid = float(torch.linalg.norm(G.double() @ P.double() - Xbb.double()) / torch.linalg.norm(Xbb.double()))
+    terms = tg.nt * npix * (npix + 1) // 2
+    tbps = terms * FISHER_TABLE_BYTES_PER_TERM / (t_full * 1e-3) / 1e12
+    log(f"full Fisher matrix {npix}^2 over {tg.nt} segments: {t_full:.2f} ms; CG x{args.cg_iters}: {t_cg:.2f} ms; "
+        f"relative residual {resid:.3e}")
+    print(json.dumps({"metric": "full Fisher matrix pair-terms/s (t*p*q, q>=p)", "value": terms / (t_full * 1e-3),
+                      "unit": "terms/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": t_full,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                      "data": "synthetic", "config": {"workload": wl.name + "_fisher_full", "nt": tg.nt,
+                                                      "nf": fgd.nf, "npix": npix, "parallelism": "single GPU"},
+                      "roofline": {"bound": "lds", "achieved": tbps * 1e3, "peak": PEAK_LDS_TBPS * 1e3,
+                                   "unit": "GB/s", "frac": tbps / PEAK_LDS_TBPS, "traffic": None},
+                      "clean_map": {"cg_iters": args.cg_iters, "ms": t_cg, "relative_residual": resid}}),
+          flush=True)
+
+
 def bench_folded(args, torch, sg):
     """Folded pipeline over --days synthetic sidereal days of the full band: fold
     (v, u, w, x), dirty map of x, overlap-corrected Fisher diagonal, band sums."""
@@ -408,6 +467,9 @@ def main():
     ap.add_argument("--days", type=int, default=10)
     ap.add_argument("--fisher-overlap", action="store_true",
                     help="overlap-corrected Fisher diagonal over the full band of --workload")
+    ap.add_argument("--fisher-full", action="store_true",
+                    help="full Fisher matrix of the whole band and the CG clean map for --workload")
+    ap.add_argument("--cg-iters", type=int, default=50)
     ap.add_argument("--rates", type=float, nargs="+", default=[25.0, 50.0, 100.0, 200.0])
     ap.add_argument("--duration", type=float, default=5.0)
     ap.add_argument("--slots", type=int, default=4)
@@ -437,6 +499,9 @@ def main():
         return
     if args.folded:
         bench_folded(args, torch, sg)
+        return
+    if args.fisher_full:
+        bench_fisher_full(args, torch, sg)
         return
     wl = synth.workload(args.workload)
     tg, fgd = wl.tgrid, wl.fgrid

@@ -340,7 +340,7 @@ size_t sgwb_fisher_full_workspace_size(const sgwb_fgrid *fg, int64_t k0, int32_t
         return 0;
     const double f_max = fg->f0_hz + (double)(k0 + chi - 1) * fg->df_hz;
     if (!fisher_full_band_ok(f_max)) return 0;
-    return fisher_full_workspace_bytes(f_max, nt, npix);
+    return fisher_full_workspace_bytes(f_max, chi, nt, npix);
 }
 
 int sgwb_fisher_full(const float *a, const float *b, const float *H, int32_t nf, const sgwb_fgrid *fg, int64_t k0,

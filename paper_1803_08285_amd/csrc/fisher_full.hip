@@ -37,47 +37,63 @@ void fisher_table_geometry(double f_max, double *delta, int32_t *J, int32_t *fb)
     *fb = b;
 }
 
-// Pass 1, entry j <= J: W(D_j) and delta dW/dD (D_j) in float64, D_j = j delta.
-// Phases are reduced in float64 at every 64th bin and advanced by a float64
-// rotation in between.
+// Pass 1, entry j <= J and one chunk of kTabChunk bins: the chunk's share of
+// W(D_j) and delta dW/dD (D_j) in float64, D_j = j delta.  Phases are reduced
+// in float64 at every 64th bin and advanced by a float64 rotation in between.
+constexpr int kTabChunk = 2048;
+
 __global__ __launch_bounds__(256) void delay_table_kernel(const float *__restrict__ H, const float *__restrict__ b,
                                                           int32_t clo, int32_t chi, double f0, double df, int64_t k0,
-                                                          double delta, int32_t J, double2 *__restrict__ wd)
+                                                          double delta, int32_t J, double2 *__restrict__ part)
 {
+    __shared__ double hb[kTabChunk], hbf[kTabChunk];
+    const int32_t cb = clo + (int32_t)blockIdx.y * kTabChunk, ce = min(cb + kTabChunk, chi);
+    for (int32_t c = cb + threadIdx.x; c < ce; c += 256) {
+        const double h = (double)H[c] * (double)b[c];
+        hb[c - cb] = h;
+        hbf[c - cb] = h * kTwoPi * (f0 + (double)(k0 + c) * df);
+    }
+    __syncthreads();
     const int32_t j = blockIdx.x * 256 + threadIdx.x;
     if (j > J) return;
     const double D = (double)j * delta;
     double er, ei;
     sincospi(2.0 * df * D, &ei, &er);
     double sw = 0.0, sd = 0.0;
-    for (int32_t c0 = clo; c0 < chi; c0 += 64) {
+    for (int32_t c0 = cb; c0 < ce; c0 += 64) {
         const double fa = f0 + (double)(k0 + c0) * df;
         const double x = fa * D, r = x - rint(x);
         double zr, zi;
         sincospi(2.0 * r, &zi, &zr);
-        const int32_t c1 = min(c0 + 64, chi);
+        const int32_t c1 = min(c0 + 64, ce);
         for (int32_t c = c0; c < c1; ++c) {
-            const double hb = (double)H[c] * (double)b[c];
-            const double f = f0 + (double)(k0 + c) * df;
-            sw += hb * zr;
-            sd -= hb * kTwoPi * f * zi;
+            sw += hb[c - cb] * zr;
+            sd -= hbf[c - cb] * zi;
             const double nr = zr * er - zi * ei, ni = zr * ei + zi * er;
             zr = nr;
             zi = ni;
         }
     }
-    wd[j] = make_double2(sw, sd * delta);
+    part[(size_t)blockIdx.y * (J + 1) + j] = make_double2(sw, sd * delta);
 }
 
-// Pass 2, interval j < J: the cubic Hermite interpolant of W on [D_j, D_j+1]
-// written as a polynomial in x = 1 + s, s in [0, 1) the position inside the
-// interval (x is what the assembly kernel builds from the fraction bits).
-__global__ __launch_bounds__(256) void delay_cubic_kernel(const double2 *__restrict__ wd, int32_t J,
+// Pass 2, interval j < J: the chunk sums at both ends (chunk order fixed), then
+// the cubic Hermite interpolant of W on [D_j, D_j+1] written as a polynomial in
+// x = 1 + s, s in [0, 1) the position inside the interval (x is what the
+// assembly kernel builds from the fraction bits).
+__global__ __launch_bounds__(256) void delay_cubic_kernel(const double2 *__restrict__ part, int32_t nchunk, int32_t J,
                                                           float4 *__restrict__ cub)
 {
     const int32_t j = blockIdx.x * 256 + threadIdx.x;
     if (j >= J) return;
-    const double2 a = wd[j], b = wd[j + 1];
+    double2 a = make_double2(0.0, 0.0), b = a;
+    for (int32_t q = 0; q < nchunk; ++q) {
+        const double2 u = part[(size_t)q * (J + 1) + j], v = part[(size_t)q * (J + 1) + j + 1];
+        a.x += u.x;
+        a.y += u.y;
+        b.x += v.x;
+        b.y += v.y;
+    }
     // polynomial in s
     const double c0 = a.x, c1 = a.y, c2 = 3.0 * (b.x - a.x) - 2.0 * a.y - b.y, c3 = 2.0 * (a.x - b.x) + a.y + b.y;
     // re-expanded around s = x - 1
@@ -304,12 +320,14 @@ static bool fisher_full_table_in_lds()
 
 static size_t up256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-size_t fisher_full_workspace_bytes(double f_max, int32_t nt, int32_t npix)
+// nbins bounds the band width (the chunk count of the table pass).
+size_t fisher_full_workspace_bytes(double f_max, int32_t nbins, int32_t nt, int32_t npix)
 {
     double delta;
     int32_t J, fb;
     fisher_table_geometry(f_max, &delta, &J, &fb);
-    return up256((size_t)(J + 1) * sizeof(double2)) + up256((size_t)J * sizeof(float4)) +
+    const size_t nchunk = ((size_t)nbins + kTabChunk - 1) / kTabChunk;
+    return up256(nchunk * (J + 1) * sizeof(double2)) + up256((size_t)J * sizeof(float4)) +
            up256((size_t)nt * npix * sizeof(uint32_t));
 }
 
@@ -322,15 +340,17 @@ hipError_t launch_fisher_full(const float *a, const float *b, const float *H, in
     int32_t J, fb;
     fisher_table_geometry(f_max, &delta, &J, &fb);
     if (fb < kFracBitsMin) return hipErrorInvalidValue;
+    const int32_t nchunk = (chi - clo + kTabChunk - 1) / kTabChunk;
+    if (nchunk > 65535) return hipErrorInvalidValue;
     char *w = reinterpret_cast<char *>(work);
-    double2 *wd = reinterpret_cast<double2 *>(w);
-    w += up256((size_t)(J + 1) * sizeof(double2));
+    double2 *part = reinterpret_cast<double2 *>(w);
+    w += up256((size_t)nchunk * (J + 1) * sizeof(double2));
     float4 *cub = reinterpret_cast<float4 *>(w);
     w += up256((size_t)J * sizeof(float4));
     uint32_t *U = reinterpret_cast<uint32_t *>(w);
-    hipLaunchKernelGGL(delay_table_kernel, dim3((unsigned)((J + 1 + 255) / 256)), dim3(256), 0, s, H, b, clo, chi,
-                       f0, df, k0, delta, J, wd);
-    hipLaunchKernelGGL(delay_cubic_kernel, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, s, wd, J, cub);
+    hipLaunchKernelGGL(delay_table_kernel, dim3((unsigned)((J + 1 + 255) / 256), (unsigned)nchunk), dim3(256), 0, s,
+                       H, b, clo, chi, f0, df, k0, delta, J, part);
+    hipLaunchKernelGGL(delay_cubic_kernel, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, s, part, nchunk, J, cub);
     const int64_t n = (int64_t)nt * npix;
     hipLaunchKernelGGL(fixed_delay_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tau, n,
                        std::ldexp(1.0, fb) / delta, U);
@@ -354,20 +374,50 @@ hipError_t launch_fisher_full(const float *a, const float *b, const float *H, in
 // ---- conjugate gradient on G P = X (float64 vectors, fixed-order sums) ----
 constexpr int kCgParts = 256;
 
+// q = G p for kCgRows rows per workgroup: each p[j] is read once for all of
+// them; per-thread partial sums over a fixed column stride, then a fixed tree.
+// VEC: four consecutive columns per load (n % 4 == 0, G 16-byte aligned).
+constexpr int kCgRows = 4;
+
+template <bool VEC>
 __global__ __launch_bounds__(256) void cg_matvec_kernel(const float *__restrict__ G, const double *__restrict__ p,
                                                         int32_t n, double *__restrict__ q)
 {
-    __shared__ double red[256];
-    const float *row = G + (int64_t)blockIdx.x * n;
-    double acc = 0.0;
-    for (int32_t j = threadIdx.x; j < n; j += 256) acc += (double)row[j] * p[j];
-    red[threadIdx.x] = acc;
+    __shared__ double red[kCgRows][256];
+    const int64_t r0 = (int64_t)blockIdx.x * kCgRows;
+    const int nr = (int)min<int64_t>(kCgRows, n - r0);
+    const float *row[kCgRows];
+#pragma unroll
+    for (int r = 0; r < kCgRows; ++r) row[r] = G + (r0 + min(r, nr - 1)) * n;  // tail rows repeat the last
+    double acc[kCgRows] = {};
+    if (VEC) {
+        const int32_t n4 = n / 4;
+        for (int32_t j4 = threadIdx.x; j4 < n4; j4 += 256) {
+            const double2 pa = reinterpret_cast<const double2 *>(p)[2 * j4];
+            const double2 pb = reinterpret_cast<const double2 *>(p)[2 * j4 + 1];
+#pragma unroll
+            for (int r = 0; r < kCgRows; ++r) {
+                const float4 g = reinterpret_cast<const float4 *>(row[r])[j4];
+                acc[r] += (double)g.x * pa.x + (double)g.y * pa.y + (double)g.z * pb.x + (double)g.w * pb.y;
+            }
+        }
+    } else {
+        for (int32_t j = threadIdx.x; j < n; j += 256) {
+            const double pj = p[j];
+#pragma unroll
+            for (int r = 0; r < kCgRows; ++r) acc[r] += (double)row[r][j] * pj;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kCgRows; ++r) red[r][threadIdx.x] = acc[r];
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        if ((int)threadIdx.x < st)
+#pragma unroll
+            for (int r = 0; r < kCgRows; ++r) red[r][threadIdx.x] += red[r][threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) q[blockIdx.x] = red[0];
+    if ((int)threadIdx.x < nr) q[r0 + threadIdx.x] = red[threadIdx.x][0];
 }
 
 __global__ __launch_bounds__(256) void cg_dot_kernel(const double *__restrict__ x, const double *__restrict__ y,
@@ -448,12 +498,17 @@ hipError_t launch_clean_map_cg(const float *G, const float *X, int32_t n, int32_
     double *x = reinterpret_cast<double *>(work), *r = x + n, *p = r + n, *q = p + n, *part = q + n;
     double *sc = part + kCgParts;  // sc[0], sc[1]: |r|^2 of even/odd iterations; sc[2]: p.q
     const unsigned g = (unsigned)((n + 255) / 256);
+    const unsigned mg = (unsigned)((n + kCgRows - 1) / kCgRows);
+    const bool vec = n % 4 == 0 && reinterpret_cast<uintptr_t>(G) % 16 == 0;
     hipLaunchKernelGGL(cg_init_kernel, dim3(g), dim3(256), 0, s, X, n, x, r, p);
     hipLaunchKernelGGL(cg_dot_kernel, dim3(kCgParts), dim3(256), 0, s, r, r, n, part);
     hipLaunchKernelGGL(cg_dot_final_kernel, dim3(1), dim3(256), 0, s, part, sc);
     for (int32_t it = 0; it < niter; ++it) {
         double *rr = sc + (it & 1), *rr_new = sc + ((it + 1) & 1);
-        hipLaunchKernelGGL(cg_matvec_kernel, dim3((unsigned)n), dim3(256), 0, s, G, p, n, q);
+        if (vec)
+            hipLaunchKernelGGL(cg_matvec_kernel<true>, dim3(mg), dim3(256), 0, s, G, p, n, q);
+        else
+            hipLaunchKernelGGL(cg_matvec_kernel<false>, dim3(mg), dim3(256), 0, s, G, p, n, q);
         hipLaunchKernelGGL(cg_dot_kernel, dim3(kCgParts), dim3(256), 0, s, p, q, n, part);
         hipLaunchKernelGGL(cg_dot_final_kernel, dim3(1), dim3(256), 0, s, part, sc + 2);
         hipLaunchKernelGGL(cg_step_kernel, dim3(g), dim3(256), 0, s, x, r, p, q, rr, sc + 2, n);

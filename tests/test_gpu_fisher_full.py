@@ -119,7 +119,7 @@ def test_noise_free_sky_gives_x_equal_g_p(sg):
     assert np.max(np.abs(lhs - rhs)) <= 1e-4 * np.max(np.abs(lhs))
 
 
-@pytest.mark.parametrize("n,niter", [(48, 10), (300, 25), (1000, 12), (5, 0)])
+@pytest.mark.parametrize("n,niter", [(48, 10), (300, 25), (1000, 12), (333, 10), (7, 5), (5, 0)])
 def test_clean_map_cg_vs_oracle(sg, oracle_mod, n, niter):
     rng = np.random.default_rng(n)
     M = rng.standard_normal((n, n + 7))
