@@ -27,6 +27,8 @@ CASES = [  # baseline, nside, npix used (None: all), nt, k0, nf, band, df
     ("BC", 4, 150, 33, 0, 30, (0, 30), 1.0),            # ragged multi-tile (150 = 2 x 64 + 22)
     ("AB", 8, None, 60, 53000, 64, (0, 64), 1 / 32),    # top of the band (1.68 kHz), 12 x 12 tiles
     ("AC", 2, None, 7, 63, 2, (1, 2), 0.25),            # single bin, tiny day
+    ("AB", 4, 100, 30, 79000, 40, (0, 40), 1 / 32),     # 2.49 kHz: table above the LDS size, global-memory form
+    ("BC", 2, None, 20, 39000, 50, (3, 47), 0.125),     # 4.9 kHz: 16 fraction bits
 ]
 
 
@@ -158,3 +160,19 @@ def test_clean_map_cg_on_the_fisher_matrix(sg, oracle_mod):
     Po = oracle_mod.cg(Gh, Xh.astype(np.float64), 15)
     assert np.linalg.norm(Pg - Po) <= 1e-6 * np.linalg.norm(Po)
     assert np.linalg.norm(Gh @ Pg - Xh) <= 0.05 * np.linalg.norm(Xh)
+
+
+def test_fisher_full_and_clean_map_are_deterministic(sg):
+    """Fixed summation orders: a second call gives the same bits (the table's chunk
+    sums, the persistent tile walk and the CG reductions are order-fixed)."""
+    nt, nside, k0, nf, df = 36, 8, 500, 300, 1 / 32
+    g, t, a, b, H = _inputs(sg, "AC", nside, None, nt, k0, nf, df, 25)
+    ad, bd, Hd = (torch.from_numpy(x).cuda() for x in (a, b, H))
+    G1 = sg.fisher_full(ad, bd, Hd, sg.FGrid(F0, df), k0, 0, nf, g, t)
+    G2 = sg.fisher_full(ad, bd, Hd, sg.FGrid(F0, df), k0, 0, nf, g, t)
+    X = torch.diagonal(G1).contiguous()
+    P1 = sg.clean_map_cg(G1, X, 20)
+    P2 = sg.clean_map_cg(G2, X, 20)
+    torch.cuda.synchronize()
+    assert torch.equal(G1, G2)
+    assert torch.equal(P1, P2)
