@@ -28,7 +28,12 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X published fp32 vector peak
 PEAK_F16_MFMA_TFLOPS = 2500.0    # MI355X published dense fp16/bf16 matrix peak
 X_FLOPS_PER_TERM = 10            # algorithmic: rotation 6 + Re(y z) accumulation 4 (vector form);
                                  # the matrix form's 5-term contraction is also 10 flops per term
-X_MFMA_ISSUED_PER_TERM = 22      # matrix form as issued: 11 f16 products (hi/lo splits) x 2 flops
+# Matrix form as issued, f16 products per term per component x 2 flops: the form
+# follows the largest |eta| = 2 pi 31.5 df max|tau| of the seeds (four terms up
+# to 0.07: 8 products; five terms with m = 2 unsplit up to 0.17: 9; else 11).
+def x_mfma_issued_per_term(eta: float) -> int:
+    return 2 * (8 if eta <= 0.07 else 9 if eta <= 0.17 else 11)
+
 CPU_BASELINE_TARGET_S = 15.0
 # Sources of the matrix-core dirty-map kernel: a recorded HBM traffic figure is
 # reported only while these are unchanged since the counters were taken.
@@ -549,13 +554,14 @@ def main():
     terms = tg.nt * fgd.nf * npix
     x_tflops = X_FLOPS_PER_TERM * terms / (t_x.mean() * 1e-3) / 1e12
     matrix_form = fgd.df * 2 * 6.371e6 / 299792458.0 * 2 * np.pi * 31.5 <= 0.29  # where make_maps uses MFMA
+    eta = 2 * np.pi * 31.5 * fgd.df * float(inp["tau"].abs().max())
     if matrix_form:
         rec = recorded_traffic(wl.name)
         roofline = {"bound": "mfma", "kernel": "xm_main_kernel (f16 MFMA dirty map)", "achieved": x_tflops,
                     "peak": PEAK_F16_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": x_tflops / PEAK_F16_MFMA_TFLOPS,
                     "traffic": rec["hbm_bytes"] if rec else None, "flops_per_term": X_FLOPS_PER_TERM,
                     "launch_ms": float(t_x.mean()),
-                    "issued_tflops": X_MFMA_ISSUED_PER_TERM * terms / (t_x.mean() * 1e-3) / 1e12,
+                    "issued_tflops": x_mfma_issued_per_term(eta) * terms / (t_x.mean() * 1e-3) / 1e12,
                     "frac_vs_fp32_vector_peak": x_tflops / PEAK_FP32_VECTOR_TFLOPS}
         if rec:
             roofline["traffic_algorithmic_bytes"] = rec["algorithmic_bytes"]
