@@ -80,11 +80,9 @@ __global__ __launch_bounds__(256) void prep_frag_kernel(const float *__restrict_
     dst[frag_index(blk, ks, 1, lane, fd.nks)] = lo;
 }
 
-// Each wave computes a (WM x 32) x (WN x 32) tile of Gam; waves are independent
-// and read their operand fragments straight from L2.  The next K-step's
-// fragments are loaded while the current step's MFMAs run, and the three
-// products of a K-step are issued part by part over all WM x WN accumulators so
-// that consecutive MFMAs never depend on each other.
+// The three products of a K-step are issued part by part over all WM x WN
+// accumulators so that consecutive MFMAs never depend on each other.
+
 template <int WM, int WN>
 struct Frags {
     uint4 a[WM][2], b[WN][2];
@@ -132,8 +130,8 @@ __device__ inline bool patch_tile(int64_t b, int w, int64_t tiles_m, int64_t til
     // patches walk the bin direction fastest, so neighbouring patches share pixel tiles
     const int64_t pi = patch % pm, pj = patch / pm;
     *tm = pi * kPatch + in % kPatch;
-    *tn = pj * kPatch + in / kPatch;
-    return *tm < tiles_m && *tn < tiles_n;
+    *tn = pj * kPatch + in / kPatch;  // the same for the four waves of a workgroup
+    return *tn < tiles_n;             // uniform over the workgroup; tm may lie past the last tile
 }
 
 // Number of workgroups that covers every patch in the XCD-striped order.
@@ -145,8 +143,10 @@ __host__ inline int64_t patch_grid(int64_t tiles_m, int64_t tiles_n)
     return per_xcd * kWgPerPatch * kXcds;
 }
 
+// 4 x 4 wave tiles (256 accumulators) leave no registers for staging: each wave
+// reads both operands straight from L2, one K-step ahead in registers.
 template <int WM, int WN>
-__device__ inline void beam_wave_tile(const BJob &jb, int64_t tm, int64_t tn, int lane)
+__device__ inline void beam_wave_tile_direct(const BJob &jb, int64_t tm, int64_t tn, int lane)
 {
     const FragDims fm = jb.fm, fn = jb.fn;
     const int64_t nks = fm.nks;
@@ -198,14 +198,135 @@ __device__ inline void beam_wave_tile(const BJob &jb, int64_t tm, int64_t tn, in
     }
 }
 
+constexpr int kVmcnt0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt left at their maxima
+
+// The pixel-side fragments of one K-step for the workgroup's column tile tn
+// (2 WN fragments of 64 x 16 B: blocks tn WN + j, hi and lo), copied global ->
+// LDS directly; wave w moves fragments w, w + 4, ...  Blocks past the last
+// are clamped to it (their columns are never stored).
+template <int WN>
+__device__ inline void stage_bfrags(const uint4 *__restrict__ Gf, int64_t tn, int64_t ks, const FragDims &fn,
+                                    int wave, int lane, uint4 (*dst)[64])
+{
+#pragma unroll
+    for (int f = wave; f < 2 * WN; f += kWavesPerWg) {
+        const int64_t nb = min(tn * WN + f / 2, fn.nblk - 1);
+        __builtin_amdgcn_global_load_lds(Gf + frag_index(nb, ks, f % 2, lane, fn.nks), &dst[f][0], 16, 0, 0);
+    }
+}
+
+// One wave's (WM x 32) x (WN x 32) tile.  The four waves of a workgroup share
+// the column tile tn (the patch order makes it uniform), so its fragments are
+// staged once per K-step in LDS (two distinct buffers, K loop unrolled by two
+// so that reads of one need not wait for the copy into the other); each wave
+// reads its own bin-side fragments from L2, one K-step ahead in registers.
+// Every wave of the workgroup runs the K loop (it holds barriers): a wave
+// whose bin tile lies past the last block multiplies zero fragments and
+// stores nothing.
+template <int WM, int WN>
+__device__ inline void beam_wave_tile(const BJob &jb, int64_t tm, int64_t tn, int lane, uint4 (*Bs0)[64],
+                                      uint4 (*Bs1)[64])
+{
+    const FragDims fm = jb.fm, fn = jb.fn;
+    const int64_t nks = fm.nks;
+    const int wave = threadIdx.x >> 6;
+    f32x16 acc[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    const uint4 zero4 = make_uint4(0, 0, 0, 0);
+    uint4 a[WM][2], an[WM][2];
+    auto load_a = [&](int64_t ks, uint4 (&d)[WM][2]) {
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            const int64_t mb = tm * WM + i;
+#pragma unroll
+            for (int part = 0; part < 2; ++part)
+                d[i][part] = mb < fm.nblk ? jb.Wf[frag_index(mb, ks, part, lane, fm.nks)] : zero4;
+        }
+    };
+    __syncthreads();  // the previous tile's readers of the buffers are done
+    load_a(0, a);
+    stage_bfrags<WN>(jb.Gf, tn, 0, fn, wave, lane, Bs0);
+    __builtin_amdgcn_s_waitcnt(kVmcnt0);
+    __syncthreads();
+    auto step = [&](int64_t ks, uint4 (*Bcur)[64], uint4 (*Bnext)[64]) {
+        const bool more = ks + 1 < nks;
+        if (more) {
+            stage_bfrags<WN>(jb.Gf, tn, ks + 1, fn, wave, lane, Bnext);
+            load_a(ks + 1, an);
+        }
+        uint4 b[WN][2];
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            b[j][0] = Bcur[2 * j][lane];
+            b[j][1] = Bcur[2 * j + 1][lane];
+        }
+        // lo.hi, then hi.lo, then hi.hi: smallest terms first, fixed order
+#pragma unroll
+        for (int part = 0; part < 3; ++part)
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j) {
+                    const bf16x8 av = __builtin_bit_cast(bf16x8, a[i][part == 0 ? 1 : 0]);
+                    const bf16x8 bv = __builtin_bit_cast(bf16x8, b[j][part == 1 ? 1 : 0]);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[i][j], 0, 0, 0);
+                }
+        if (more) {
+#pragma unroll
+            for (int i = 0; i < WM; ++i) {
+                a[i][0] = an[i][0];
+                a[i][1] = an[i][1];
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(kVmcnt0);  // the next K-step's fragments have landed
+        __syncthreads();
+    };
+    for (int64_t ks = 0; ks < nks; ks += 2) {
+        step(ks, Bs0, Bs1);
+        if (ks + 1 < nks) step(ks + 1, Bs1, Bs0);
+    }
+
+    // Accumulator layout of the 32x32 MFMA: lane l holds column l % 32 and rows
+    // 8 (r / 4) + 4 (l / 32) + r % 4 for r = 0..15.
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+        const int64_t n = (tn * WN + j) * kBlk + (lane & 31);
+        if (n >= jb.ncol) continue;
+        int64_t nB = -1;
+        if (jb.nside > 0) nB = antipode_north(ring_of_north(n, jb.nside), jb.npix);
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t m = (tm * WM + i) * kBlk + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (m >= jb.nf) continue;
+                float *row = jb.Gam + m * (int64_t)jb.npix;
+                row[n] = acc[i][j][r];
+                if (nB >= 0) row[nB] = acc[i][j][r];
+            }
+        }
+    }
+}
+
 template <int WM, int WN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 2 ? 2 : 1))) void beam_gemm_kernel(BJob jb)
 {
+    __shared__ uint4 Bs0[2 * WN][64], Bs1[2 * WN][64];
     const int64_t tiles_m = (jb.fm.nblk + WM - 1) / WM;
     const int64_t tiles_n = (jb.fn.nblk + WN - 1) / WN;
     int64_t tm, tn;
     if (!patch_tile(blockIdx.x, threadIdx.x >> 6, tiles_m, tiles_n, &tm, &tn)) return;
-    beam_wave_tile<WM, WN>(jb, tm, tn, threadIdx.x & 63);
+    if constexpr (WM == 4) {
+        if (tm < tiles_m) beam_wave_tile_direct<WM, WN>(jb, tm, tn, threadIdx.x & 63);
+    } else {
+        beam_wave_tile<WM, WN>(jb, tm, tn, threadIdx.x & 63, Bs0, Bs1);
+    }
 }
 
 // Persistent multi-job form: workgroup g of the concatenated per-job patch
@@ -215,6 +336,7 @@ template <int WM, int WN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 2 ? 2 : 1))) void beam_gemm_batched_kernel(const BJob *__restrict__ jobs, int32_t njobs,
                                                                 int64_t nwg)
 {
+    __shared__ uint4 Bs0[2 * WN][64], Bs1[2 * WN][64];
     for (int64_t g = blockIdx.x; g < nwg; g += gridDim.x) {
         int j = 0;
         while (j + 1 < njobs && g >= jobs[j + 1].wg_begin) ++j;
@@ -222,8 +344,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 2 ? 2
         const int64_t tiles_m = (jb.fm.nblk + WM - 1) / WM;
         const int64_t tiles_n = (jb.fn.nblk + WN - 1) / WN;
         int64_t tm, tn;
-        if (patch_tile(g - jb.wg_begin, threadIdx.x >> 6, tiles_m, tiles_n, &tm, &tn))
-            beam_wave_tile<WM, WN>(jb, tm, tn, threadIdx.x & 63);
+        if (patch_tile(g - jb.wg_begin, threadIdx.x >> 6, tiles_m, tiles_n, &tm, &tn)) {
+            if constexpr (WM == 4) {
+                if (tm < tiles_m) beam_wave_tile_direct<WM, WN>(jb, tm, tn, threadIdx.x & 63);
+            } else {
+                beam_wave_tile<WM, WN>(jb, tm, tn, threadIdx.x & 63, Bs0, Bs1);
+            }
+        }
     }
 }
 
