@@ -201,36 +201,42 @@ int sgwb_fisher_overlap(const float *v, const float *u, const float *w, int64_t 
 
 /* ---- full Fisher matrix of a band: Eq. eq_fisher, broadband H weighting of
  * Sec. V ----------------------------------------------------------------------
- * For separable weights w(t,c) = a(t) b(c) (a per-segment noise factor times a
- * per-bin spectral factor, which is how w = H / P^2 factors when the noise
- * spectrum is stationary across segments):
- *   G(p,q) = sum_{c in [clo,chi)} H(c) sum_t a(t) b(c) gamma(t,p) gamma(t,q)
+ * For weights given as a sum of rank separable terms,
+ *   w(t,c) = sum_{r < rank} a_r(t) b_r(c)
+ * (rank 1: a per-segment noise factor times a per-bin spectral factor, which is
+ * how w = H / P^2 factors when the noise spectrum keeps its shape across
+ * segments; any w is a sum of min(nt, nf) such terms, e.g. from its singular
+ * value decomposition):
+ *   G(p,q) = sum_{c in [clo,chi)} H(c) sum_t w(t,c) gamma(t,p) gamma(t,q)
  *              cos 2 pi f_{k0+c} (tau(t,p) - tau(t,q))
- *          = sum_t a(t) gamma(t,p) gamma(t,q) Wd(tau(t,p) - tau(t,q)),
- *   Wd(D)  = sum_{c in [clo,chi)} H(c) b(c) cos 2 pi f_{k0+c} D.
+ *          = sum_r sum_t a_r(t) gamma(t,p) gamma(t,q) Wd_r(tau(t,p) - tau(t,q)),
+ *   Wd_r(D) = sum_{c in [clo,chi)} H(c) b_r(c) cos 2 pi f_{k0+c} D.
  * Its diagonal is the band sum of the per-bin diagonal Gam (sgwb_reduce_band's
  * Gbb for the same w).
- * Inputs (device): a float32 [nt]; b, H float32 [nf] (column c = bin k0 + c);
- * gamma float32, tau float64 [nt][npix] as for sgwb_make_maps (no antipodal
- * pairing: every pixel is a row and a column).  0 <= clo < chi <= nf.
+ * Inputs (device): a float32 [rank][nt]; b float32 [rank][nf], H float32 [nf]
+ * (column c = bin k0 + c); gamma float32, tau float64 [nt][npix] as for
+ * sgwb_make_maps (no antipodal pairing: every pixel is a row and a column).
+ * 0 <= clo < chi <= nf, 1 <= rank <= 64.
  * Output: G float32 [npix][npix] row-major, symmetric (overwritten).
- * Arithmetic: Wd and its derivative tabulated once per call in float64 on 64
+ * Arithmetic, per rank: Wd_r and its derivative tabulated in float64 on 64
  * points per period of the highest band frequency over 0 <= D <= 4 R_earth / c,
  * turned into the float32 cubic Hermite interpolant of each interval (relative
- * error < 2.4e-7 of sum |H b|); delays enter as 32-bit fixed-point table
+ * error < 2.4e-7 of sum |H b_r|); delays enter as 32-bit fixed-point table
  * coordinates (resolution 2^-17 of a table step below 3 kHz, 2^-14 at the
  * 24 kHz limit), so tau_p - tau_q is exact and G exactly symmetric; float32
- * accumulation over t.  Delays are clamped to |tau| <= 2 R_earth / c.
+ * accumulation over t, then over the ranks.  Delays are clamped to
+ * |tau| <= 2 R_earth / c.
  * Workspace: at least sgwb_fisher_full_workspace_size() bytes (0 for
  * arguments out of range), 256-byte aligned, owned by the caller.
- * Errors: SGWB_EINVAL (null pointer, nt/nf/npix < 1, band out of range or
- * reaching above 24 kHz, bad grid, misaligned pointer, more than 2^31 - 1
- * matrix tiles), SGWB_ENOMEM (workspace too small).                          */
+ * Errors: SGWB_EINVAL (null pointer, nt/nf/npix < 1, rank out of range, band
+ * out of range or reaching above 24 kHz, bad grid, misaligned pointer, more than
+ * 2^31 - 1 matrix tiles), SGWB_ENOMEM (workspace too small).                 */
 size_t sgwb_fisher_full_workspace_size(const sgwb_fgrid *fg /*host*/, int64_t k0, int32_t chi, int32_t nt,
                                        int32_t npix);
-int sgwb_fisher_full(const float *a, const float *b, const float *H, int32_t nf, const sgwb_fgrid *fg /*host*/,
-                     int64_t k0, int32_t clo, int32_t chi, const float *gamma, const double *tau, int32_t nt,
-                     int32_t npix, float *G, void *workspace, size_t workspace_bytes, hipStream_t stream);
+int sgwb_fisher_full(const float *a, const float *b, int32_t rank, const float *H, int32_t nf,
+                     const sgwb_fgrid *fg /*host*/, int64_t k0, int32_t clo, int32_t chi, const float *gamma,
+                     const double *tau, int32_t nt, int32_t npix, float *G, void *workspace,
+                     size_t workspace_bytes, hipStream_t stream);
 
 /* ---- clean map: Eq. eq_ML_linear and its footnote ---------------------------
  * The maximum-likelihood map P solves G P = X; G is poorly conditioned, so the

@@ -94,8 +94,8 @@ _SIGNATURES = {
     "sgwb_fisher_overlap": ([_VP, _VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
                              ctypes.c_uint32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_fisher_full_workspace_size": ([ctypes.POINTER(_FGrid), _I64, _I32, _I32, _I32], ctypes.c_size_t),
-    "sgwb_fisher_full": ([_VP, _VP, _VP, _I32, ctypes.POINTER(_FGrid), _I64, _I32, _I32, _VP, _VP, _I32, _I32, _VP,
-                          _VP, ctypes.c_size_t, _VP], ctypes.c_int),
+    "sgwb_fisher_full": ([_VP, _VP, _I32, _VP, _I32, ctypes.POINTER(_FGrid), _I64, _I32, _I32, _VP, _VP, _I32, _I32,
+                          _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_clean_map_workspace_size": ([_I32], ctypes.c_size_t),
     "sgwb_clean_map_cg": ([_VP, _VP, _I32, _I32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_reduce_band_workspace_size": ([_I32, _I32, _I32], ctypes.c_size_t),
@@ -421,16 +421,19 @@ def fisher_full_workspace_bytes(fgrid: FGrid, k0: int, khi: int, nt: int, npix: 
 def fisher_full(a: torch.Tensor, b: torch.Tensor, H: torch.Tensor, fgrid: FGrid, k0: int, klo: int, khi: int,
                 gamma: torch.Tensor, tau: torch.Tensor, out=None, workspace: torch.Tensor | None = None):
     """Full Fisher matrix G [npix][npix] of the bins [klo, khi) (Eq. eq_fisher,
-    broadband H weighting of Sec. V) for separable weights w(t,c) = a[t] b[c]:
-    a float32 [nt], b and H float32 [nf] (column c = bin k0 + c)."""
+    broadband H weighting of Sec. V) for weights w(t,c) = sum_r a[r][t] b[r][c]:
+    a float32 [nt] or [rank][nt], b float32 [nf] or [rank][nf], H float32 [nf]
+    (column c = bin k0 + c)."""
     nt, npix = gamma.shape
-    nf = b.shape[0]
-    _require(a, "a", torch.float32, (nt,))
-    _require(b, "b", torch.float32, (nf,))
+    a2 = a.reshape(1, -1) if a.dim() == 1 else a
+    b2 = b.reshape(1, -1) if b.dim() == 1 else b
+    rank, nf = b2.shape
+    _require(a2, "a", torch.float32, (rank, nt))
+    _require(b2, "b", torch.float32, (rank, nf))
     _require(H, "H", torch.float32, (nf,))
     _require(gamma, "gamma", torch.float32, (nt, npix))
     _require(tau, "tau", torch.float64, (nt, npix))
-    for name, t in (("a", a), ("b", b), ("H", H), ("gamma", gamma), ("tau", tau)):
+    for name, t in (("a", a2), ("b", b2), ("H", H), ("gamma", gamma), ("tau", tau)):
         _require_contig(t, name)
     dev = gamma.device
     G = out if out is not None else torch.empty((npix, npix), dtype=torch.float32, device=dev)
@@ -442,8 +445,9 @@ def fisher_full(a: torch.Tensor, b: torch.Tensor, H: torch.Tensor, fgrid: FGrid,
             need = fisher_full_workspace_bytes(fgrid, k0, khi, nt, npix)
             workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
         wsz = workspace.numel() * workspace.element_size()
-        rc = lib().sgwb_fisher_full(_ptr(a), _ptr(b), _ptr(H), nf, ctypes.byref(fg), int(k0), int(klo), int(khi),
-                                    _ptr(gamma), _ptr(tau), nt, npix, _ptr(G), _ptr(workspace), wsz, _stream())
+        rc = lib().sgwb_fisher_full(_ptr(a2), _ptr(b2), rank, _ptr(H), nf, ctypes.byref(fg), int(k0), int(klo),
+                                    int(khi), _ptr(gamma), _ptr(tau), nt, npix, _ptr(G), _ptr(workspace), wsz,
+                                    _stream())
     _check(rc, "fisher_full")
     return G
 

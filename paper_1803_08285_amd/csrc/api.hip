@@ -343,12 +343,13 @@ size_t sgwb_fisher_full_workspace_size(const sgwb_fgrid *fg, int64_t k0, int32_t
     return fisher_full_workspace_bytes(f_max, chi, nt, npix);
 }
 
-int sgwb_fisher_full(const float *a, const float *b, const float *H, int32_t nf, const sgwb_fgrid *fg, int64_t k0,
-                     int32_t clo, int32_t chi, const float *gamma, const double *tau, int32_t nt, int32_t npix,
-                     float *G, void *workspace, size_t workspace_bytes, hipStream_t stream)
+int sgwb_fisher_full(const float *a, const float *b, int32_t rank, const float *H, int32_t nf, const sgwb_fgrid *fg,
+                     int64_t k0, int32_t clo, int32_t chi, const float *gamma, const double *tau, int32_t nt,
+                     int32_t npix, float *G, void *workspace, size_t workspace_bytes, hipStream_t stream)
 {
     if (!a || !b || !H || !fg || !gamma || !tau || !G) return set_error(SGWB_EINVAL, "fisher_full: null pointer");
     if (nt < 1 || nf < 1 || npix < 1) return set_error(SGWB_EINVAL, "fisher_full: nt, nf, npix must be >= 1");
+    if (rank < 1 || rank > 64) return set_error(SGWB_EINVAL, "fisher_full: rank must be 1..64");
     if (!(0 <= clo && clo < chi && chi <= nf))
         return set_error(SGWB_EINVAL, "fisher_full: band [%d, %d) not inside [0, %d)", clo, chi, nf);
     if (!std::isfinite(fg->f0_hz) || !std::isfinite(fg->df_hz) || fg->df_hz <= 0.0 || fg->f0_hz < 0.0 || k0 < 0)
@@ -365,8 +366,8 @@ int sgwb_fisher_full(const float *a, const float *b, const float *H, int32_t nf,
     const size_t need = sgwb_fisher_full_workspace_size(fg, k0, chi, nt, npix);
     if (workspace_bytes < need)
         return set_error(SGWB_ENOMEM, "fisher_full: workspace of %zu bytes needed, %zu given", need, workspace_bytes);
-    return check_hip(launch_fisher_full(a, b, H, clo, chi, fg->f0_hz, fg->df_hz, k0, gamma, tau, nt, npix, G,
-                                        workspace, stream),
+    return check_hip(launch_fisher_full(a, b, rank, H, nf, clo, chi, fg->f0_hz, fg->df_hz, k0, gamma, tau, nt, npix,
+                                        G, workspace, stream),
                      "full Fisher launch");
 }
 

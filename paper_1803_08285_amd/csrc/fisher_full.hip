@@ -1,6 +1,7 @@
 // Full Fisher information matrix of a band and the conjugate-gradient clean map
 // (Eqs. eq_fisher, eq_ML_linear and its footnote; broadband H weighting of
-// Sec. V), for separable weights w(t,f) = a(t) b(f):
+// Sec. V), for weights of rank R, w(t,f) = sum_r a_r(t) b_r(f) (one pass per rank;
+// the formulas below are one rank's):
 //   G(p,q) = sum_{k in band} H_k sum_t w(t,k) gamma_p gamma_q cos 2 pi f_k (tau_p - tau_q)
 //          = sum_t a_t gamma_p(t) gamma_q(t) W(tau_p(t) - tau_q(t)),
 //   W(D)   = sum_{k in band} H_k b_k cos 2 pi f_k D.
@@ -123,6 +124,19 @@ __device__ __forceinline__ void tri_tile(int64_t k, int64_t n, int64_t &r, int64
     c = r + (k - start(r));
 }
 
+// G(p,q) and G(q,p) (once on the diagonal), overwritten or added to (the
+// terms of a further rank of the weights).
+__device__ __forceinline__ void store_pair(float *__restrict__ G, int64_t npix, int64_t p, int64_t q, float v,
+                                           int32_t accumulate)
+{
+    float *e = G + p * npix + q;
+    *e = accumulate ? *e + v : v;
+    if (p != q) {
+        float *m = G + q * npix + p;
+        *m = accumulate ? *m + v : v;
+    }
+}
+
 __device__ __forceinline__ uint32_t abs_diff(uint32_t x, uint32_t y)
 {
     uint32_t d;
@@ -136,7 +150,7 @@ __device__ __forceinline__ uint32_t abs_diff(uint32_t x, uint32_t y)
 // evaluate the cubic, two more weight and accumulate it.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void fisher_full_kernel(const float *__restrict__ a, const float *__restrict__ gamma,
                                                           const uint32_t *__restrict__ U, int32_t nt, int32_t npix,
-                                                          const float4 *__restrict__ cub, int32_t fb,
+                                                          const float4 *__restrict__ cub, int32_t fb, int32_t accumulate,
                                                           float *__restrict__ G)
 {
     __shared__ float gP[kFtSeg][kFt], gQ[kFtSeg][kFt];
@@ -198,10 +212,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
         for (int jj = 0; jj < 4; ++jj) {
             const int64_t p = tr * kFt + ty * 4 + i, q = tc * kFt + tx * 4 + jj;
             // a diagonal tile writes its upper triangle and the mirror of it
-            if (p < npix && q < npix && (tr != tc || p <= q)) {
-                G[p * npix + q] = acc[i][jj];
-                G[q * npix + p] = acc[i][jj];
-            }
+            if (p < npix && q < npix && (tr != tc || p <= q)) store_pair(G, npix, p, q, acc[i][jj], accumulate);
         }
 }
 
@@ -217,7 +228,7 @@ __global__ __launch_bounds__(512) void fisher_full_lds_kernel(const float *__res
                                                                const uint32_t *__restrict__ U, int32_t nt,
                                                                int32_t npix, const float4 *__restrict__ cub,
                                                                int32_t J, int32_t fb, int64_t ntiles,
-                                                               float *__restrict__ G)
+                                                               int32_t accumulate, float *__restrict__ G)
 {
     __shared__ float4 tab[kLdsTable];
     for (int j = threadIdx.x; j < J; j += 512) tab[j] = cub[j];
@@ -294,10 +305,7 @@ __global__ __launch_bounds__(512) void fisher_full_lds_kernel(const float *__res
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
                 const int64_t p = tr * kFt + ty * 4 + i, q = tc * kFt + tx * 4 + jj;
-                if (pv[i] && q < npix && (tr != tc || p <= q)) {
-                    G[p * npix + q] = acc[i][jj];
-                    G[q * npix + p] = acc[i][jj];
-                }
+                if (pv[i] && q < npix && (tr != tc || p <= q)) store_pair(G, npix, p, q, acc[i][jj], accumulate);
             }
     }
 }
@@ -331,9 +339,9 @@ size_t fisher_full_workspace_bytes(double f_max, int32_t nbins, int32_t nt, int3
            up256((size_t)nt * npix * sizeof(uint32_t));
 }
 
-hipError_t launch_fisher_full(const float *a, const float *b, const float *H, int32_t clo, int32_t chi, double f0,
-                              double df, int64_t k0, const float *gamma, const double *tau, int32_t nt, int32_t npix,
-                              float *G, void *work, hipStream_t s)
+hipError_t launch_fisher_full(const float *a, const float *b, int32_t rank, const float *H, int32_t nf, int32_t clo,
+                              int32_t chi, double f0, double df, int64_t k0, const float *gamma, const double *tau,
+                              int32_t nt, int32_t npix, float *G, void *work, hipStream_t s)
 {
     const double f_max = f0 + (double)(k0 + chi - 1) * df;
     double delta;
@@ -348,25 +356,35 @@ hipError_t launch_fisher_full(const float *a, const float *b, const float *H, in
     float4 *cub = reinterpret_cast<float4 *>(w);
     w += up256((size_t)J * sizeof(float4));
     uint32_t *U = reinterpret_cast<uint32_t *>(w);
-    hipLaunchKernelGGL(delay_table_kernel, dim3((unsigned)((J + 1 + 255) / 256), (unsigned)nchunk), dim3(256), 0, s,
-                       H, b, clo, chi, f0, df, k0, delta, J, part);
-    hipLaunchKernelGGL(delay_cubic_kernel, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, s, part, nchunk, J, cub);
     const int64_t n = (int64_t)nt * npix;
     hipLaunchKernelGGL(fixed_delay_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tau, n,
                        std::ldexp(1.0, fb) / delta, U);
     const int64_t nT = (npix + kFt - 1) / kFt, ntiles = nT * (nT + 1) / 2;
     if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
-    if (J <= kLdsTable && fisher_full_table_in_lds()) {
-        int dev = 0, cus = 0;
+    const bool lds = J <= kLdsTable && fisher_full_table_in_lds();
+    int cus = 256;
+    if (lds) {
+        int dev = 0;
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
-        const int64_t grid = std::min<int64_t>(cus, (ntiles + 1) / 2);
-        hipLaunchKernelGGL(fisher_full_lds_kernel, dim3((unsigned)grid), dim3(512), 0, s, a, gamma, U, nt, npix,
-                           cub, J, fb, ntiles, G);
-    } else {
-        hipLaunchKernelGGL(fisher_full_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, a, gamma, U, nt, npix, cub,
-                           fb, G);
+    }
+    // one delay table and one pass over the matrix per rank of the weights,
+    // the later passes adding to G
+    for (int32_t r = 0; r < rank; ++r) {
+        const float *ar = a + (int64_t)r * nt, *br = b + (int64_t)r * nf;
+        hipLaunchKernelGGL(delay_table_kernel, dim3((unsigned)((J + 1 + 255) / 256), (unsigned)nchunk), dim3(256), 0,
+                           s, H, br, clo, chi, f0, df, k0, delta, J, part);
+        hipLaunchKernelGGL(delay_cubic_kernel, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, s, part, nchunk, J,
+                           cub);
+        if (lds) {
+            const int64_t grid = std::min<int64_t>(cus, (ntiles + 1) / 2);
+            hipLaunchKernelGGL(fisher_full_lds_kernel, dim3((unsigned)grid), dim3(512), 0, s, ar, gamma, U, nt, npix,
+                               cub, J, fb, ntiles, (int32_t)(r > 0), G);
+        } else {
+            hipLaunchKernelGGL(fisher_full_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, ar, gamma, U, nt, npix,
+                               cub, fb, (int32_t)(r > 0), G);
+        }
     }
     return hipGetLastError();
 }

@@ -139,9 +139,9 @@ hipError_t launch_contract(const float *M, int32_t nf, int32_t npix, const int32
 // full Fisher matrix of a band for separable weights, and its CG clean map
 size_t fisher_full_workspace_bytes(double f_max, int32_t nbins, int32_t nt, int32_t npix);
 bool fisher_full_band_ok(double f_max);
-hipError_t launch_fisher_full(const float *a, const float *b, const float *H, int32_t clo, int32_t chi, double f0,
-                              double df, int64_t k0, const float *gamma, const double *tau, int32_t nt, int32_t npix,
-                              float *G, void *work, hipStream_t s);
+hipError_t launch_fisher_full(const float *a, const float *b, int32_t rank, const float *H, int32_t nf, int32_t clo,
+                              int32_t chi, double f0, double df, int64_t k0, const float *gamma, const double *tau,
+                              int32_t nt, int32_t npix, float *G, void *work, hipStream_t s);
 size_t cg_workspace_bytes(int32_t n);
 hipError_t launch_clean_map_cg(const float *G, const float *X, int32_t n, int32_t niter, float *P, void *work,
                                hipStream_t s);

@@ -176,3 +176,30 @@ def test_fisher_full_and_clean_map_are_deterministic(sg):
     torch.cuda.synchronize()
     assert torch.equal(G1, G2)
     assert torch.equal(P1, P2)
+
+
+@pytest.mark.parametrize("rank,nside,k0,nf,df", [(3, 4, 100, 64, 0.25), (2, 8, 53000, 64, 1 / 32)])
+def test_fisher_full_rank_r_weights_vs_oracle(sg, oracle_mod, rank, nside, k0, nf, df):
+    """w(t,c) = sum_r a_r(t) b_r(c) with unrelated factors (a noise level that drifts
+    across the day with a spectral shape of its own per rank): one delay table and
+    one pass per rank, against the oracle on the summed, non-separable w."""
+    nt = 40
+    g, t, _, _, H = _inputs(sg, "AC", nside, None, nt, k0, nf, df, 26)
+    rng = np.random.default_rng(27)
+    f = freqs(F0, df, k0, nf)
+    a = rng.uniform(0.2, 1.0, (rank, nt)).astype(np.float32)
+    b = np.stack([(synth.spectrum_H(f) / synth.noise_psd(f) ** 2) * rng.uniform(0.5, 1.5, nf)
+                  for _ in range(rank)]).astype(np.float32)
+    klo, khi = 2, nf - 3
+    G = sg.fisher_full(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), torch.from_numpy(H).cuda(),
+                       sg.FGrid(F0, df), k0, klo, khi, g, t)
+    torch.cuda.synchronize()
+    Gg = G.cpu().numpy().astype(np.float64)
+    gh, th = g.cpu().numpy().astype(np.float64), t.cpu().numpy()
+    npix = gh.shape[1]
+    sel = np.arange(npix) if npix <= 200 else np.sort(np.random.default_rng(5).choice(npix, 40, replace=False))
+    w = sum(np.outer(a[r].astype(np.float64), b[r].astype(np.float64)) for r in range(rank))
+    Go = oracle_mod.fisher_full(w, H.astype(np.float64), F0, df, k0, klo, khi, gh[:, sel], th[:, sel])
+    S = sum(_scale(a[r], b[r], H, klo, khi, gh[:, sel]) for r in range(rank))
+    assert np.max(np.abs(Gg[np.ix_(sel, sel)] - Go) / S) <= 1e-5
+    assert np.array_equal(Gg, Gg.T)
