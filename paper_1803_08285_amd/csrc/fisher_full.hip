@@ -390,16 +390,21 @@ hipError_t launch_fisher_full(const float *a, const float *b, int32_t rank, cons
 }
 
 // ---- conjugate gradient on G P = X (float64 vectors, fixed-order sums) ----
-constexpr int kCgParts = 256;
+// Three kernels per iteration: q = G p with the partial sums of p.q; the step
+// (every block adds the p.q partials itself, in one fixed order, so all agree
+// on alpha) with the partial sums of r.r; the new direction (likewise for
+// beta).  The scalars never leave the device.
 
 // q = G p for kCgRows rows per workgroup: each p[j] is read once for all of
-// them; per-thread partial sums over a fixed column stride, then a fixed tree.
+// them; per-thread partial sums over a fixed column stride, then a fixed tree;
+// the workgroup's share of p.q goes to pq_part[blockIdx.x].
 // VEC: four consecutive columns per load (n % 4 == 0, G 16-byte aligned).
 constexpr int kCgRows = 4;
 
 template <bool VEC>
 __global__ __launch_bounds__(256) void cg_matvec_kernel(const float *__restrict__ G, const double *__restrict__ p,
-                                                        int32_t n, double *__restrict__ q)
+                                                        int32_t n, double *__restrict__ q,
+                                                        double *__restrict__ pq_part)
 {
     __shared__ double red[kCgRows][256];
     const int64_t r0 = (int64_t)blockIdx.x * kCgRows;
@@ -435,16 +440,37 @@ __global__ __launch_bounds__(256) void cg_matvec_kernel(const float *__restrict_
             for (int r = 0; r < kCgRows; ++r) red[r][threadIdx.x] += red[r][threadIdx.x + st];
         __syncthreads();
     }
-    if ((int)threadIdx.x < nr) q[r0 + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x == 0) {
+        double d = 0.0;
+        for (int r = 0; r < nr; ++r) {
+            q[r0 + r] = red[r][0];
+            d += p[r0 + r] * red[r][0];
+        }
+        pq_part[blockIdx.x] = d;
+    }
 }
 
-__global__ __launch_bounds__(256) void cg_dot_kernel(const double *__restrict__ x, const double *__restrict__ y,
-                                                     int32_t n, double *__restrict__ part)
+// Sum of part[0..np) in a fixed order (per-thread strides, then a fixed tree),
+// the same in every block; called by all 256 threads.
+__device__ __forceinline__ double cg_block_sum(const double *__restrict__ part, int32_t np, double *red)
 {
-    __shared__ double red[256];
     double acc = 0.0;
-    for (int32_t j = blockIdx.x * 256 + threadIdx.x; j < n; j += kCgParts * 256) acc += x[j] * y[j];
+    for (int32_t j = threadIdx.x; j < np; j += 256) acc += part[j];
     red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    const double v = red[0];
+    __syncthreads();
+    return v;
+}
+
+// Partial sums of x.y, one per block of 256 elements.
+__device__ __forceinline__ void cg_block_dot(double v, double *__restrict__ part, double *red)
+{
+    red[threadIdx.x] = v;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
         if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
@@ -453,50 +479,55 @@ __global__ __launch_bounds__(256) void cg_dot_kernel(const double *__restrict__ 
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(256) void cg_dot_final_kernel(const double *__restrict__ part, double *__restrict__ out)
+// x = 0, r = p = X, partial sums of r.r
+__global__ __launch_bounds__(256) void cg_init_kernel(const float *__restrict__ X, int32_t n, double *__restrict__ x,
+                                                      double *__restrict__ r, double *__restrict__ p,
+                                                      double *__restrict__ rr_part)
 {
     __shared__ double red[256];
-    red[threadIdx.x] = part[threadIdx.x];
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = red[0];
-}
-
-// x = 0, r = p = X
-__global__ __launch_bounds__(256) void cg_init_kernel(const float *__restrict__ X, int32_t n, double *__restrict__ x,
-                                                      double *__restrict__ r, double *__restrict__ p)
-{
     const int32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    x[j] = 0.0;
-    r[j] = p[j] = (double)X[j];
+    double v = 0.0;
+    if (j < n) {
+        const double xj = (double)X[j];
+        x[j] = 0.0;
+        r[j] = p[j] = xj;
+        v = xj * xj;
+    }
+    cg_block_dot(v, rr_part, red);
 }
 
-// alpha = rr / pq (0 once the residual vanishes); x += alpha p; r -= alpha q
+// alpha = rr / pq (0 once the residual or the curvature vanishes); x += alpha p;
+// r -= alpha q; partial sums of the new r.r.  rr = sum of rr_part (nb blocks).
 __global__ __launch_bounds__(256) void cg_step_kernel(double *__restrict__ x, double *__restrict__ r,
                                                       const double *__restrict__ p, const double *__restrict__ q,
-                                                      const double *__restrict__ rr, const double *__restrict__ pq,
-                                                      int32_t n)
+                                                      const double *__restrict__ rr_part,
+                                                      const double *__restrict__ pq_part, int32_t nb, int32_t nm,
+                                                      int32_t n, double *__restrict__ rr_new_part)
 {
+    __shared__ double red[256];
+    const double rr = cg_block_sum(rr_part, nb, red), pq = cg_block_sum(pq_part, nm, red);
+    const double alpha = (rr != 0.0 && pq != 0.0) ? rr / pq : 0.0;
     const int32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    const double alpha = (rr[0] != 0.0 && pq[0] != 0.0) ? rr[0] / pq[0] : 0.0;
-    x[j] += alpha * p[j];
-    r[j] -= alpha * q[j];
+    double v = 0.0;
+    if (j < n) {
+        x[j] += alpha * p[j];
+        const double rj = r[j] - alpha * q[j];
+        r[j] = rj;
+        v = rj * rj;
+    }
+    cg_block_dot(v, rr_new_part, red);
 }
 
 // p = r + (rr_new / rr) p
 __global__ __launch_bounds__(256) void cg_dir_kernel(double *__restrict__ p, const double *__restrict__ r,
-                                                     const double *__restrict__ rr, const double *__restrict__ rr_new,
-                                                     int32_t n)
+                                                     const double *__restrict__ rr_part,
+                                                     const double *__restrict__ rr_new_part, int32_t nb, int32_t n)
 {
+    __shared__ double red[256];
+    const double rr = cg_block_sum(rr_part, nb, red), rr_new = cg_block_sum(rr_new_part, nb, red);
+    const double beta = rr != 0.0 ? rr_new / rr : 0.0;
     const int32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    const double beta = rr[0] != 0.0 ? rr_new[0] / rr[0] : 0.0;
-    p[j] = r[j] + beta * p[j];
+    if (j < n) p[j] = r[j] + beta * p[j];
 }
 
 __global__ __launch_bounds__(256) void cg_out_kernel(const double *__restrict__ x, int32_t n, float *__restrict__ P)
@@ -507,34 +538,29 @@ __global__ __launch_bounds__(256) void cg_out_kernel(const double *__restrict__ 
 
 size_t cg_workspace_bytes(int32_t n)
 {
-    return (size_t)4 * n * sizeof(double) + (kCgParts + 8) * sizeof(double);
+    const size_t nb = ((size_t)n + 255) / 256, nm = ((size_t)n + kCgRows - 1) / kCgRows;
+    return (4 * (size_t)n + nm + 2 * nb) * sizeof(double);
 }
 
 hipError_t launch_clean_map_cg(const float *G, const float *X, int32_t n, int32_t niter, float *P, void *work,
                                hipStream_t s)
 {
-    double *x = reinterpret_cast<double *>(work), *r = x + n, *p = r + n, *q = p + n, *part = q + n;
-    double *sc = part + kCgParts;  // sc[0], sc[1]: |r|^2 of even/odd iterations; sc[2]: p.q
-    const unsigned g = (unsigned)((n + 255) / 256);
-    const unsigned mg = (unsigned)((n + kCgRows - 1) / kCgRows);
+    const int32_t nb = (n + 255) / 256, nm = (n + kCgRows - 1) / kCgRows;
+    double *x = reinterpret_cast<double *>(work), *r = x + n, *p = r + n, *q = p + n;
+    double *pq_part = q + n, *rr_a = pq_part + nm, *rr_b = rr_a + nb;  // r.r partials, this and the next iterate
     const bool vec = n % 4 == 0 && reinterpret_cast<uintptr_t>(G) % 16 == 0;
-    hipLaunchKernelGGL(cg_init_kernel, dim3(g), dim3(256), 0, s, X, n, x, r, p);
-    hipLaunchKernelGGL(cg_dot_kernel, dim3(kCgParts), dim3(256), 0, s, r, r, n, part);
-    hipLaunchKernelGGL(cg_dot_final_kernel, dim3(1), dim3(256), 0, s, part, sc);
+    hipLaunchKernelGGL(cg_init_kernel, dim3((unsigned)nb), dim3(256), 0, s, X, n, x, r, p, rr_a);
     for (int32_t it = 0; it < niter; ++it) {
-        double *rr = sc + (it & 1), *rr_new = sc + ((it + 1) & 1);
+        double *rr = (it & 1) ? rr_b : rr_a, *rr_new = (it & 1) ? rr_a : rr_b;
         if (vec)
-            hipLaunchKernelGGL(cg_matvec_kernel<true>, dim3(mg), dim3(256), 0, s, G, p, n, q);
+            hipLaunchKernelGGL(cg_matvec_kernel<true>, dim3((unsigned)nm), dim3(256), 0, s, G, p, n, q, pq_part);
         else
-            hipLaunchKernelGGL(cg_matvec_kernel<false>, dim3(mg), dim3(256), 0, s, G, p, n, q);
-        hipLaunchKernelGGL(cg_dot_kernel, dim3(kCgParts), dim3(256), 0, s, p, q, n, part);
-        hipLaunchKernelGGL(cg_dot_final_kernel, dim3(1), dim3(256), 0, s, part, sc + 2);
-        hipLaunchKernelGGL(cg_step_kernel, dim3(g), dim3(256), 0, s, x, r, p, q, rr, sc + 2, n);
-        hipLaunchKernelGGL(cg_dot_kernel, dim3(kCgParts), dim3(256), 0, s, r, r, n, part);
-        hipLaunchKernelGGL(cg_dot_final_kernel, dim3(1), dim3(256), 0, s, part, rr_new);
-        hipLaunchKernelGGL(cg_dir_kernel, dim3(g), dim3(256), 0, s, p, r, rr, rr_new, n);
+            hipLaunchKernelGGL(cg_matvec_kernel<false>, dim3((unsigned)nm), dim3(256), 0, s, G, p, n, q, pq_part);
+        hipLaunchKernelGGL(cg_step_kernel, dim3((unsigned)nb), dim3(256), 0, s, x, r, p, q, rr, pq_part, nb, nm, n,
+                           rr_new);
+        hipLaunchKernelGGL(cg_dir_kernel, dim3((unsigned)nb), dim3(256), 0, s, p, r, rr, rr_new, nb, n);
     }
-    hipLaunchKernelGGL(cg_out_kernel, dim3(g), dim3(256), 0, s, x, n, P);
+    hipLaunchKernelGGL(cg_out_kernel, dim3((unsigned)nb), dim3(256), 0, s, x, n, P);
     return hipGetLastError();
 }
 
