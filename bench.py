@@ -1,8 +1,9 @@
 """Benchmark of the folded-data radiometer map-making hot path on one MI355X.
 
-One step = the whole path for one folded day of one baseline:
-  make_maps (dirty map X and Fisher diagonal Gam for every bin and pixel)
-  + reduce_band over the full band (broadband Xbb, Gbb).
+One step = the whole path for one folded day of one baseline: the dirty map X
+and the Fisher diagonal Gam for every bin and pixel, and their broadband sums
+Xbb, Gbb over the full band (make_maps_band: the band sums are taken inside the
+map kernels).
 Inputs (seeds gamma/tau, CSD C, weights w) are resident in HBM before timing.
 
 Prints ONE JSON line with the metric (map terms/s, t * f * pixel, for X + Gam),
@@ -517,21 +518,24 @@ def main():
     G = torch.empty_like(X)
     Xbb = torch.empty(npix, dtype=torch.float32, device=dev)
     Gbb = torch.empty_like(Xbb)
-    ws = sg.make_workspace(tg.nt, fgd.nf, npix, True, device=dev)
+    ws = torch.empty(sg.band_maps_workspace_bytes(tg.nt, fgd.nf, npix, True), dtype=torch.uint8, device=dev)
     fg = sg.FGrid(fgd.f0, fgd.df)
 
+    # One step: the dirty map with its band sum, then the beam with its band sum
+    # (make_maps_band: the map kernels add their tiles' band sums, one small
+    # kernel per map adds those up).  The band phase below is what is left
+    # between the two calls' ends: nothing.
     def step(evs=None):
         if evs:
             evs[0].record()
-        sg.make_maps(inp["C"], inp["w"], fg, fgd.k0, inp["gamma"], inp["tau"], want_gamma=False, out=(X, None))
+        sg.make_maps_band(inp["C"], inp["w"], fg, fgd.k0, inp["gamma"], inp["tau"], None, 0, fgd.nf,
+                          want_gamma=False, out=(X, None, Xbb, None), workspace=ws)
         if evs:
             evs[1].record()
-        sg.make_maps(inp["C"], inp["w"], fg, fgd.k0, inp["gamma"], inp["tau"], want_x=False, out=(None, G),
-                     workspace=ws)
+        sg.make_maps_band(inp["C"], inp["w"], fg, fgd.k0, inp["gamma"], inp["tau"], inp["H"], 0, fgd.nf,
+                          want_x=False, out=(None, G, None, Gbb), workspace=ws)
         if evs:
             evs[2].record()
-        sg.reduce_band(X, G, inp["H"], 0, fgd.nf, out=(Xbb, Gbb))
-        if evs:
             evs[3].record()
 
     for i in range(args.warmup):

@@ -281,6 +281,31 @@ int sgwb_reduce_band_f64(const double *X, const double *Gam, const double *H, in
                          int32_t npix, int32_t k_lo, int32_t k_hi, double *Xbb, double *Gbb,
                          hipStream_t stream);
 
+/* ---- narrowband and broadband maps in one call: Secs. III.E and V ----------
+ * X, Gam as sgwb_make_maps (same flags, same bits) and the broadband maps over
+ * columns [k_lo, k_hi) of the same call, without reading the narrowband maps
+ * back:
+ *   Xbb(p) = sum_k X(k,p): where the matrix-core dirty map runs it also writes
+ *     the float64 sum of each absolute 64-bin strip and one small kernel adds
+ *     the strips in order, rounding once (equal to sgwb_reduce_band's Xbb up to
+ *     the order of the float64 sums); otherwise the single-pass band kernel;
+ *   Gbb(p) = sum_k H(k) Gam(k,p) = sum_t v(t) gamma(t,p)^2, v(t) = sum_k H(k) w(t,k):
+ *     the band sum moved into the weights, float64 throughout, rounded once (the
+ *     exact band-summed diagonal; sgwb_reduce_band of the split-bf16 Gam meets it
+ *     within that map's 1e-4).
+ * X and Xbb, Gam and Gbb come in pairs (either pair may be NULL, not both);
+ * H[nf] is needed with Gbb.
+ * Workspace: at least sgwb_make_maps_band_workspace_size() bytes, 256-byte
+ * aligned, owned by the caller.
+ * Errors: as sgwb_make_maps; SGWB_EINVAL also for unpaired outputs, a band
+ * outside [0, nf] or a null H.                                               */
+size_t sgwb_make_maps_band_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint32_t flags);
+int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf,
+                        const sgwb_fgrid *fg /*host*/, int64_t k0, const float *gamma, const double *tau,
+                        int32_t npix, uint32_t flags, const float *H, int32_t k_lo, int32_t k_hi, float *X,
+                        float *Gam, float *Xbb, float *Gbb, void *workspace, size_t workspace_bytes,
+                        hipStream_t stream);
+
 /* ---- batched plans ------------------------------------------------------
  * Several map jobs (baselines, resolutions, uneven bands; Sec. III.C notes
  * that maps of several baselines are made the same way and added) run as one

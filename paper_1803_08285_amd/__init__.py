@@ -98,6 +98,10 @@ _SIGNATURES = {
                           _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_clean_map_workspace_size": ([_I32], ctypes.c_size_t),
     "sgwb_clean_map_cg": ([_VP, _VP, _I32, _I32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
+    "sgwb_make_maps_band_workspace_size": ([_I32, _I32, _I32, ctypes.c_uint32], ctypes.c_size_t),
+    "sgwb_make_maps_band": ([_VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
+                             ctypes.c_uint32, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP],
+                            ctypes.c_int),
     "sgwb_reduce_band_workspace_size": ([_I32, _I32, _I32], ctypes.c_size_t),
     "sgwb_reduce_band": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_reduce_band_f64": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
@@ -291,6 +295,63 @@ def make_maps(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamma: to
                                       _stream())
     _check(rc, "make_maps")
     return X, G
+
+
+def band_maps_workspace_bytes(nt: int, nf: int, npix: int, antipodal: bool = True) -> int:
+    return int(lib().sgwb_make_maps_band_workspace_size(nt, nf, npix, SGWB_MAPS_ANTIPODAL if antipodal else 0))
+
+
+def make_maps_band(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamma: torch.Tensor,
+                   tau: torch.Tensor, H: torch.Tensor | None, k_lo: int, k_hi: int, antipodal: bool = True,
+                   want_x: bool = True, want_gamma: bool = True, out=None, workspace: torch.Tensor | None = None,
+                   x_kernel: str = "auto"):
+    """make_maps and reduce_band over columns [k_lo, k_hi) in one call (float32):
+    returns X, Gam [nf][npix] and Xbb, Gbb [npix] (None where not asked for)."""
+    if C.dim() != 2 or w.dim() != 2:
+        raise SgwbError("C and w must be 2-D")
+    nt, nf = w.shape
+    npix = gamma.shape[1]
+    _require(C, "C", torch.complex64, (nt, nf))
+    _require(w, "w", torch.float32, (nt, nf))
+    if C.stride(0) != w.stride(0):
+        raise SgwbError("C and w must share their row stride")
+    _require(gamma, "gamma", torch.float32, (nt, npix))
+    _require(tau, "tau", torch.float64, (nt, npix))
+    _require_contig(gamma, "gamma")
+    _require_contig(tau, "tau")
+    if want_gamma:
+        if H is None:
+            raise SgwbError("H is needed for Gbb")
+        _require(H, "H", torch.float32, (nf,))
+        _require_contig(H, "H")
+    dev = C.device
+    if out is None:
+        X = torch.empty((nf, npix), dtype=torch.float32, device=dev) if want_x else None
+        G = torch.empty((nf, npix), dtype=torch.float32, device=dev) if want_gamma else None
+        Xbb = torch.empty(npix, dtype=torch.float32, device=dev) if want_x else None
+        Gbb = torch.empty(npix, dtype=torch.float32, device=dev) if want_gamma else None
+    else:
+        X, G, Xbb, Gbb = out
+    for name, t, shape in (("X", X, (nf, npix)), ("Gam", G, (nf, npix)), ("Xbb", Xbb, (npix,)),
+                           ("Gbb", Gbb, (npix,))):
+        if t is not None:
+            _require(t, name, torch.float32, shape)
+            _require_contig(t, name)
+    if x_kernel not in ("auto", "valu"):
+        raise SgwbError("x_kernel must be 'auto' or 'valu'")
+    flags = (SGWB_MAPS_ANTIPODAL if antipodal else 0) | (SGWB_MAPS_VALU_X if x_kernel == "valu" else 0)
+    fg = _FGrid(float(fgrid.f0), float(fgrid.df))
+    with torch.cuda.device(dev):
+        if workspace is None:
+            workspace = torch.empty(max(band_maps_workspace_bytes(nt, nf, npix, antipodal), 256), dtype=torch.uint8,
+                                    device=dev)
+        wsz = workspace.numel() * workspace.element_size()
+        rc = lib().sgwb_make_maps_band(_ptr(torch.view_as_real(C)), _ptr(w), int(w.stride(0)), nt, nf,
+                                       ctypes.byref(fg), int(k0), _ptr(gamma), _ptr(tau), npix, flags,
+                                       _ptr(H) if H is not None else None, int(k_lo), int(k_hi), _ptr(X), _ptr(G),
+                                       _ptr(Xbb), _ptr(Gbb), _ptr(workspace), wsz, _stream())
+    _check(rc, "make_maps_band")
+    return X, G, Xbb, Gbb
 
 
 def network_sum(maps, out=None):

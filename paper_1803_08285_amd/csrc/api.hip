@@ -409,6 +409,76 @@ int sgwb_make_maps_f64(const double *C, const double *w, int64_t ldc, int32_t nt
     return SGWB_OK;
 }
 
+size_t sgwb_make_maps_band_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint32_t flags)
+{
+    const size_t base = sgwb_make_maps_workspace_size(nt, nf, npix, flags);
+    if (!base) return 0;
+    // X partial sums: at most nf / 64 + 2 strips (any k0); Gbb: one weight per segment
+    const size_t rows_x = (size_t)nf / 64 + 2;
+    return up256(base) + up256(rows_x * npix * sizeof(double)) + up256(band_gamma_scratch_bytes(nt, npix));
+}
+
+int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
+                        int64_t k0, const float *gamma, const double *tau, int32_t npix, uint32_t flags,
+                        const float *H, int32_t k_lo, int32_t k_hi, float *X, float *Gam, float *Xbb, float *Gbb,
+                        void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    if (!X != !Xbb || !Gam != !Gbb)
+        return set_error(SGWB_EINVAL, "make_maps_band: X and Xbb, Gam and Gbb come in pairs");
+    if (!X && !Gam) return set_error(SGWB_EINVAL, "make_maps_band: nothing to compute");
+    if (Gbb && !H) return set_error(SGWB_EINVAL, "make_maps_band: null H");
+    if (!(0 <= k_lo && k_lo <= k_hi && k_hi <= nf))
+        return set_error(SGWB_EINVAL, "make_maps_band: band [%d, %d) not inside [0, %d]", k_lo, k_hi, nf);
+    MapArgs a;
+    int rc = check_maps_args<float>(C, w, ldc, nt, nf, fg, k0, gamma, tau, npix, flags, &a);
+    if (rc) return rc;
+    if (!workspace || (uintptr_t)workspace % 256)
+        return set_error(SGWB_EINVAL, "make_maps_band: workspace null or not 256-byte aligned");
+    const size_t need = sgwb_make_maps_band_workspace_size(nt, nf, npix, flags);
+    if (workspace_bytes < need)
+        return set_error(SGWB_ENOMEM, "make_maps_band: workspace of %zu bytes needed, %zu given", need,
+                         workspace_bytes);
+    const size_t base = up256(sgwb_make_maps_workspace_size(nt, nf, npix, flags));
+    const size_t rows_x = (size_t)nf / 64 + 2;
+    char *ws = reinterpret_cast<char *>(workspace);
+    double *part_x = reinterpret_cast<double *>(ws + base);
+    double *vband = reinterpret_cast<double *>(ws + base + up256(rows_x * npix * sizeof(double)));
+    const int32_t ncol = a.nside > 0 ? npix / 2 : npix;
+    const size_t beam_bytes = up256(beam_workspace_bytes(nt, nf, ncol));
+    if (X) {
+        const bool use_xm = !(flags & SGWB_MAPS_VALU_X) && x_kernel_choice() != kXKernelValu && xm_eligible(a) &&
+                            workspace_bytes >= beam_bytes + xm_workspace_bytes(k0, nt, nf);
+        if (use_xm) {
+            // the dirty map writes per-strip partial sums; one small kernel adds them
+            MapArgs ab = a;
+            ab.band_part = part_x;
+            ab.band_lo = k_lo;
+            ab.band_hi = k_hi;
+            rc = check_hip(launch_dirty_map_mfma(ab, C, w, gamma, tau, X, ws + beam_bytes, stream),
+                           "dirty-map (matrix cores) launch");
+            if (rc) return rc;
+            rc = check_hip(launch_band_partial_finish(part_x, xm_band_rows(a), npix, Xbb, stream), "band finish");
+        } else {
+            rc = check_hip(launch_dirty_map<float>(a, C, w, gamma, tau, X, stream), "dirty-map kernel launch");
+            if (rc) return rc;
+            rc = check_hip(launch_band<float>(X, nullptr, nullptr, nf, npix, k_lo, k_hi, Xbb, nullptr, nullptr, 0,
+                                              stream),
+                           "band kernel launch");
+        }
+        if (rc) return rc;
+    }
+    if (Gam) {
+        rc = check_hip(launch_beam_bf16x3(a, w, gamma, Gam, workspace, default_beam_shape(), stream),
+                       "beam kernel launch");
+        if (rc) return rc;
+        // Gbb from its definition, the band sum moved into the weights (no pass over Gam)
+        rc = check_hip(launch_band_gamma(w, ldc, nt, H, k_lo, k_hi, gamma, npix, vband, Gbb, stream),
+                       "band weights launch");
+        if (rc) return rc;
+    }
+    return SGWB_OK;
+}
+
 size_t sgwb_reduce_band_workspace_size(int32_t npix, int32_t k_lo, int32_t k_hi)
 {
     if (npix < 1 || k_lo < 0 || k_hi <= k_lo) return 0;

@@ -221,4 +221,78 @@ template hipError_t launch_band<float>(const float *, const float *, const float
 template hipError_t launch_band<double>(const double *, const double *, const double *, int32_t, int32_t,
                                         int32_t, int32_t, double *, double *, void *, size_t, hipStream_t);
 
+// Broadband sums from the partial sums the dirty-map and beam kernels write
+// per 64-bin unit: out[p] = sum_{r < nrows} part[r][p], float64 in row order,
+// rounded once.  One thread per pixel, coalesced across pixels.
+__global__ __launch_bounds__(256) void band_partial_finish_kernel(const double *__restrict__ part, int64_t nrows,
+                                                                  int32_t npix, float *__restrict__ out)
+{
+    const int32_t p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= npix) return;
+    double acc = 0.0;
+    for (int64_t r = 0; r < nrows; ++r) acc += part[r * npix + p];
+    out[p] = (float)acc;
+}
+
+hipError_t launch_band_partial_finish(const double *part, int64_t nrows, int32_t npix, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(band_partial_finish_kernel, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, part, nrows,
+                       npix, out);
+    return hipGetLastError();
+}
+
+// v[t] = sum_{c in [klo,khi)} H[c] w[t][c]: one workgroup per segment, per-thread
+// strides over the bins, then a fixed tree (float64).
+__global__ __launch_bounds__(256) void band_weight_kernel(const float *__restrict__ w, int64_t ldw,
+                                                          const float *__restrict__ H, int32_t klo, int32_t khi,
+                                                          double *__restrict__ v)
+{
+    __shared__ double red[256];
+    const float *row = w + (int64_t)blockIdx.x * ldw;
+    double acc = 0.0;
+    for (int32_t c = klo + threadIdx.x; c < khi; c += 256) acc = fma((double)H[c], (double)row[c], acc);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) v[blockIdx.x] = red[0];
+}
+
+// Gbb[p] = sum_t v[t] gamma(t,p)^2 (float64, rounded once): kBandTChunks
+// segment chunks per pixel block write partial sums in segment order, then a
+// second kernel adds the chunks in order.  One thread per pixel, coalesced rows.
+constexpr int kBandTChunks = 32;
+
+__global__ __launch_bounds__(256) void band_gamma_kernel(const float *__restrict__ gamma, int32_t npix, int32_t nt,
+                                                         const double *__restrict__ v, double *__restrict__ part)
+{
+    const int32_t p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= npix) return;
+    const int32_t per = (nt + kBandTChunks - 1) / kBandTChunks;
+    const int32_t t0 = blockIdx.y * per, t1 = min(t0 + per, nt);
+    double acc = 0.0;
+    for (int32_t t = t0; t < t1; ++t) {
+        const double g = (double)gamma[(int64_t)t * npix + p];
+        acc = fma(v[t], g * g, acc);
+    }
+    part[(int64_t)blockIdx.y * npix + p] = acc;
+}
+
+size_t band_gamma_scratch_bytes(int32_t nt, int32_t npix)
+{
+    return ((size_t)nt + (size_t)kBandTChunks * npix) * sizeof(double);
+}
+
+hipError_t launch_band_gamma(const float *w, int64_t ldw, int32_t nt, const float *H, int32_t klo, int32_t khi,
+                             const float *gamma, int32_t npix, double *scratch, float *Gbb, hipStream_t s)
+{
+    double *v = scratch, *part = scratch + nt;
+    hipLaunchKernelGGL(band_weight_kernel, dim3((unsigned)nt), dim3(256), 0, s, w, ldw, H, klo, khi, v);
+    hipLaunchKernelGGL(band_gamma_kernel, dim3((unsigned)((npix + 255) / 256), kBandTChunks), dim3(256), 0, s, gamma,
+                       npix, nt, v, part);
+    return launch_band_partial_finish(part, kBandTChunks, npix, Gbb, s);
+}
+
 }  // namespace sgwb

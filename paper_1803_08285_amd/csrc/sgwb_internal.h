@@ -121,6 +121,10 @@ struct MapArgs {
     double f0, df;
     int32_t unit_c = 0;      // C is not read: C = 1 + 0i, so y = w (real data)
     int32_t accumulate = 0;  // add the dirty map to X instead of writing it
+    // Broadband partial sums written by the matrix-core dirty map (nullptr: none):
+    // band_part[strip][pixel] = sum of the strip's X rows with columns in [band_lo, band_hi).
+    double *band_part = nullptr;
+    int32_t band_lo = 0, band_hi = 0;
 };
 template <typename T>
 hipError_t launch_dirty_map(const MapArgs &a, const T *C, const T *w, const T *gamma,
@@ -135,6 +139,16 @@ struct MapList {
 hipError_t launch_network_sum(const MapList &l, int64_t n, float *out, hipStream_t s);
 hipError_t launch_contract(const float *M, int32_t nf, int32_t npix, const int32_t *pix, int32_t nsel, float *out,
                            hipStream_t s);
+
+// fused broadband sums: out[p] = sum_{r < nrows} part[r][p] (float64, fixed order, rounded once)
+hipError_t launch_band_partial_finish(const double *part, int64_t nrows, int32_t npix, float *out, hipStream_t s);
+int64_t xm_band_rows(const MapArgs &a);    // rows of the dirty map's partial-sum array
+// broadband Fisher diagonal from its definition with the band sum moved into
+// the weights: Gbb[p] = sum_t v[t] gamma(t,p)^2, v[t] = sum_{c in [klo,khi)} H[c] w[t][c]
+// (float64, fixed order, rounded once); scratch: band_gamma_scratch_bytes() of device memory
+size_t band_gamma_scratch_bytes(int32_t nt, int32_t npix);
+hipError_t launch_band_gamma(const float *w, int64_t ldw, int32_t nt, const float *H, int32_t klo, int32_t khi,
+                             const float *gamma, int32_t npix, double *scratch, float *Gbb, hipStream_t s);
 
 // full Fisher matrix of a band for separable weights, and its CG clean map
 size_t fisher_full_workspace_bytes(double f_max, int32_t nbins, int32_t nt, int32_t npix);

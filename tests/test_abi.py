@@ -165,3 +165,34 @@ def test_fisher_full_and_clean_map_validation_on_the_host():
     rc = L.sgwb_clean_map_cg(d, d, 10, 5, d, d, 8, None)
     assert rc == -2
     assert L.sgwb_clean_map_workspace_size(0) == 0 < L.sgwb_clean_map_workspace_size(10)
+
+
+def test_make_maps_band_validation_on_the_host():
+    import paper_1803_08285_amd as sg
+
+    L = sg.lib()
+    fg = sg._FGrid(20.0, 1 / 32)
+    d = ctypes.c_void_p(256)
+    big = 1 << 40
+    # X without Xbb
+    rc = L.sgwb_make_maps_band(d, d, 8, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1, d, 0, 8, d, None, None, None, d,
+                               big, None)
+    assert rc == -1 and b"pairs" in L.sgwb_last_error()
+    # nothing asked for
+    rc = L.sgwb_make_maps_band(d, d, 8, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1, d, 0, 8, None, None, None, None,
+                               d, big, None)
+    assert rc == -1
+    # band beyond the columns
+    rc = L.sgwb_make_maps_band(d, d, 8, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1, d, 0, 9, d, d, d, d, d, big,
+                               None)
+    assert rc == -1 and b"band" in L.sgwb_last_error()
+    # Gbb without H
+    rc = L.sgwb_make_maps_band(d, d, 8, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1, None, 0, 8, d, d, d, d, d, big,
+                               None)
+    assert rc == -1 and b"H" in L.sgwb_last_error()
+    # workspace too small; its size covers make_maps' and grows with the bins
+    rc = L.sgwb_make_maps_band(d, d, 8, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1, d, 0, 8, d, d, d, d, d, 256,
+                               None)
+    assert rc == -2
+    assert L.sgwb_make_maps_band_workspace_size(10, 8, 768, 1) > L.sgwb_make_maps_workspace_size(10, 8, 768, 1)
+    assert L.sgwb_make_maps_band_workspace_size(10, 800, 768, 1) > L.sgwb_make_maps_band_workspace_size(10, 8, 768, 1)
