@@ -125,7 +125,7 @@ def cpu_baseline(inp, wl, target_s=CPU_BASELINE_TARGET_S):
 
 def bench_batched(args, torch, sg):
     """Batched form: three baselines with uneven jobs in one plan (graph replay)
-    against the plain path (one make_maps + reduce_band call per job)."""
+    against the plain path (one make_maps_band call per job)."""
     dev = torch.device("cuda:0")
     jobs, terms = [], 0
     for wl in synth.batched_jobs():
@@ -151,12 +151,13 @@ def bench_batched(args, torch, sg):
     t0 = time.perf_counter()
     plan = sg.Plan(jobs, autotune=True)
     log(f"plan created in {time.perf_counter() - t0:.1f} s: {plan.describe()}")
-    ws = [sg.make_workspace(j.w.shape[0], j.w.shape[1], j.gamma.shape[1], True, device=dev) for j in jobs]
+    ws = [torch.empty(sg.band_maps_workspace_bytes(j.w.shape[0], j.w.shape[1], j.gamma.shape[1], True),
+                      dtype=torch.uint8, device=dev) for j in jobs]
 
     def plain():
         for j, wsp in zip(jobs, ws):
-            sg.make_maps(j.C, j.w, j.fgrid, j.k0, j.gamma, j.tau, out=(j.X, j.G), workspace=wsp)
-            sg.reduce_band(j.X, j.G, j.H, *j.band, out=(j.Xbb, j.Gbb))
+            sg.make_maps_band(j.C, j.w, j.fgrid, j.k0, j.gamma, j.tau, j.H, *j.band, out=(j.X, j.G, j.Xbb, j.Gbb),
+                              workspace=wsp)
 
     def timed(fn, k):
         fn()
@@ -390,8 +391,7 @@ def bench_serve(args, torch, sg):
         if (ds, nside) not in geoms:
             geoms[(ds, nside)] = sg.build_geometry(d.sites, nside, d.tgrid, device=dev)
         g, t = geoms[(ds, nside)]
-        X, G = sg.make_maps(d.C[:, lo:hi], d.w[:, lo:hi], d.fgrid, d.k0 + lo, g, t)
-        sg.reduce_band(X, G, d.H[lo:hi], 0, hi - lo)
+        sg.make_maps_band(d.C[:, lo:hi], d.w[:, lo:hi], d.fgrid, d.k0 + lo, g, t, d.H[lo:hi].contiguous(), 0, hi - lo)
         torch.cuda.synchronize()
 
     for ds in range(3):  # warm the plain path's seeds too

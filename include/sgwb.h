@@ -322,7 +322,9 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
  * the device and the job shapes; SGWB_TUNE_CACHE names the cache file);
  * without it the default schedule is used.  SGWB_PLAN_NO_GRAPH launches the
  * kernels directly instead of replaying a graph.  The schedule never changes
- * a result: maps are bitwise equal to the single-call path.
+ * a result: maps are bitwise equal to the single-call path (sgwb_make_maps_band:
+ * the broadband maps are taken the same way, from the dirty map's per-strip
+ * sums and the weight-side Gbb).
  * plan_create allocates the workspaces and job tables (device memory owned by
  * the plan) and synchronises the device; plan_launch allocates nothing and
  * queues the graph asynchronously on `stream`.

@@ -38,8 +38,10 @@ struct sgwb_plan {
     std::vector<BJob> bjobs;
     BJob *d_bjobs = nullptr;
     int64_t b_wgs = 0;
-    // band
+    // band: per job, the dirty map's per-strip partial sums (matrix-core jobs)
+    // and the scratch of the weight-side broadband Fisher diagonal
     std::vector<size_t> band_off;
+    std::vector<char> use_xm;
     // memory
     void *beam_ws = nullptr, *band_ws = nullptr, *xm_ws = nullptr;
     size_t beam_bytes = 0, band_bytes = 0, xm_bytes = 0;
@@ -148,14 +150,28 @@ static hipError_t enqueue(sgwb_plan *p, hipStream_t s, int parts)
             return e;
     }
     if (parts & 4) {
+        // the same broadband forms as sgwb_make_maps_band, so the bits agree
         for (size_t i = 0; i < p->jobs.size(); ++i) {
             const sgwb_job &j = p->jobs[i];
             if (!j.Xbb && !j.Gbb) continue;
             char *ws = reinterpret_cast<char *>(p->band_ws) + p->band_off[i];
-            const size_t wsz = band_workspace_bytes(j.npix, j.band_lo, j.band_hi);
-            e = launch_band<float>(j.Xbb ? j.X : nullptr, j.Gbb ? j.Gam : nullptr, j.H, j.nf, j.npix, j.band_lo,
-                                   j.band_hi, j.Xbb, j.Gbb, wsz ? ws : nullptr, wsz, s);
-            if (e != hipSuccess) return e;
+            size_t xpart = 0;
+            if (j.Xbb) {
+                if (p->use_xm[i]) {
+                    xpart = (size_t)xm_band_rows(p->args[i]) * j.npix * sizeof(double);
+                    e = launch_band_partial_finish(reinterpret_cast<double *>(ws), xm_band_rows(p->args[i]), j.npix,
+                                                   j.Xbb, s);
+                } else {
+                    e = launch_band<float>(j.X, nullptr, nullptr, j.nf, j.npix, j.band_lo, j.band_hi, j.Xbb, nullptr,
+                                           nullptr, 0, s);
+                }
+                if (e != hipSuccess) return e;
+            }
+            if (j.Gbb) {
+                double *scratch = reinterpret_cast<double *>(ws + (xpart + 255) / 256 * 256);
+                e = launch_band_gamma(j.w, j.ldc, j.nt, j.H, j.band_lo, j.band_hi, j.gamma, j.npix, scratch, j.Gbb, s);
+                if (e != hipSuccess) return e;
+            }
         }
     }
     return hipGetLastError();
@@ -311,10 +327,12 @@ int sgwb_plan_create(const sgwb_job *jobs, int32_t njobs, uint32_t flags, sgwb_p
     std::vector<size_t> beam_off(njobs, 0), xm_off(njobs, 0);
     std::vector<bool> use_xm(njobs, false);
     p->band_off.assign(njobs, 0);
+    p->use_xm.assign(njobs, 0);
     for (int i = 0; i < njobs; ++i) {
         const sgwb_job &j = p->jobs[i];
         if (j.X && xm_eligible(p->args[i]) && !(j.flags & SGWB_MAPS_VALU_X)) {
             use_xm[i] = true;
+            p->use_xm[i] = 1;
             xm_off[i] = p->xm_bytes;
             p->xm_bytes += (xm_workspace_bytes(j.k0, j.nt, j.nf) + 255) / 256 * 256;
         }
@@ -325,7 +343,11 @@ int sgwb_plan_create(const sgwb_job *jobs, int32_t njobs, uint32_t flags, sgwb_p
         }
         if (j.Xbb || j.Gbb) {
             p->band_off[i] = p->band_bytes;
-            p->band_bytes += (band_workspace_bytes(j.npix, j.band_lo, j.band_hi) + 255) / 256 * 256;
+            size_t n = 0;
+            if (j.Xbb && use_xm[i]) n += (size_t)xm_band_rows(p->args[i]) * j.npix * sizeof(double);
+            n = (n + 255) / 256 * 256;
+            if (j.Gbb) n += band_gamma_scratch_bytes(j.nt, j.npix);
+            p->band_bytes += (n + 255) / 256 * 256;
         }
     }
     hipError_t e = hipSuccess;
@@ -357,6 +379,11 @@ int sgwb_plan_create(const sgwb_job *jobs, int32_t njobs, uint32_t flags, sgwb_p
         if (use_xm[i]) {
             XmJob x;
             fill_xmjob(&x, p->args[i], j.C, j.w, j.gamma, j.tau, j.X, reinterpret_cast<char *>(p->xm_ws) + xm_off[i]);
+            if (j.Xbb) {  // the tiles write per-strip band sums
+                x.x.a.band_part = reinterpret_cast<double *>(reinterpret_cast<char *>(p->band_ws) + p->band_off[i]);
+                x.x.a.band_lo = j.band_lo;
+                x.x.a.band_hi = j.band_hi;
+            }
             p->xmjobs.push_back(x);
         }
         if (j.Gam) {

@@ -124,9 +124,9 @@ struct Query {
     int status = SGWB_OK;
     int slot = -1;
     Clock::time_point t_submit, t_start, t_done;
-    char *X = nullptr, *G = nullptr, *ws = nullptr, *bws = nullptr;  // narrowband buffers (arena)
+    char *X = nullptr, *G = nullptr, *ws = nullptr;  // narrowband buffers (arena)
     float *Xbb = nullptr, *Gbb = nullptr;                             // result (arena)
-    size_t bws_bytes = 0, ws_bytes = 0;
+    size_t ws_bytes = 0;
     int32_t npix = 0;
 };
 
@@ -166,16 +166,15 @@ double secs(const sgwb_server *s, Clock::time_point t)
     return std::chrono::duration<double>(t - s->t0).count();
 }
 
-size_t query_footprint(const sgwb_server *s, const sgwb_query &q, size_t *ws_bytes, size_t *bws_bytes)
+size_t query_footprint(const sgwb_server *s, const sgwb_query &q, size_t *ws_bytes)
 {
     const sgwb_dataset &d = s->data[q.dataset];
     const int64_t npix = 12LL * q.nside * q.nside;
     const int32_t nf = q.k_hi - q.k_lo;
     const size_t maps = (size_t)nf * npix * sizeof(float);
-    *ws_bytes = sgwb_make_maps_workspace_size(d.tg.nt, nf, (int32_t)npix, SGWB_MAPS_ANTIPODAL);
-    *bws_bytes = band_workspace_bytes((int32_t)npix, 0, nf);
+    *ws_bytes = sgwb_make_maps_band_workspace_size(d.tg.nt, nf, (int32_t)npix, SGWB_MAPS_ANTIPODAL);
     auto up = [](size_t n) { return (n + 255) / 256 * 256; };
-    return 2 * up(maps) + up(*ws_bytes) + up(*bws_bytes) + 2 * up(npix * sizeof(float));
+    return 2 * up(maps) + up(*ws_bytes) + 2 * up(npix * sizeof(float));
 }
 
 size_t geom_bytes(const sgwb_dataset &d, int nside)
@@ -239,20 +238,16 @@ int launch_query(sgwb_server *s, Query &q, int k)
     q.X = s->arena.alloc(maps);
     q.G = s->arena.alloc(maps);
     q.ws = s->arena.alloc(q.ws_bytes);
-    q.bws = s->arena.alloc(q.bws_bytes);
     q.Xbb = reinterpret_cast<float *>(s->arena.alloc(npix * sizeof(float)));
     q.Gbb = reinterpret_cast<float *>(s->arena.alloc(npix * sizeof(float)));
-    if (!q.X || !q.G || !q.ws || !q.bws || !q.Xbb || !q.Gbb)
+    if (!q.X || !q.G || !q.ws || !q.Xbb || !q.Gbb)
         return set_error(SGWB_ENOMEM, "server: arena exhausted");
     q.npix = npix;
     const float *C = d.C + 2 * (int64_t)q.q.k_lo;
     const float *w = d.w + q.q.k_lo;
-    rc = sgwb_make_maps(C, w, d.ldc, d.tg.nt, nf, &d.fg, d.k0 + q.q.k_lo, g->gamma, g->tau, npix,
-                        SGWB_MAPS_ANTIPODAL, reinterpret_cast<float *>(q.X), reinterpret_cast<float *>(q.G), q.ws,
-                        q.ws_bytes, sl.stream);
-    if (rc) return rc;
-    rc = sgwb_reduce_band(reinterpret_cast<float *>(q.X), reinterpret_cast<float *>(q.G), d.H + q.q.k_lo, nf, npix,
-                          0, nf, q.Xbb, q.Gbb, q.bws, q.bws_bytes, sl.stream);
+    rc = sgwb_make_maps_band(C, w, d.ldc, d.tg.nt, nf, &d.fg, d.k0 + q.q.k_lo, g->gamma, g->tau, npix,
+                             SGWB_MAPS_ANTIPODAL, d.H + q.q.k_lo, 0, nf, reinterpret_cast<float *>(q.X),
+                             reinterpret_cast<float *>(q.G), q.Xbb, q.Gbb, q.ws, q.ws_bytes, sl.stream);
     if (rc) return rc;
     if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return check_hip(hipGetLastError(), "server: record");
     sl.ticket = q.ticket;
@@ -267,8 +262,7 @@ void release_narrowband(sgwb_server *s, Query &q)
     s->arena.release(q.X);
     s->arena.release(q.G);
     s->arena.release(q.ws);
-    s->arena.release(q.bws);
-    q.X = q.G = q.ws = q.bws = nullptr;
+    q.X = q.G = q.ws = nullptr;
 }
 
 void worker_loop(sgwb_server *s)
@@ -306,7 +300,7 @@ void worker_loop(sgwb_server *s)
                 }
             if (free_slot < 0) break;
             Query &q = s->queries[s->pending.front()];
-            size_t need = query_footprint(s, q.q, &q.ws_bytes, &q.bws_bytes);
+            size_t need = query_footprint(s, q.q, &q.ws_bytes);
             const auto gk = std::make_pair(q.q.dataset, q.q.nside);
             if (!s->geoms.count(gk)) need += geom_bytes(s->data[q.q.dataset], q.q.nside);
             if (need > s->arena.size()) {

@@ -1,9 +1,9 @@
 """Batched plans on the GPU: several baselines, resolutions and uneven bands in
 one persistent launch per kernel, replayed from a HIP graph.
 
-The plan's maps must be bitwise equal to the single-call path (which the
-parity tests compare with the oracle), on every graph replay, with eager work
-between replays; autotuned, cached and graph-free plans must agree too.
+The plan's maps must be bitwise equal to the single-call path (make_maps_band,
+which the parity tests compare with the oracle), on every graph replay, with
+eager work between replays; autotuned, cached and graph-free plans must agree too.
 """
 import numpy as np
 import pytest
@@ -51,8 +51,7 @@ def _make_jobs(sg):
         Gbb = torch.full((npix,), float("nan"), device="cuda")
         jobs.append(sg.Job(Cd, wd, sg.FGrid(F0, DF), k0, g, t, X=X, G=G, H=H, band=band, Xbb=Xbb, Gbb=Gbb,
                            antipodal=anti))
-        Xr, Gr = sg.make_maps(Cd, wd, sg.FGrid(F0, DF), k0, g, t, antipodal=anti)
-        Xbr, Gbr = sg.reduce_band(Xr, Gr, H, *band)
+        Xr, Gr, Xbr, Gbr = sg.make_maps_band(Cd, wd, sg.FGrid(F0, DF), k0, g, t, H, *band, antipodal=anti)
         refs.append((Xr, Gr, Xbr, Gbr))
         host.append((C, w, g, t, k0, DF))
     torch.cuda.synchronize()

@@ -44,8 +44,8 @@ QUERIES = [(0, 8, 0, 700), (1, 16, 100, 101), (2, 4, 64, 1500), (0, 2, 5, 69), (
 
 def _direct(sg, d, nside, lo, hi):
     g, t = sg.build_geometry(d.sites, nside, d.tgrid)
-    X, G = sg.make_maps(d.C[:, lo:hi], d.w[:, lo:hi], d.fgrid, d.k0 + lo, g, t)
-    Xbb, Gbb = sg.reduce_band(X, G, d.H[lo:hi].contiguous(), 0, hi - lo)
+    _, _, Xbb, Gbb = sg.make_maps_band(d.C[:, lo:hi], d.w[:, lo:hi], d.fgrid, d.k0 + lo, g, t,
+                                       d.H[lo:hi].contiguous(), 0, hi - lo)
     torch.cuda.synchronize()
     return Xbb, Gbb
 
