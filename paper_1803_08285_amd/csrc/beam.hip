@@ -9,7 +9,8 @@
 //     K-step, lane l holds the 8 consecutive segments 8 (l / 32) .. +7 of row
 //     32 * block + l % 32, exactly the operand layout of
 //     v_mfma_f32_32x32x16_bf16, so the GEMM loads each fragment with one
-//     16-byte load per lane;
+//     16-byte load per lane (with 2 x 4 wave tiles the four waves of a
+//     workgroup share each K-step's pixel-side fragments through LDS);
 //   * the GEMM accumulates hi.hi + hi.lo + lo.hi in float32 (lo.lo, below
 //     2^-16 relative, is dropped) in a fixed K order;
 //   * with antipodal seeds only the northern half of the pixels is computed
