@@ -46,7 +46,13 @@ __device__ inline void split8(const float v[8], uint4 *hi, uint4 *lo)
     *lo = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16), l[6] | (l[7] << 16));
 }
 
-// Fragment array: [blk][ks][part 0 = hi, 1 = lo][64 lanes] of uint4.
+// Fragment array: [blk][ks][part 0 = hi, 1 = lo][64 lanes] of uint4, with
+// the block count padded to whole 4-block tiles; the padding blocks are zero.
+constexpr int64_t kTileBlocks = 4;
+__host__ __device__ inline int64_t padded_blocks(int64_t nblk)
+{
+    return (nblk + kTileBlocks - 1) / kTileBlocks * kTileBlocks;
+}
 __host__ __device__ inline int64_t frag_index(int64_t blk, int64_t ks, int part, int lane, int64_t nks)
 {
     return ((blk * nks + ks) * 2 + part) * 64 + lane;
@@ -89,25 +95,45 @@ struct Frags {
     uint4 a[WM][2], b[WN][2];
 };
 
+// The fragment arrays arrive through a by-value job descriptor, so the
+// compiler cannot tell that they live in global memory and would read them
+// with flat loads, which also count against the LDS counter and must wait for
+// the direct global -> LDS copies.  Reading through an explicit global
+// pointer keeps those loads on the vector-memory counter alone.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ inline const __attribute__((address_space(1))) u32x4 *as_global(const uint4 *p)
+{
+    return (const __attribute__((address_space(1))) u32x4 *)p;
+}
+
+// Fragment (blk, ks, part) for this lane.  The arrays hold whole tiles
+// (padded_blocks), so every block a wave tile touches exists and the loads
+// need no condition: a condition would turn into a branch around each load
+// and keep the compiler from counting loads in flight.
+__device__ inline uint4 fetch_frag(const uint4 *F, int64_t blk, int64_t ks, int part, int lane, int64_t nks)
+{
+    const u32x4 v = as_global(F)[frag_index(blk, ks, part, lane, nks)];
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 template <int WM, int WN>
 __device__ inline void load_frags(Frags<WM, WN> &f, const uint4 *__restrict__ Wf, const uint4 *__restrict__ Gf,
                                   int64_t tm, int64_t tn, int64_t ks, const FragDims &fm, const FragDims &fn,
                                   int lane)
 {
-    const uint4 zero4 = make_uint4(0, 0, 0, 0);
 #pragma unroll
     for (int i = 0; i < WM; ++i) {
         const int64_t mb = tm * WM + i;
 #pragma unroll
         for (int part = 0; part < 2; ++part)
-            f.a[i][part] = mb < fm.nblk ? Wf[frag_index(mb, ks, part, lane, fm.nks)] : zero4;
+            f.a[i][part] = fetch_frag(Wf, mb, ks, part, lane, fm.nks);
     }
 #pragma unroll
     for (int j = 0; j < WN; ++j) {
         const int64_t nb = tn * WN + j;
 #pragma unroll
         for (int part = 0; part < 2; ++part)
-            f.b[j][part] = nb < fn.nblk ? Gf[frag_index(nb, ks, part, lane, fn.nks)] : zero4;
+            f.b[j][part] = fetch_frag(Gf, nb, ks, part, lane, fn.nks);
     }
 }
 
@@ -200,18 +226,21 @@ __device__ inline void beam_wave_tile_direct(const BJob &jb, int64_t tm, int64_t
 }
 
 constexpr int kVmcnt0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt left at their maxima
+constexpr int kVmcnt2 = 0x0F72;  // s_waitcnt vmcnt(2)
 
 // The pixel-side fragments of one K-step for the workgroup's column tile tn
 // (2 WN fragments of 64 x 16 B: blocks tn WN + j, hi and lo), copied global ->
-// LDS directly; wave w moves fragments w, w + 4, ...  Blocks past the last
-// are clamped to it (their columns are never stored).
+// LDS directly; wave w moves fragments w, w + 4, ... (the same number per
+// wave; the padding blocks past the last are zero).
 template <int WN>
 __device__ inline void stage_bfrags(const uint4 *__restrict__ Gf, int64_t tn, int64_t ks, const FragDims &fn,
                                     int wave, int lane, uint4 (*dst)[64])
 {
+    static_assert(2 * WN % kWavesPerWg == 0, "every wave moves the same number of fragments");
 #pragma unroll
-    for (int f = wave; f < 2 * WN; f += kWavesPerWg) {
-        const int64_t nb = min(tn * WN + f / 2, fn.nblk - 1);
+    for (int r = 0; r < 2 * WN / kWavesPerWg; ++r) {
+        const int f = wave + r * kWavesPerWg;
+        const int64_t nb = tn * WN + f / 2;
         __builtin_amdgcn_global_load_lds(Gf + frag_index(nb, ks, f % 2, lane, fn.nks), &dst[f][0], 16, 0, 0);
     }
 }
@@ -226,7 +255,7 @@ __device__ inline void stage_bfrags(const uint4 *__restrict__ Gf, int64_t tn, in
 // stores nothing.
 template <int WM, int WN>
 __device__ inline void beam_wave_tile(const BJob &jb, int64_t tm, int64_t tn, int lane, uint4 (*Bs0)[64],
-                                      uint4 (*Bs1)[64])
+                                      uint4 (*Bs1)[64], uint4 (*Bs2)[64])
 {
     const FragDims fm = jb.fm, fn = jb.fn;
     const int64_t nks = fm.nks;
@@ -239,28 +268,38 @@ __device__ inline void beam_wave_tile(const BJob &jb, int64_t tm, int64_t tn, in
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-    const uint4 zero4 = make_uint4(0, 0, 0, 0);
+    // a wave past the last bin tile multiplies the last tile's fragments
+    const int64_t tml = min(tm, (fm.nblk + WM - 1) / WM - 1);
     uint4 a[WM][2], an[WM][2];
     auto load_a = [&](int64_t ks, uint4 (&d)[WM][2]) {
 #pragma unroll
         for (int i = 0; i < WM; ++i) {
-            const int64_t mb = tm * WM + i;
+            const int64_t mb = tml * WM + i;
 #pragma unroll
             for (int part = 0; part < 2; ++part)
-                d[i][part] = mb < fm.nblk ? jb.Wf[frag_index(mb, ks, part, lane, fm.nks)] : zero4;
+                d[i][part] = fetch_frag(jb.Wf, mb, ks, part, lane, fm.nks);
         }
     };
     __syncthreads();  // the previous tile's readers of the buffers are done
     load_a(0, a);
     stage_bfrags<WN>(jb.Gf, tn, 0, fn, wave, lane, Bs0);
+    if (nks > 1) stage_bfrags<WN>(jb.Gf, tn, 1, fn, wave, lane, Bs1);
     __builtin_amdgcn_s_waitcnt(kVmcnt0);
     __syncthreads();
-    auto step = [&](int64_t ks, uint4 (*Bcur)[64], uint4 (*Bnext)[64]) {
-        const bool more = ks + 1 < nks;
-        if (more) {
-            stage_bfrags<WN>(jb.Gf, tn, ks + 1, fn, wave, lane, Bnext);
-            load_a(ks + 1, an);
-        }
+    // Three pixel-side buffers: step ks reads Bcur (K-step ks) while the copy
+    // of K-step ks + 2 goes into Bnext2 (read last in step ks - 1, before the
+    // previous barrier); the bin-side fragments of ks + 1 are loaded first, so
+    // waiting until only that step's own copies (kStageOps per wave, issued
+    // last) are in flight leaves everything of ks + 1 landed.
+    constexpr int kStageOps = (2 * WN + kWavesPerWg - 1) / kWavesPerWg;
+    static_assert(kStageOps == 2, "the wait below counts two copies per wave");
+    auto step = [&](int64_t ks, uint4 (*Bcur)[64], uint4 (*Bnext2)[64]) {
+        // past the end the loads repeat the last K-step into registers and a
+        // buffer that nothing reads any more, so every step issues the same
+        // operations and the wait below is one fixed count
+        load_a(min(ks + 1, nks - 1), an);
+        stage_bfrags<WN>(jb.Gf, tn, min(ks + 2, nks - 1), fn, wave, lane, Bnext2);
+        __builtin_amdgcn_sched_barrier(0);  // the loads go out before the products
         uint4 b[WN][2];
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
@@ -278,20 +317,26 @@ __device__ inline void beam_wave_tile(const BJob &jb, int64_t tm, int64_t tn, in
                     const bf16x8 bv = __builtin_bit_cast(bf16x8, b[j][part == 1 ? 1 : 0]);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[i][j], 0, 0, 0);
                 }
-        if (more) {
 #pragma unroll
-            for (int i = 0; i < WM; ++i) {
-                a[i][0] = an[i][0];
-                a[i][1] = an[i][1];
-            }
+        for (int i = 0; i < WM; ++i) {
+            a[i][0] = an[i][0];
+            a[i][1] = an[i][1];
         }
-        __builtin_amdgcn_s_waitcnt(kVmcnt0);  // the next K-step's fragments have landed
-        __syncthreads();
+        // the next K-step's fragments have landed (those of ks + 2 may still
+        // fly); the reads of Bcur are done before any wave copies into it again
+        __builtin_amdgcn_sched_barrier(0);  // the wait stays after the products
+        __builtin_amdgcn_s_waitcnt(kVmcnt2);
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
     };
-    for (int64_t ks = 0; ks < nks; ks += 2) {
-        step(ks, Bs0, Bs1);
-        if (ks + 1 < nks) step(ks + 1, Bs1, Bs0);
+    int64_t ks = 0;
+    for (; ks + 3 <= nks; ks += 3) {
+        step(ks, Bs0, Bs2);
+        step(ks + 1, Bs1, Bs0);
+        step(ks + 2, Bs2, Bs1);
     }
+    if (ks < nks) step(ks, Bs0, Bs2);
+    if (ks + 1 < nks) step(ks + 1, Bs1, Bs0);
+    __builtin_amdgcn_s_waitcnt(kVmcnt0);  // the repeated copies of the last steps
 
     // Accumulator layout of the 32x32 MFMA: lane l holds column l % 32 and rows
     // 8 (r / 4) + 4 (l / 32) + r % 4 for r = 0..15.
@@ -318,7 +363,8 @@ __device__ inline void beam_wave_tile(const BJob &jb, int64_t tm, int64_t tn, in
 template <int WM, int WN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 2 ? 2 : 1))) void beam_gemm_kernel(BJob jb)
 {
-    __shared__ uint4 Bs0[2 * WN][64], Bs1[2 * WN][64];
+    static_assert(kTileBlocks % WM == 0 && kTileBlocks % WN == 0, "wave tiles stay inside the padded arrays");
+    __shared__ uint4 Bs0[2 * WN][64], Bs1[2 * WN][64], Bs2[2 * WN][64];
     const int64_t tiles_m = (jb.fm.nblk + WM - 1) / WM;
     const int64_t tiles_n = (jb.fn.nblk + WN - 1) / WN;
     int64_t tm, tn;
@@ -326,7 +372,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 2 ? 2
     if constexpr (WM == 4) {
         if (tm < tiles_m) beam_wave_tile_direct<WM, WN>(jb, tm, tn, threadIdx.x & 63);
     } else {
-        beam_wave_tile<WM, WN>(jb, tm, tn, threadIdx.x & 63, Bs0, Bs1);
+        beam_wave_tile<WM, WN>(jb, tm, tn, threadIdx.x & 63, Bs0, Bs1, Bs2);
     }
 }
 
@@ -337,7 +383,7 @@ template <int WM, int WN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 2 ? 2 : 1))) void beam_gemm_batched_kernel(const BJob *__restrict__ jobs, int32_t njobs,
                                                                 int64_t nwg)
 {
-    __shared__ uint4 Bs0[2 * WN][64], Bs1[2 * WN][64];
+    __shared__ uint4 Bs0[2 * WN][64], Bs1[2 * WN][64], Bs2[2 * WN][64];
     for (int64_t g = blockIdx.x; g < nwg; g += gridDim.x) {
         int j = 0;
         while (j + 1 < njobs && g >= jobs[j + 1].wg_begin) ++j;
@@ -349,7 +395,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 2 ? 2
             if constexpr (WM == 4) {
                 if (tm < tiles_m) beam_wave_tile_direct<WM, WN>(jb, tm, tn, threadIdx.x & 63);
             } else {
-                beam_wave_tile<WM, WN>(jb, tm, tn, threadIdx.x & 63, Bs0, Bs1);
+                beam_wave_tile<WM, WN>(jb, tm, tn, threadIdx.x & 63, Bs0, Bs1, Bs2);
             }
         }
     }
@@ -358,7 +404,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WM == 2 ? 2
 size_t beam_workspace_bytes(int32_t nt, int32_t nf, int32_t ncol)
 {
     const FragDims fm = frag_dims(nf, nt), fn = frag_dims(ncol, nt);
-    return (size_t)(fm.nblk + fn.nblk) * (size_t)fm.nks * 2 * 64 * sizeof(uint4);
+    return (size_t)(padded_blocks(fm.nblk) + padded_blocks(fn.nblk)) * (size_t)fm.nks * 2 * 64 * sizeof(uint4);
 }
 
 void fill_bjob(BJob *jb, const MapArgs &a, const float *w, const float *gamma, float *Gam, void *work)
@@ -368,7 +414,7 @@ void fill_bjob(BJob *jb, const MapArgs &a, const float *w, const float *gamma, f
     jb->fm = frag_dims(a.nf, a.nt);
     jb->fn = frag_dims(jb->ncol, a.nt);
     jb->Wf = reinterpret_cast<uint4 *>(work);
-    jb->Gf = const_cast<uint4 *>(jb->Wf) + jb->fm.nblk * jb->fm.nks * 2 * 64;
+    jb->Gf = const_cast<uint4 *>(jb->Wf) + padded_blocks(jb->fm.nblk) * jb->fm.nks * 2 * 64;
     jb->nf = a.nf;
     jb->npix = a.npix;
     jb->nside = pair ? a.nside : 0;
@@ -388,11 +434,13 @@ int64_t bjob_workgroups(const BJob &jb, int shape)
 
 hipError_t launch_beam_prep(const BJob &jb, hipStream_t s)
 {
-    const int64_t nw = jb.fm.nblk * jb.fm.nks * 64, ng = jb.fn.nblk * jb.fn.nks * 64;
+    // the padding blocks are written too (their columns lie past the data: zeros)
+    const FragDims pm{padded_blocks(jb.fm.nblk), jb.fm.nks}, pn{padded_blocks(jb.fn.nblk), jb.fn.nks};
+    const int64_t nw = pm.nblk * pm.nks * 64, ng = pn.nblk * pn.nks * 64;
     hipLaunchKernelGGL(prep_frag_kernel<false>, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, jb.w, jb.ldw,
-                       jb.nt, (int64_t)jb.nf, jb.fm, const_cast<uint4 *>(jb.Wf));
+                       jb.nt, (int64_t)jb.nf, pm, const_cast<uint4 *>(jb.Wf));
     hipLaunchKernelGGL(prep_frag_kernel<true>, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, jb.gamma,
-                       (int64_t)jb.npix, jb.nt, jb.ncol, jb.fn, const_cast<uint4 *>(jb.Gf));
+                       (int64_t)jb.npix, jb.nt, jb.ncol, pn, const_cast<uint4 *>(jb.Gf));
     return hipGetLastError();
 }
 
