@@ -221,39 +221,54 @@ template hipError_t launch_band<float>(const float *, const float *, const float
 template hipError_t launch_band<double>(const double *, const double *, const double *, int32_t, int32_t,
                                         int32_t, int32_t, double *, double *, void *, size_t, hipStream_t);
 
-// Broadband sums from the partial sums the dirty-map and beam kernels write
-// per 64-bin unit: out[p] = sum_{r < nrows} part[r][p], float64 in row order,
-// rounded once.  One thread per pixel, coalesced across pixels.
-__global__ __launch_bounds__(256) void band_partial_finish_kernel(const double *__restrict__ part, int64_t nrows,
-                                                                  int32_t npix, float *__restrict__ out)
+// Broadband sums from partial sums written per 64-bin strip (dirty map) or per
+// segment chunk (Fisher diagonal): out[p] = sum_{r < nrows} part[r][p] in
+// float64, rounded once.  A workgroup takes 64 pixels (one per lane); wave w
+// sums rows w, w + 8, ... in order and the eight partial sums are added in
+// wave order: one fixed order for every call.
+constexpr int kFinishWaves = 8;
+
+__global__ __launch_bounds__(64 * kFinishWaves) void band_partial_finish_kernel(const double *__restrict__ part,
+                                                                                int64_t nrows, int32_t npix,
+                                                                                float *__restrict__ out)
 {
-    const int32_t p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= npix) return;
+    __shared__ double red[kFinishWaves][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int32_t p = blockIdx.x * 64 + lane;
     double acc = 0.0;
-    for (int64_t r = 0; r < nrows; ++r) acc += part[r * npix + p];
-    out[p] = (float)acc;
+    if (p < npix)
+        for (int64_t r = wv; r < nrows; r += kFinishWaves) acc += part[r * npix + p];
+    red[wv][lane] = acc;
+    __syncthreads();
+    if (wv != 0 || p >= npix) return;
+    double sum = red[0][lane];
+#pragma unroll
+    for (int k = 1; k < kFinishWaves; ++k) sum += red[k][lane];
+    out[p] = (float)sum;
 }
 
 hipError_t launch_band_partial_finish(const double *part, int64_t nrows, int32_t npix, float *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(band_partial_finish_kernel, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, part, nrows,
-                       npix, out);
+    hipLaunchKernelGGL(band_partial_finish_kernel, dim3((unsigned)((npix + 63) / 64)), dim3(64 * kFinishWaves), 0, s,
+                       part, nrows, npix, out);
     return hipGetLastError();
 }
 
-// v[t] = sum_{c in [klo,khi)} H[c] w[t][c]: one workgroup per segment, per-thread
-// strides over the bins, then a fixed tree (float64).
-__global__ __launch_bounds__(256) void band_weight_kernel(const float *__restrict__ w, int64_t ldw,
-                                                          const float *__restrict__ H, int32_t klo, int32_t khi,
-                                                          double *__restrict__ v)
+// v[t] = sum_{c in [klo,khi)} H[c] w[t][c]: one workgroup of 1024 threads per
+// segment, per-thread strides over the bins, then a fixed tree (float64).
+constexpr int kWeightThreads = 1024;
+
+__global__ __launch_bounds__(kWeightThreads) void band_weight_kernel(const float *__restrict__ w, int64_t ldw,
+                                                                     const float *__restrict__ H, int32_t klo,
+                                                                     int32_t khi, double *__restrict__ v)
 {
-    __shared__ double red[256];
+    __shared__ double red[kWeightThreads];
     const float *row = w + (int64_t)blockIdx.x * ldw;
     double acc = 0.0;
-    for (int32_t c = klo + threadIdx.x; c < khi; c += 256) acc = fma((double)H[c], (double)row[c], acc);
+    for (int32_t c = klo + threadIdx.x; c < khi; c += kWeightThreads) acc = fma((double)H[c], (double)row[c], acc);
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
+    for (int st = kWeightThreads / 2; st > 0; st >>= 1) {
         if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
@@ -289,7 +304,7 @@ hipError_t launch_band_gamma(const float *w, int64_t ldw, int32_t nt, const floa
                              const float *gamma, int32_t npix, double *scratch, float *Gbb, hipStream_t s)
 {
     double *v = scratch, *part = scratch + nt;
-    hipLaunchKernelGGL(band_weight_kernel, dim3((unsigned)nt), dim3(256), 0, s, w, ldw, H, klo, khi, v);
+    hipLaunchKernelGGL(band_weight_kernel, dim3((unsigned)nt), dim3(kWeightThreads), 0, s, w, ldw, H, klo, khi, v);
     hipLaunchKernelGGL(band_gamma_kernel, dim3((unsigned)((npix + 255) / 256), kBandTChunks), dim3(256), 0, s, gamma,
                        npix, nt, v, part);
     return launch_band_partial_finish(part, kBandTChunks, npix, Gbb, s);
