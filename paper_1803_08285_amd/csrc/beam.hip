@@ -230,8 +230,9 @@ constexpr int kVmcnt2 = 0x0F72;  // s_waitcnt vmcnt(2)
 
 // The pixel-side fragments of one K-step for the workgroup's column tile tn
 // (2 WN fragments of 64 x 16 B: blocks tn WN + j, hi and lo), copied global ->
-// LDS directly; wave w moves fragments w, w + 4, ... (the same number per
-// wave; the padding blocks past the last are zero).
+// LDS directly into slot part WN + j (the hi parts, which the first products
+// use, first); wave w moves fragments w, w + 4, ... (the same number per wave;
+// the padding blocks past the last are zero).
 template <int WN>
 __device__ inline void stage_bfrags(const uint4 *__restrict__ Gf, int64_t tn, int64_t ks, const FragDims &fn,
                                     int wave, int lane, uint4 (*dst)[64])
@@ -240,8 +241,9 @@ __device__ inline void stage_bfrags(const uint4 *__restrict__ Gf, int64_t tn, in
 #pragma unroll
     for (int r = 0; r < 2 * WN / kWavesPerWg; ++r) {
         const int f = wave + r * kWavesPerWg;
-        const int64_t nb = tn * WN + f / 2;
-        __builtin_amdgcn_global_load_lds(Gf + frag_index(nb, ks, f % 2, lane, fn.nks), &dst[f][0], 16, 0, 0);
+        const int j = f / 2, part = f % 2;
+        __builtin_amdgcn_global_load_lds(Gf + frag_index(tn * WN + j, ks, part, lane, fn.nks), &dst[part * WN + j][0],
+                                         16, 0, 0);
     }
 }
 
@@ -300,12 +302,12 @@ __device__ inline void beam_wave_tile(const BJob &jb, int64_t tm, int64_t tn, in
         load_a(min(ks + 1, nks - 1), an);
         stage_bfrags<WN>(jb.Gf, tn, min(ks + 2, nks - 1), fn, wave, lane, Bnext2);
         __builtin_amdgcn_sched_barrier(0);  // the loads go out before the products
+        // hi parts first: the first products (lo.hi) need only those
         uint4 b[WN][2];
 #pragma unroll
-        for (int j = 0; j < WN; ++j) {
-            b[j][0] = Bcur[2 * j][lane];
-            b[j][1] = Bcur[2 * j + 1][lane];
-        }
+        for (int part = 0; part < 2; ++part)
+#pragma unroll
+            for (int j = 0; j < WN; ++j) b[j][part] = Bcur[part * WN + j][lane];
         // lo.hi, then hi.lo, then hi.hi: smallest terms first, fixed order
 #pragma unroll
         for (int part = 0; part < 3; ++part)
