@@ -107,6 +107,27 @@ __device__ inline void anchor4(double g, double x4, double *zr, double *zi)
     *zi = g * s;
 }
 
+// Global-memory accesses.  The multi-job kernel reads its pointers out of a
+// job table, so the compiler cannot tell them from LDS pointers and would use
+// flat instructions, which count against the LDS counter as well; through
+// these every access is a plain global one.
+template <typename T>
+__device__ inline __attribute__((address_space(1))) T *gmem(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+template <typename C2>
+__device__ inline C2 gload_c(const C2 *p, int64_t i)
+{
+    typedef decltype(p->x) R;
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    const v2 v = ((const __attribute__((address_space(1))) v2 *)p)[i];
+    C2 r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
+
 // One tile: 256 pixel columns (coltile) x one S-bin strip (absolute index strip).
 // Called by every thread of a 256-thread workgroup; ys is the workgroup's LDS stage.
 template <typename T, bool PAIR>
@@ -146,11 +167,11 @@ __device__ inline void dirty_map_tile(const MapArgs &a, int64_t strip, int64_t c
             y.y = T(0);
             if (tt < tn && c >= 0 && c < a.nf) {
                 const int64_t off = (int64_t)(tc + tt) * a.ldc + c;
-                const T wv = w[off];
+                const T wv = gmem(w)[off];
                 if (a.unit_c) {
                     y.x = wv;
                 } else {
-                    const C2 cv = C[off];
+                    const C2 cv = gload_c(C, off);
                     y.x = wv * cv.x;
                     y.y = wv * cv.y;
                 }
@@ -161,8 +182,8 @@ __device__ inline void dirty_map_tile(const MapArgs &a, int64_t strip, int64_t c
         if (!active) continue;
         for (int tt = 0; tt < tn; ++tt) {
             const int64_t g_off = (int64_t)(tc + tt) * a.npix + pcol;
-            const T g = gamma[g_off];
-            const double ta = tau[g_off];
+            const T g = gmem(gamma)[g_off];
+            const double ta = gmem(tau)[g_off];
             T zr, zi, er, ei;
             anchor4(g, fa4 * ta, &zr, &zi);
             rotor((T)(two_pi_df * ta), &er, &ei);
@@ -193,7 +214,7 @@ __device__ inline void dirty_map_tile(const MapArgs &a, int64_t strip, int64_t c
     for (int j = 0; j < S; ++j) {
         const int64_t c = c0 + j;
         if (c < 0 || c >= a.nf) continue;
-        T *row = X + c * (int64_t)a.npix;
+        auto row = gmem(X + c * (int64_t)a.npix);
         if (PAIR) {
             const T xa = acc_a[j] - acc_b[j], xb = acc_a[j] + acc_b[j];
             row[col] = a.accumulate ? row[col] + xa : xa;
