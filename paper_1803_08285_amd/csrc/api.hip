@@ -221,7 +221,7 @@ size_t sgwb_make_maps_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint3
     const int32_t ncol = (flags & SGWB_MAPS_ANTIPODAL) ? npix / 2 : npix;
     size_t n = up256(beam_workspace_bytes(nt, nf, ncol));
     // room for the matrix-core dirty map (largest strip count over all k0)
-    if (flags & SGWB_MAPS_ANTIPODAL) n += up256(xm_workspace_bytes(63, nt, nf));
+    if (flags & SGWB_MAPS_ANTIPODAL) n += up256(xm_workspace_bytes(63, nt, nf, npix));
     return n;
 }
 
@@ -239,7 +239,7 @@ int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int3
         return set_error(SGWB_ENOMEM, "make_maps: workspace of %zu bytes needed, %zu given",
                          sgwb_make_maps_workspace_size(nt, nf, npix, flags), workspace ? workspace_bytes : (size_t)0);
     if (X) {
-        const size_t xm_bytes = xm_workspace_bytes(k0, nt, nf);
+        const size_t xm_bytes = xm_workspace_bytes(k0, nt, nf, npix);
         const bool use_xm = !(flags & SGWB_MAPS_VALU_X) && x_kernel_choice() != kXKernelValu && xm_eligible(a) &&
                             workspace && workspace_bytes >= beam_bytes + xm_bytes;
         if (use_xm)
@@ -262,7 +262,7 @@ size_t sgwb_fisher_overlap_workspace_size(int32_t nt, int32_t nf, int32_t npix, 
     if (nt < 1 || nf < 1 || npix < 1) return 0;
     const int32_t ncol = (flags & SGWB_MAPS_ANTIPODAL) ? npix / 2 : npix;
     size_t n = up256(beam_workspace_bytes(nt, nf, ncol)) + up256(pair_workspace_bytes(nt, nf, npix));
-    if (flags & SGWB_MAPS_ANTIPODAL) n += up256(xm_workspace_bytes(63, nt, nf));
+    if (flags & SGWB_MAPS_ANTIPODAL) n += up256(xm_workspace_bytes(63, nt, nf, npix));
     return n;
 }
 
@@ -288,7 +288,7 @@ int sgwb_fisher_overlap(const float *v, const float *u, const float *wn, int64_t
     rc = check_hip(launch_beam_bf16x3(a, v, gamma, Gam, ws, default_beam_shape(), stream), "beam kernel launch");
     if (rc) return rc;
     const bool use_xm = !(flags & SGWB_MAPS_VALU_X) && x_kernel_choice() != kXKernelValu && xm_eligible(a) &&
-                        workspace_bytes >= beam_bytes + pair_bytes + xm_workspace_bytes(k0, nt, nf);
+                        workspace_bytes >= beam_bytes + pair_bytes + xm_workspace_bytes(k0, nt, nf, npix);
     return check_hip(launch_fisher_neighbours(a, u, wn, gamma, tau, Gam, ws + beam_bytes,
                                               ws + beam_bytes + pair_bytes, use_xm, stream),
                      "fisher neighbour-term launch");
@@ -447,7 +447,7 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
     const size_t beam_bytes = up256(beam_workspace_bytes(nt, nf, ncol));
     if (X) {
         const bool use_xm = !(flags & SGWB_MAPS_VALU_X) && x_kernel_choice() != kXKernelValu && xm_eligible(a) &&
-                            workspace_bytes >= beam_bytes + xm_workspace_bytes(k0, nt, nf);
+                            workspace_bytes >= beam_bytes + xm_workspace_bytes(k0, nt, nf, npix);
         if (use_xm) {
             // the dirty map writes per-strip partial sums; one small kernel adds them
             MapArgs ab = a;

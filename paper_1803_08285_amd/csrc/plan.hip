@@ -334,7 +334,7 @@ int sgwb_plan_create(const sgwb_job *jobs, int32_t njobs, uint32_t flags, sgwb_p
             use_xm[i] = true;
             p->use_xm[i] = 1;
             xm_off[i] = p->xm_bytes;
-            p->xm_bytes += (xm_workspace_bytes(j.k0, j.nt, j.nf) + 255) / 256 * 256;
+            p->xm_bytes += (xm_workspace_bytes(j.k0, j.nt, j.nf, j.npix) + 255) / 256 * 256;
         }
         if (j.Gam) {
             beam_off[i] = p->beam_bytes;

@@ -172,7 +172,7 @@ hipError_t launch_fisher_neighbours(const MapArgs &a, const float *u, const floa
 
 // Matrix-core dirty map (float32, antipodal seeds, df <= ~1/32 Hz).
 bool xm_eligible(const MapArgs &a);
-size_t xm_workspace_bytes(int64_t k0, int32_t nt, int32_t nf);
+size_t xm_workspace_bytes(int64_t k0, int32_t nt, int32_t nf, int32_t npix);
 hipError_t launch_dirty_map_mfma(const MapArgs &a, const float *C, const float *w, const float *gamma,
                                  const double *tau, float *X, void *work, hipStream_t s);
 struct XmArgs {
@@ -187,6 +187,8 @@ struct XmJob {
     const uint4 *A;  // data-side fragments (job workspace)
     const int *e;    // per-bin scale exponents (job workspace)
     double *tmax;    // largest |tau| of the job's seeds (job workspace, written by the prep)
+    float4 *amp;     // per (segment, pixel pair) Bessel amplitudes a_0..a_3 (job workspace, prep)
+    float *amp4;     // and a_4
     const float *C, *w, *gamma;
     const double *tau;
     float *X;
