@@ -217,9 +217,11 @@ __device__ inline void beam_wave_tile_direct(const BJob &jb, int64_t tm, int64_t
             for (int r = 0; r < 16; ++r) {
                 const int64_t m = (tm * WM + i) * kBlk + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 if (m >= jb.nf) continue;
+                // streaming stores: the map is not read back here, and the
+                // whole grid writes at once when its tiles end together
                 float *row = jb.Gam + m * (int64_t)jb.npix;
-                row[n] = acc[i][j][r];
-                if (nB >= 0) row[nB] = acc[i][j][r];
+                __builtin_nontemporal_store(acc[i][j][r], &row[n]);
+                if (nB >= 0) __builtin_nontemporal_store(acc[i][j][r], &row[nB]);
             }
         }
     }
@@ -354,9 +356,11 @@ __device__ inline void beam_wave_tile(const BJob &jb, int64_t tm, int64_t tn, in
             for (int r = 0; r < 16; ++r) {
                 const int64_t m = (tm * WM + i) * kBlk + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 if (m >= jb.nf) continue;
+                // streaming stores: the map is not read back here, and the
+                // whole grid writes at once when its tiles end together
                 float *row = jb.Gam + m * (int64_t)jb.npix;
-                row[n] = acc[i][j][r];
-                if (nB >= 0) row[nB] = acc[i][j][r];
+                __builtin_nontemporal_store(acc[i][j][r], &row[n]);
+                if (nB >= 0) __builtin_nontemporal_store(acc[i][j][r], &row[nB]);
             }
         }
     }
