@@ -127,9 +127,15 @@ static hipError_t enqueue(sgwb_plan *p, hipStream_t s, int parts)
     if ((parts & 1) && p->xm_tiles > 0) {
         for (auto &x : p->xmjobs)
             if ((e = launch_xm_prep(x, s)) != hipSuccess) return e;
-        const int64_t grid = xm_batched_grid(p->xmjobs.data(), (int32_t)p->xmjobs.size());
-        if ((e = launch_xm_batched(p->d_xmjobs, (int32_t)p->xmjobs.size(), grid, s)) != hipSuccess)
-            return e;
+        if (p->tun.xm_per_job) {
+            // the single-call kernel per job: the same tiles, so the same bits
+            for (auto &x : p->xmjobs)
+                if ((e = launch_xm_main(x, s)) != hipSuccess) return e;
+        } else {
+            const int64_t grid = xm_batched_grid(p->xmjobs.data(), (int32_t)p->xmjobs.size());
+            if ((e = launch_xm_batched(p->d_xmjobs, (int32_t)p->xmjobs.size(), grid, s)) != hipSuccess)
+                return e;
+        }
     }
     if (parts & 1) {
         const int64_t cap = (int64_t)p->num_cus * p->tun.x_grid_per_cu;
@@ -143,7 +149,10 @@ static hipError_t enqueue(sgwb_plan *p, hipStream_t s, int parts)
             return e;
     }
     if ((parts & 2) && p->b_wgs > 0) {
-        int64_t grid = std::min<int64_t>(p->b_wgs, (int64_t)p->num_cus * p->tun.beam_grid_per_cu);
+        // 0 workgroups per CU: one workgroup per tile group, no persistent loop
+        int64_t grid = p->tun.beam_grid_per_cu > 0
+                           ? std::min<int64_t>(p->b_wgs, (int64_t)p->num_cus * p->tun.beam_grid_per_cu)
+                           : p->b_wgs;
         grid = (grid + 7) / 8 * 8;
         if ((e = launch_beam_gemm_batched(p->d_bjobs, (int32_t)p->bjobs.size(), p->b_wgs, grid, p->tun.beam_shape,
                                           s)) != hipSuccess)
@@ -260,11 +269,29 @@ int autotune_plan(sgwb_plan *p, bool tune)
                 }
             }
     }
+    if (!p->xmjobs.empty()) {
+        // matrix-core dirty maps: one multi-job launch, or the single-call kernel per job
+        best_ms = 1e30;
+        int pick = 0;
+        for (int per_job : {0, 1}) {
+            Tunables c = best;
+            c.xm_per_job = per_job;
+            if ((rc = plan_set_tunables(p, c))) return rc;
+            const double ms = time_parts(p, s, 1, 1);
+            if (ms < 0) return check_hip(hipGetLastError(), "autotune: dirty-map launch");
+            p->tune_ms.push_back(ms);
+            if (ms < best_ms) {
+                best_ms = ms;
+                pick = per_job;
+            }
+        }
+        best.xm_per_job = pick;
+    }
     if (!p->bjobs.empty()) {
         best_ms = 1e30;
         Tunables bb = best;
         for (int shape : {kBeamShape2x4, kBeamShape4x4})
-            for (int g : {2, 4, 8}) {
+            for (int g : {2, 4, 8, 0}) {
                 Tunables c = best;
                 c.beam_shape = shape;
                 c.beam_grid_per_cu = g;
@@ -447,10 +474,11 @@ int sgwb_plan_describe(const sgwb_plan *p, char *buf, size_t len)
     }
     int n = snprintf(buf, len,
                      "{\"jobs\": %zu, \"x_tiles\": %lld, \"xm_tiles\": %lld, \"beam_workgroups\": %lld, \"x_strip_major\": %d, "
-                     "\"x_grid_per_cu\": %d, \"beam_shape\": \"%s\", \"beam_grid_per_cu\": %d, \"tuned\": %s, "
+                     "\"x_grid_per_cu\": %d, \"xm_per_job\": %d, \"beam_shape\": \"%s\", \"beam_grid_per_cu\": %d, \"tuned\": %s, "
                      "\"from_cache\": %s, \"tune_ms\": [%s], \"graph\": %s, \"key\": \"%s\"}",
                      p->jobs.size(), (long long)p->x_tiles, (long long)p->xm_tiles, (long long)p->b_wgs, p->tun.x_strip_major,
-                     p->tun.x_grid_per_cu, p->tun.beam_shape == kBeamShape2x4 ? "2x4" : "4x4", p->tun.beam_grid_per_cu,
+                     p->tun.x_grid_per_cu, p->tun.xm_per_job, p->tun.beam_shape == kBeamShape2x4 ? "2x4" : "4x4",
+                     p->tun.beam_grid_per_cu,
                      p->tuned ? "true" : "false", p->from_cache ? "true" : "false", ms.c_str(),
                      p->exec ? "true" : "false", p->tune_key.c_str());
     if (n < 0 || (size_t)n >= len) return set_error(SGWB_ENOMEM, "plan_describe: buffer too small");

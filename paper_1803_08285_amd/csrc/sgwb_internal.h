@@ -200,6 +200,7 @@ void fill_xmjob(XmJob *j, const MapArgs &a, const float *C, const float *w, cons
 int64_t xmjob_tiles(const XmJob &j);
 hipError_t launch_xm_prep(const XmJob &j, hipStream_t s);
 hipError_t launch_xm_batched(const XmJob *jobs_dev, int32_t njobs, int64_t grid, hipStream_t s);
+hipError_t launch_xm_main(const XmJob &j, hipStream_t s);  // one job's tiles (after its prep)
 int64_t xm_batched_grid(const XmJob *jobs, int32_t njobs);  // host job copies
 
 // One job of the persistent multi-job dirty-map kernel (float32 path).
@@ -268,7 +269,8 @@ struct Tunables {
     int x_strip_major = 1;    // dirty-map tiles: column tiles fastest within a strip
     int x_grid_per_cu = 2;    // persistent dirty-map workgroups per compute unit
     int beam_shape = kBeamShape2x4;
-    int beam_grid_per_cu = 4; // persistent beam workgroups per compute unit
+    int beam_grid_per_cu = 4; // persistent beam workgroups per compute unit (0: one per tile group)
+    int xm_per_job = 0;       // matrix-core dirty maps: one launch per job instead of one for all
 };
 bool tune_cache_load(const std::string &key, Tunables *t);
 void tune_cache_store(const std::string &key, const Tunables &t);

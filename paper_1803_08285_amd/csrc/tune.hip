@@ -44,8 +44,11 @@ static std::map<std::string, Tunables> read_cache(const std::string &path)
         if (!q2) continue;
         std::string key(q1 + 1, q2);
         Tunables t;
-        if (sscanf(q2 + 1, ": {\"x_strip_major\": %d, \"x_grid_per_cu\": %d, \"beam_shape\": %d, \"beam_grid_per_cu\": %d}",
-                   &t.x_strip_major, &t.x_grid_per_cu, &t.beam_shape, &t.beam_grid_per_cu) == 4)
+        // entries without every field (an older format) are left out: a miss retunes
+        if (sscanf(q2 + 1,
+                   ": {\"x_strip_major\": %d, \"x_grid_per_cu\": %d, \"beam_shape\": %d, \"beam_grid_per_cu\": %d, "
+                   "\"xm_per_job\": %d}",
+                   &t.x_strip_major, &t.x_grid_per_cu, &t.beam_shape, &t.beam_grid_per_cu, &t.xm_per_job) == 5)
             m[key] = t;
     }
     fclose(f);
@@ -61,9 +64,11 @@ static void write_cache(const std::string &path, const std::map<std::string, Tun
     fprintf(f, "{\n");
     size_t i = 0;
     for (const auto &kv : m) {
-        fprintf(f, "\"%s\": {\"x_strip_major\": %d, \"x_grid_per_cu\": %d, \"beam_shape\": %d, \"beam_grid_per_cu\": %d}%s\n",
+        fprintf(f,
+                "\"%s\": {\"x_strip_major\": %d, \"x_grid_per_cu\": %d, \"beam_shape\": %d, \"beam_grid_per_cu\": %d, "
+                "\"xm_per_job\": %d}%s\n",
                 kv.first.c_str(), kv.second.x_strip_major, kv.second.x_grid_per_cu, kv.second.beam_shape,
-                kv.second.beam_grid_per_cu, ++i < m.size() ? "," : "");
+                kv.second.beam_grid_per_cu, kv.second.xm_per_job, ++i < m.size() ? "," : "");
     }
     fprintf(f, "}\n");
     fclose(f);
