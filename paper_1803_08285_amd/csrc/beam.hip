@@ -10,11 +10,14 @@
 //     32 * block + l % 32, exactly the operand layout of
 //     v_mfma_f32_32x32x16_bf16, so the GEMM loads each fragment with one
 //     16-byte load per lane (with 2 x 4 wave tiles the four waves of a
-//     workgroup share each K-step's pixel-side fragments through LDS);
+//     workgroup share each K-step's pixel-side fragments through LDS); the
+//     arrays are padded to whole 4-block tiles with zero blocks, so no load
+//     needs a bounds condition;
 //   * the GEMM accumulates hi.hi + hi.lo + lo.hi in float32 (lo.lo, below
 //     2^-16 relative, is dropped) in a fixed K order;
 //   * with antipodal seeds only the northern half of the pixels is computed
-//     and each result is also written to the antipode column.
+//     and each result is also written to the antipode column, with streaming
+//     (nontemporal) stores.
 // A float64 vector-unit kernel serves the float64 path.
 #include "sgwb_internal.h"
 
@@ -251,12 +254,12 @@ __device__ inline void stage_bfrags(const uint4 *__restrict__ Gf, int64_t tn, in
 
 // One wave's (WM x 32) x (WN x 32) tile.  The four waves of a workgroup share
 // the column tile tn (the patch order makes it uniform), so its fragments are
-// staged once per K-step in LDS (two distinct buffers, K loop unrolled by two
-// so that reads of one need not wait for the copy into the other); each wave
-// reads its own bin-side fragments from L2, one K-step ahead in registers.
-// Every wave of the workgroup runs the K loop (it holds barriers): a wave
-// whose bin tile lies past the last block multiplies zero fragments and
-// stores nothing.
+// staged once per K-step in LDS (three distinct buffers, K loop unrolled by
+// three, so that reads of one need not wait for the copies into the others);
+// each wave reads its own bin-side fragments from L2, one K-step ahead in
+// registers.  Every wave of the workgroup runs the K loop (it holds
+// barriers): a wave whose bin tile lies past the last multiplies the last
+// tile's fragments and stores nothing.
 template <int WM, int WN>
 __device__ inline void beam_wave_tile(const BJob &jb, int64_t tm, int64_t tn, int lane, uint4 (*Bs0)[64],
                                       uint4 (*Bs1)[64], uint4 (*Bs2)[64])
