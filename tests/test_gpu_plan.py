@@ -5,6 +5,8 @@ The plan's maps must be bitwise equal to the single-call path (make_maps_band,
 which the parity tests compare with the oracle), on every graph replay, with
 eager work between replays; autotuned, cached and graph-free plans must agree too.
 """
+import json
+
 import numpy as np
 import pytest
 
@@ -107,6 +109,34 @@ def test_plan_every_schedule_gives_the_same_maps(sg, tmp_path, monkeypatch):
         torch.cuda.synchronize()
         _assert_equal(jobs, refs)
         plan.close()
+
+
+@pytest.mark.parametrize("xm_per_job,beam_shape,beam_grid", [(1, 1, 0), (0, 1, 0), (1, 0, 2), (0, 0, 8)])
+def test_plan_forced_schedules_give_the_same_maps(sg, tmp_path, monkeypatch, xm_per_job, beam_shape, beam_grid):
+    """Each schedule candidate, forced through the tuning cache: identical bits.
+
+    beam_shape 1 is the 2x4 wave tile, 0 the 4x4; beam_grid 0 is one workgroup per
+    tile group (no persistent loop); xm_per_job 1 launches the single-call
+    dirty-map kernel once per job instead of the multi-job kernel."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("SGWB_TUNE_CACHE", str(cache))
+    jobs, refs, _ = _make_jobs(sg)
+    p0 = sg.Plan(jobs, autotune=False)
+    key = p0.describe()["key"]
+    p0.close()
+    cache.write_text(json.dumps({key: {"x_strip_major": 0, "x_grid_per_cu": 4, "beam_shape": beam_shape,
+                                       "beam_grid_per_cu": beam_grid, "xm_per_job": xm_per_job}}))
+    plan = sg.Plan(jobs, autotune=True)
+    d = plan.describe()
+    assert d["from_cache"] and d["xm_per_job"] == xm_per_job and d["beam_grid_per_cu"] == beam_grid
+    assert d["beam_shape"] == ("2x4" if beam_shape == 1 else "4x4")
+    for j in jobs:
+        for t in (j.X, j.G, j.Xbb, j.Gbb):
+            t.fill_(float("nan"))
+    plan.launch()
+    torch.cuda.synchronize()
+    _assert_equal(jobs, refs)
+    plan.close()
 
 
 def test_plan_against_oracle(sg, oracle_mod):
