@@ -106,9 +106,11 @@ int sgwb_build_geometry_f64(const sgwb_baseline *bl /*host*/, int32_t nside,
  * X arithmetic, two forms with the same definition:
  *   matrix cores (used with SGWB_MAPS_ANTIPODAL, df <= 0.0347 Hz and a
  *   workspace of sgwb_make_maps_workspace_size() bytes): per 64-bin strip,
- *   float64 phase reduction at the strip centre and a 5-term Jacobi-Anger
- *   expansion of the phase across the strip, contracted on float16 MFMA with
- *   hi + lo splits of the leading terms and float32 accumulation;
+ *   float64 phase reduction at the strip centre and a Jacobi-Anger
+ *   expansion of the phase across the strip (4 or 5 terms: the fewest the
+ *   seeds' largest delay allows, measured on the device per call),
+ *   contracted on float16 MFMA with hi + lo splits of the leading terms and
+ *   float32 accumulation;
  *   vector units (otherwise, with flag SGWB_MAPS_VALU_X, or with
  *   SGWB_X_KERNEL=valu in the environment):
  *   float64 phase reduction at anchor bins k = 0 mod 64 and a float32
