@@ -22,6 +22,10 @@ CASES = [  # baseline, nside, nt, k0, nf, df, antipodal, x_kernel
     ("BC", 8, 50, 5, 96, 0.25, True, "auto"),
     ("AB", 4, 33, 64, 70, 1 / 32, True, "valu"),
     ("AC", 4, 40, 3, 50, 1 / 32, False, "auto"),
+    # segments of a full-resolution day: pair delays so small (eta <= 1e-3)
+    # that the expansion's higher terms nearly vanish
+    ("AB", 4, 898, 0, 64, 1 / 32, True, "auto"),
+    ("BC", 2, 1200, 100, 70, 1 / 32, True, "auto"),
 ]
 
 
@@ -60,6 +64,9 @@ def test_overlap_fisher_vs_oracle(sg, oracle_mod, case):
     npix = 12 * nside * nside
     rows, cols = synth.random_selection(3, nf, npix, 4, 6)
     gh, th = g.cpu().numpy(), t.cpu().numpy()
+    if nt >= 898:  # the case is there for tiny pair delays: check that they are
+        dtau = np.abs(np.roll(th, -1, axis=0) - th).max()
+        assert 2 * np.pi * 31.5 * df * dtau <= 1e-3
     Go, _, S = oracle_mod.fisher_overlap_at(v, u, w, F0, df, k0, gh, th, rows, cols)
     zh = np.zeros_like(v)
     Go0, _, _ = oracle_mod.fisher_overlap_at(v, zh, zh, F0, df, k0, gh, th, rows, cols)
