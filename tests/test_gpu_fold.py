@@ -30,8 +30,10 @@ def _days(seed, ndays, nt, nf, p_missing):
     return C, s, present
 
 
+# nt = 37 and 898 leave a ragged last group of the four segments a thread
+# folds; nt = 3 and 1 are a single ragged group (every neighbour in another day)
 @pytest.mark.parametrize("ndays,nt,nf,p_missing", [(5, 37, 300, 0.1), (1, 16, 256, 0.0), (3, 8, 1, 0.3),
-                                                    (2, 898, 70, 0.02)])
+                                                    (2, 898, 70, 0.02), (4, 3, 50, 0.2), (3, 1, 40, 0.0)])
 def test_fold_vs_oracle(sg, oracle_mod, ndays, nt, nf, p_missing):
     C, s, present = _days(7 + nt, ndays, nt, nf, p_missing)
     v, u, w, x = sg.fold(torch.from_numpy(C).cuda(), torch.from_numpy(s).cuda(), torch.from_numpy(present).cuda(), W)
