@@ -255,7 +255,8 @@ hipError_t launch_band_partial_finish(const double *part, int64_t nrows, int32_t
 }
 
 // v[t] = sum_{c in [klo,khi)} H[c] w[t][c]: one workgroup of 1024 threads per
-// segment, per-thread strides over the bins, then a fixed tree (float64).
+// segment, per-thread strides over the bins in four interleaved partial sums,
+// then a fixed tree (float64).
 constexpr int kWeightThreads = 1024;
 
 __global__ __launch_bounds__(kWeightThreads) void band_weight_kernel(const float *__restrict__ w, int64_t ldw,
@@ -264,9 +265,17 @@ __global__ __launch_bounds__(kWeightThreads) void band_weight_kernel(const float
 {
     __shared__ double red[kWeightThreads];
     const float *row = w + (int64_t)blockIdx.x * ldw;
-    double acc = 0.0;
-    for (int32_t c = klo + threadIdx.x; c < khi; c += kWeightThreads) acc = fma((double)H[c], (double)row[c], acc);
-    red[threadIdx.x] = acc;
+    // four independent partial sums per thread (their loads go out together),
+    // added in a fixed order
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int32_t c = klo + threadIdx.x;
+    for (; c + 3 * kWeightThreads < khi; c += 4 * kWeightThreads) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            acc[u] = fma((double)H[c + u * kWeightThreads], (double)row[c + u * kWeightThreads], acc[u]);
+    }
+    for (int u = 0; c < khi; c += kWeightThreads, ++u) acc[u] = fma((double)H[c], (double)row[c], acc[u]);
+    red[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     __syncthreads();
     for (int st = kWeightThreads / 2; st > 0; st >>= 1) {
         if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
