@@ -100,28 +100,34 @@ int sgwb_build_geometry_f64(const sgwb_baseline *bl /*host*/, int32_t nside,
  * w float32 [nt][ldc], ldc >= nf; gamma float32 and tau float64 [nt][npix].
  * Outputs (may be NULL to skip): X, Gam float32 [nf][npix].
  * flags: SGWB_MAPS_ANTIPODAL promises that gamma/tau have the exact
- * antipodal symmetry that sgwb_build_geometry writes (npix = 12 nside^2);
- * the kernels then evaluate one phasor per antipodal pair and write both
- * pixels.  Without the flag any npix and any seeds are accepted.
+ * antipodal symmetry that sgwb_build_geometry writes (npix = 12 nside^2) and
+ * delays of a baseline on the Earth (|tau| <= 2 R / c); the kernels then
+ * evaluate one phasor per antipodal pair and write both pixels.  Without the
+ * flag any npix and any seeds are accepted.
  * X arithmetic, two forms with the same definition:
- *   matrix cores (used with SGWB_MAPS_ANTIPODAL, df <= 0.0347 Hz and a
- *   workspace of sgwb_make_maps_workspace_size() bytes): per 64-bin strip,
- *   float64 phase reduction at the strip centre and a Jacobi-Anger
- *   expansion of the phase across the strip (4 or 5 terms: the fewest the
- *   seeds' largest delay allows, measured on the device per call),
- *   contracted on float16 MFMA with hi + lo splits of the leading terms and
- *   float32 accumulation;
- *   vector units (otherwise, with flag SGWB_MAPS_VALU_X, or with
- *   SGWB_X_KERNEL=valu in the environment):
+ *   matrix cores (used with SGWB_MAPS_ANTIPODAL, df <= 0.0344 Hz, i.e.
+ *   2 pi 31.5 df 2R/c <= 0.29, and a workspace): per 64-bin strip, float64
+ *   phase reduction at the strip centre and a Jacobi-Anger expansion of the
+ *   phase across the strip (4 or 5 terms: the fewest the seeds' largest delay
+ *   allows, measured on the device per call), contracted on float16 MFMA
+ *   with hi + lo splits of the leading terms and float32 accumulation.  The
+ *   same device pass spot-checks the promise of SGWB_MAPS_ANTIPODAL (exact
+ *   symmetry on the first, middle and last segment, and the delay bound);
+ *   seeds that fail it give X = NaN everywhere and sgwb_last_x_form()
+ *   reports SGWB_EINVAL;
+ *   vector units (without a workspace, without the flag, for larger df, with
+ *   flag SGWB_MAPS_VALU_X, or with SGWB_X_KERNEL=valu in the environment):
  *   float64 phase reduction at anchor bins k = 0 mod 64 and a float32
  *   complex-rotation recurrence between anchors.
+ * sgwb_last_x_form() names the form a call took.
  * Gam arithmetic: float32 inputs split into bfloat16 hi + lo, three MFMA
  * products (hi.hi + hi.lo + lo.hi), float32 accumulation.
  * Workspace: device memory of at least sgwb_make_maps_workspace_size() bytes,
  * 256-byte aligned, owned by the caller (NULL allowed when Gam is NULL; the
  * dirty map then uses the vector-unit form).
  * Errors: SGWB_EINVAL (null input, nt/nf/npix < 1, ldc < nf, k0 < 0, bad
- * grid, misaligned pointer), SGWB_ENOMEM (workspace too small).             */
+ * grid, misaligned pointer), SGWB_ENOMEM (workspace given but smaller than
+ * the form that applies needs; nothing falls back silently).               */
 #define SGWB_MAPS_ANTIPODAL 1u
 #define SGWB_MAPS_VALU_X 2u /* use the vector-unit dirty map even where the matrix-core form applies */
 size_t sgwb_make_maps_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint32_t flags);
@@ -129,6 +135,28 @@ int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int3
                    const sgwb_fgrid *fg /*host*/, int64_t k0, const float *gamma, const double *tau,
                    int32_t npix, uint32_t flags, float *X, float *Gam, void *workspace,
                    size_t workspace_bytes, hipStream_t stream);
+
+/* ---- which dirty-map form ran ------------------------------------------
+ * The form of X that the last sgwb_make_maps, sgwb_make_maps_band or
+ * sgwb_fisher_overlap call made on the calling thread took:
+ *   SGWB_XFORM_NONE    the call computed no dirty map (or failed);
+ *   SGWB_XFORM_VALU    vector-unit recurrence (chosen on the host, or by the
+ *                      device when no matrix-core form meets the delays);
+ *   SGWB_XFORM_MFMA4   matrix cores, four terms (|eta| <= 0.07);
+ *   SGWB_XFORM_MFMA5   five terms, m = 2 unsplit (|eta| <= 0.17);
+ *   SGWB_XFORM_MFMA5S  five terms, m = 2 split hi + lo (|eta| <= 0.29),
+ * with eta = 2 pi 31.5 df max|tau| of the call's seeds.  The matrix-core
+ * choice is made on the device; for it this call synchronises the stream of
+ * that call and reads the choice back from its workspace (16 bytes), so it
+ * must come before that workspace is reused or freed.
+ * Returns SGWB_OK, or SGWB_EINVAL if the seeds failed the antipodal spot check
+ * of that call (its X is then NaN; *form = SGWB_XFORM_NONE), or SGWB_EDEVICE.  */
+#define SGWB_XFORM_NONE 0
+#define SGWB_XFORM_VALU 1
+#define SGWB_XFORM_MFMA4 2
+#define SGWB_XFORM_MFMA5 3
+#define SGWB_XFORM_MFMA5S 4
+int sgwb_last_x_form(int32_t *form /*host*/);
 
 /* ---- network sum: the sum over baselines I of Eq. eq:narrowband ------------
  * out[i] = sum_{m < nmaps} maps[m][i] for i < n: the narrowband (or broadband)

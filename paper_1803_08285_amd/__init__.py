@@ -117,6 +117,7 @@ _SIGNATURES = {
     "sgwb_plan_launch": ([_VP, _VP], ctypes.c_int),
     "sgwb_plan_destroy": ([_VP], None),
     "sgwb_plan_describe": ([_VP, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
+    "sgwb_last_x_form": ([ctypes.POINTER(_I32)], ctypes.c_int),
     "sgwb_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "sgwb_last_error": ([], ctypes.c_char_p),
     "sgwb_device_supported": ([], ctypes.c_int),
@@ -226,6 +227,19 @@ def build_geometry(sites, nside: int, tgrid: TGrid, dtype=torch.float32, device=
         _check(fn(ctypes.byref(bl), int(nside), ctypes.byref(tg), _ptr(gamma), _ptr(tau), _stream()),
                "build_geometry")
     return gamma, tau
+
+
+X_FORMS = {0: "none", 1: "valu", 2: "mfma4", 3: "mfma5", 4: "mfma5_split"}
+
+
+def last_x_form() -> str:
+    """Form of the dirty map that the last make_maps / make_maps_band /
+    fisher_overlap call of this thread took: "none", "valu", "mfma4", "mfma5" or
+    "mfma5_split" (synchronises that call's stream for the matrix-core forms;
+    raises if its seeds failed the antipodal check)."""
+    f = _I32(0)
+    _check(lib().sgwb_last_x_form(ctypes.byref(f)), "last_x_form")
+    return X_FORMS[int(f.value)]
 
 
 def workspace_bytes(nt: int, nf: int, npix: int, antipodal: bool = True) -> int:

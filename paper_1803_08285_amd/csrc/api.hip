@@ -169,11 +169,68 @@ static int x_kernel_choice()
     return k;
 }
 
+// What the last map call on this thread did for X: the host's choice, and for
+// the matrix-core forms the device address of the call's form record and the
+// stream it was queued on.
+struct XFormRecord {
+    int host = SGWB_XFORM_NONE;
+    const double *rec = nullptr;
+    hipStream_t stream = nullptr;
+};
+static thread_local XFormRecord g_xform;
+constexpr int kXFormDevice = -2;  // host marker: the matrix-core prep chose on the device
+
+static void note_xform(int host, const double *rec = nullptr, hipStream_t stream = nullptr)
+{
+    g_xform.host = host;
+    g_xform.rec = rec;
+    g_xform.stream = stream;
+}
+
+// Matrix-core dirty map for this call?  Applies with the antipodal flag where
+// a form can meet the Earth's delay bound at this df, unless the vector form is
+// forced.  *rc = SGWB_ENOMEM when it applies and a workspace was given that
+// cannot hold it (no silent fallback); without a workspace the vector form runs.
+static bool want_xm(const MapArgs &a, uint32_t flags, const void *workspace, size_t workspace_bytes,
+                    size_t need, const char *who, int *rc)
+{
+    *rc = SGWB_OK;
+    if ((flags & SGWB_MAPS_VALU_X) || x_kernel_choice() == kXKernelValu || !xm_eligible(a) || !workspace) return false;
+    if (workspace_bytes < need) {
+        *rc = set_error(SGWB_ENOMEM, "%s: the matrix-core dirty map needs a workspace of %zu bytes, %zu given", who,
+                        need, workspace_bytes);
+        return false;
+    }
+    return true;
+}
+
 }  // namespace sgwb
 
 using namespace sgwb;
 
 extern "C" {
+
+int sgwb_last_x_form(int32_t *form)
+{
+    if (!form) return set_error(SGWB_EINVAL, "last_x_form: null pointer");
+    *form = g_xform.host;
+    if (g_xform.host != kXFormDevice) return SGWB_OK;  // host-side choices are final
+    double rec[2];
+    int rc = check_hip(hipStreamSynchronize(g_xform.stream), "last_x_form: stream synchronisation");
+    if (!rc) rc = check_hip(hipMemcpy(rec, g_xform.rec, sizeof rec, hipMemcpyDeviceToHost), "last_x_form: read back");
+    if (rc) {
+        *form = SGWB_XFORM_NONE;
+        return rc;
+    }
+    const int code = (int)rec[1];
+    if (code == kXFormRejected) {
+        *form = SGWB_XFORM_NONE;
+        return set_error(SGWB_EINVAL, "last_x_form: the seeds failed the antipodal check or the delay bound "
+                                      "(max |tau| = %.6g s); X was written as NaN", rec[0]);
+    }
+    *form = code;
+    return SGWB_OK;
+}
 
 const char *sgwb_status_string(int status)
 {
@@ -229,6 +286,7 @@ int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int3
                    int64_t k0, const float *gamma, const double *tau, int32_t npix, uint32_t flags, float *X,
                    float *Gam, void *workspace, size_t workspace_bytes, hipStream_t stream)
 {
+    note_xform(SGWB_XFORM_NONE);
     MapArgs a;
     int rc = check_maps_args<float>(C, w, ldc, nt, nf, fg, k0, gamma, tau, npix, flags, &a);
     if (rc) return rc;
@@ -240,14 +298,18 @@ int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int3
                          sgwb_make_maps_workspace_size(nt, nf, npix, flags), workspace ? workspace_bytes : (size_t)0);
     if (X) {
         const size_t xm_bytes = xm_workspace_bytes(k0, nt, nf, npix);
-        const bool use_xm = !(flags & SGWB_MAPS_VALU_X) && x_kernel_choice() != kXKernelValu && xm_eligible(a) &&
-                            workspace && workspace_bytes >= beam_bytes + xm_bytes;
-        if (use_xm)
+        const bool use_xm = want_xm(a, flags, workspace, workspace_bytes, beam_bytes + xm_bytes, "make_maps", &rc);
+        if (rc) return rc;
+        if (use_xm) {
+            const double *rec = nullptr;
             rc = check_hip(launch_dirty_map_mfma(a, C, w, gamma, tau, X, reinterpret_cast<char *>(workspace) + beam_bytes,
-                                                 stream),
+                                                 stream, &rec),
                            "dirty-map (matrix cores) launch");
-        else
+            if (!rc) note_xform(kXFormDevice, rec, stream);
+        } else {
             rc = check_hip(launch_dirty_map<float>(a, C, w, gamma, tau, X, stream), "dirty-map kernel launch");
+            if (!rc) note_xform(SGWB_XFORM_VALU);
+        }
         if (rc) return rc;
     }
     if (Gam) {
@@ -270,6 +332,7 @@ int sgwb_fisher_overlap(const float *v, const float *u, const float *wn, int64_t
                         const sgwb_fgrid *fg, int64_t k0, const float *gamma, const double *tau, int32_t npix,
                         uint32_t flags, float *Gam, void *workspace, size_t workspace_bytes, hipStream_t stream)
 {
+    note_xform(SGWB_XFORM_NONE);
     if (!Gam) return set_error(SGWB_EINVAL, "fisher_overlap: null Gam");
     if (!u || !wn) return set_error(SGWB_EINVAL, "fisher_overlap: null neighbour series");
     if (((uintptr_t)u % 4) || ((uintptr_t)wn % 4)) return set_error(SGWB_EINVAL, "fisher_overlap: misaligned input");
@@ -285,13 +348,17 @@ int sgwb_fisher_overlap(const float *v, const float *u, const float *wn, int64_t
         return set_error(SGWB_ENOMEM, "fisher_overlap: workspace of %zu bytes needed, %zu given",
                          sgwb_fisher_overlap_workspace_size(nt, nf, npix, flags), workspace_bytes);
     char *ws = reinterpret_cast<char *>(workspace);
+    const bool use_xm = want_xm(a, flags, workspace, workspace_bytes,
+                                beam_bytes + pair_bytes + xm_workspace_bytes(k0, nt, nf, npix), "fisher_overlap", &rc);
+    if (rc) return rc;
     rc = check_hip(launch_beam_bf16x3(a, v, gamma, Gam, ws, default_beam_shape(), stream), "beam kernel launch");
     if (rc) return rc;
-    const bool use_xm = !(flags & SGWB_MAPS_VALU_X) && x_kernel_choice() != kXKernelValu && xm_eligible(a) &&
-                        workspace_bytes >= beam_bytes + pair_bytes + xm_workspace_bytes(k0, nt, nf, npix);
-    return check_hip(launch_fisher_neighbours(a, u, wn, gamma, tau, Gam, ws + beam_bytes,
-                                              ws + beam_bytes + pair_bytes, use_xm, stream),
-                     "fisher neighbour-term launch");
+    const double *rec = nullptr;
+    rc = check_hip(launch_fisher_neighbours(a, u, wn, gamma, tau, Gam, ws + beam_bytes, ws + beam_bytes + pair_bytes,
+                                            use_xm, stream, &rec),
+                   "fisher neighbour-term launch");
+    if (!rc) note_xform(use_xm ? kXFormDevice : SGWB_XFORM_VALU, rec, stream);
+    return rc;
 }
 
 int sgwb_fold(const float *C, const float *sinv, const uint8_t *present, int64_t ldc, int32_t ndays, int32_t nt,
@@ -423,6 +490,7 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
                         const float *H, int32_t k_lo, int32_t k_hi, float *X, float *Gam, float *Xbb, float *Gbb,
                         void *workspace, size_t workspace_bytes, hipStream_t stream)
 {
+    note_xform(SGWB_XFORM_NONE);
     if (!X != !Xbb || !Gam != !Gbb)
         return set_error(SGWB_EINVAL, "make_maps_band: X and Xbb, Gam and Gbb come in pairs");
     if (!X && !Gam) return set_error(SGWB_EINVAL, "make_maps_band: nothing to compute");
@@ -446,21 +514,26 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
     const int32_t ncol = a.nside > 0 ? npix / 2 : npix;
     const size_t beam_bytes = up256(beam_workspace_bytes(nt, nf, ncol));
     if (X) {
-        const bool use_xm = !(flags & SGWB_MAPS_VALU_X) && x_kernel_choice() != kXKernelValu && xm_eligible(a) &&
-                            workspace_bytes >= beam_bytes + xm_workspace_bytes(k0, nt, nf, npix);
+        const bool use_xm =
+            want_xm(a, flags, workspace, workspace_bytes, beam_bytes + xm_workspace_bytes(k0, nt, nf, npix),
+                    "make_maps_band", &rc);
+        if (rc) return rc;
         if (use_xm) {
             // the dirty map writes per-strip partial sums; one small kernel adds them
             MapArgs ab = a;
             ab.band_part = part_x;
             ab.band_lo = k_lo;
             ab.band_hi = k_hi;
-            rc = check_hip(launch_dirty_map_mfma(ab, C, w, gamma, tau, X, ws + beam_bytes, stream),
+            const double *rec = nullptr;
+            rc = check_hip(launch_dirty_map_mfma(ab, C, w, gamma, tau, X, ws + beam_bytes, stream, &rec),
                            "dirty-map (matrix cores) launch");
             if (rc) return rc;
+            note_xform(kXFormDevice, rec, stream);
             rc = check_hip(launch_band_partial_finish(part_x, xm_band_rows(a), npix, Xbb, stream), "band finish");
         } else {
             rc = check_hip(launch_dirty_map<float>(a, C, w, gamma, tau, X, stream), "dirty-map kernel launch");
             if (rc) return rc;
+            note_xform(SGWB_XFORM_VALU);
             rc = check_hip(launch_band<float>(X, nullptr, nullptr, nf, npix, k_lo, k_hi, Xbb, nullptr, nullptr, 0,
                                               stream),
                            "band kernel launch");

@@ -231,9 +231,11 @@ __global__ __launch_bounds__(256) void dirty_map_kernel(MapArgs a, int64_t strip
                                                          const T *__restrict__ w,
                                                          const T *__restrict__ gamma,
                                                          const double *__restrict__ tau,
-                                                         T *__restrict__ X)
+                                                         T *__restrict__ X, const double *__restrict__ gate)
 {
     __shared__ typename Cplx<T>::type ys[StripTraits<T>::XTC][StripTraits<T>::S];
+    // gated launch: only where the matrix-core prep found no accurate form
+    if (gate && (int)gmem(gate)[1] != SGWB_XFORM_VALU) return;
     dirty_map_tile<T, PAIR>(a, strip0 + (int64_t)blockIdx.y, blockIdx.x, C, w, gamma, tau, X, ys);
 }
 
@@ -300,7 +302,7 @@ hipError_t launch_dirty_map_batched(const XJob *jobs_dev, int32_t njobs, int64_t
 
 template <typename T>
 hipError_t launch_dirty_map(const MapArgs &a, const T *C, const T *w, const T *gamma,
-                            const double *tau, T *X, hipStream_t s)
+                            const double *tau, T *X, hipStream_t s, const double *gate)
 {
     using C2 = typename Cplx<T>::type;
     constexpr int S = StripTraits<T>::S;
@@ -316,18 +318,19 @@ hipError_t launch_dirty_map(const MapArgs &a, const T *C, const T *w, const T *g
         dim3 grid((unsigned)((ncol + 255) / 256), (unsigned)ns);
         if (pair)
             hipLaunchKernelGGL((dirty_map_kernel<T, true>), grid, dim3(256), 0, s, a, strip_first + s0, Cc,
-                               w, gamma, tau, X);
+                               w, gamma, tau, X, gate);
         else
             hipLaunchKernelGGL((dirty_map_kernel<T, false>), grid, dim3(256), 0, s, a, strip_first + s0,
-                               Cc, w, gamma, tau, X);
+                               Cc, w, gamma, tau, X, gate);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 template hipError_t launch_dirty_map<float>(const MapArgs &, const float *, const float *,
-                                            const float *, const double *, float *, hipStream_t);
+                                            const float *, const double *, float *, hipStream_t, const double *);
 template hipError_t launch_dirty_map<double>(const MapArgs &, const double *, const double *,
-                                             const double *, const double *, double *, hipStream_t);
+                                             const double *, const double *, double *, hipStream_t,
+                                             const double *);
 
 }  // namespace sgwb

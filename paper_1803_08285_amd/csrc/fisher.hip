@@ -49,7 +49,7 @@ size_t pair_workspace_bytes(int32_t nt, int32_t nf, int32_t npix)
 
 hipError_t launch_fisher_neighbours(const MapArgs &a, const float *u, const float *wn, const float *gamma,
                                     const double *tau, float *Gam, void *pair_ws, void *xm_ws, bool use_xm,
-                                    hipStream_t s)
+                                    hipStream_t s, const double **form_rec)
 {
     const int32_t nq = a.nt;  // pairs (q, q + 1 mod nt)
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -73,8 +73,19 @@ hipError_t launch_fisher_neighbours(const MapArgs &a, const float *u, const floa
     b.ldc = a.nf;
     b.unit_c = 1;
     b.accumulate = 1;
-    if (use_xm) return launch_dirty_map_mfma(b, nullptr, y, g2, t2, Gam, xm_ws, s);
-    return launch_dirty_map<float>(b, nullptr, y, g2, t2, Gam, s);
+    // a pair delay is a difference of two delays: |tau'| <= 4 R / c.  Adjacent
+    // segments of a full day keep it far smaller, but a partial day's wrap pair
+    // (nt - 1, 0) or a short day can reach that bound, beyond what the
+    // matrix-core forms cover at this df; the form record then selects the
+    // vector-unit kernel, launched behind the matrix-core one and gated on it.
+    b.tau_limit = 4.0 * kEarthRadius / kLightSpeed;
+    if (!use_xm) return launch_dirty_map<float>(b, nullptr, y, g2, t2, Gam, s);
+    const double *rec = nullptr;
+    e = launch_dirty_map_mfma(b, nullptr, y, g2, t2, Gam, xm_ws, s, &rec);
+    if (e != hipSuccess) return e;
+    if (form_rec) *form_rec = rec;
+    if (kTwoPi * 31.5 * b.df * b.tau_limit > kXmEtaMax) e = launch_dirty_map<float>(b, nullptr, y, g2, t2, Gam, s, rec);
+    return e;
 }
 
 }  // namespace sgwb

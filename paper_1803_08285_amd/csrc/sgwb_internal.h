@@ -125,10 +125,17 @@ struct MapArgs {
     // band_part[strip][pixel] = sum of the strip's X rows with columns in [band_lo, band_hi).
     double *band_part = nullptr;
     int32_t band_lo = 0, band_hi = 0;
+    // Bound on |tau| that valid seeds of this call meet (s): 2 R / c for the
+    // delays of a baseline on the Earth, 4 R / c for differences of two.
+    double tau_limit = 2.0 * kEarthRadius / kLightSpeed;
 };
+// gate (optional): the dirty-map form record of a matrix-core launch on the
+// same seeds ([0] largest |tau|, [1] form code); with it the kernel computes
+// only where that record selected the vector-unit form (its workgroups exit
+// at once otherwise).
 template <typename T>
 hipError_t launch_dirty_map(const MapArgs &a, const T *C, const T *w, const T *gamma,
-                            const double *tau, T *X, hipStream_t s);
+                            const double *tau, T *X, hipStream_t s, const double *gate = nullptr);
 
 // Network sums and pixel contractions.
 constexpr int kMaxNetworkMaps = 32;
@@ -168,13 +175,26 @@ hipError_t launch_fold(const float *C, const float *sv, const uint8_t *present, 
 size_t pair_workspace_bytes(int32_t nt, int32_t nf, int32_t npix);
 hipError_t launch_fisher_neighbours(const MapArgs &a, const float *u, const float *wn, const float *gamma,
                                     const double *tau, float *Gam, void *pair_ws, void *xm_ws, bool use_xm,
-                                    hipStream_t s);
+                                    hipStream_t s, const double **form_rec = nullptr);
 
-// Matrix-core dirty map (float32, antipodal seeds, df <= ~1/32 Hz).
+// Matrix-core dirty map (float32, antipodal seeds, df <= 0.0344 Hz).
+// Jacobi-Anger forms by the largest |eta| = 2 pi 31.5 df max|tau| of the seeds:
+// four terms up to kXmEtaFour, five with m = 2 unsplit up to kXmEtaM2, five
+// with m = 2 split up to kXmEtaMax (truncation below 1e-6 there).
+constexpr double kXmEtaFour = 0.07;
+constexpr double kXmEtaM2 = 0.17;
+constexpr double kXmEtaMax = 0.29;
+// Form record written by the prep on the device and read by the main kernel
+// (and by sgwb_last_x_form): SGWB_XFORM_* codes, or kXFormRejected when the
+// seeds fail the antipodal spot check or exceed the call's delay bound (the
+// map is then written as NaN).
+constexpr int kXFormRejected = -1;
 bool xm_eligible(const MapArgs &a);
 size_t xm_workspace_bytes(int64_t k0, int32_t nt, int32_t nf, int32_t npix);
+// form_rec (optional out): device address of the call's form record
 hipError_t launch_dirty_map_mfma(const MapArgs &a, const float *C, const float *w, const float *gamma,
-                                 const double *tau, float *X, void *work, hipStream_t s);
+                                 const double *tau, float *X, void *work, hipStream_t s,
+                                 const double **form_rec = nullptr);
 struct XmArgs {
     MapArgs a;
     int64_t strip_first, nstrips, nchunks;
@@ -186,7 +206,7 @@ struct XmJob {
     XmArgs x;
     const uint4 *A;  // data-side fragments (job workspace)
     const int *e;    // per-bin scale exponents (job workspace)
-    double *tmax;    // largest |tau| of the job's seeds (job workspace, written by the prep)
+    double *tmax;    // form record: [0] largest |tau| of the job's seeds, [1] form code (job workspace, prep)
     float4 *amp;     // per (segment, pixel pair) Bessel amplitudes a_0..a_3 (job workspace, prep)
     float *amp4;     // and a_4
     const float *C, *w, *gamma;

@@ -24,8 +24,10 @@ DETECTORS = {
     "A": (46.5, -119.4, 126.0),
     "B": (30.6, -90.8, 198.0),
     "C": (43.6, 10.5, 71.0),
+    # a fourth site, far from the others (chord to A 11.8 Mm): long-baseline test cases
+    "D": (-31.5, 115.7, 45.0),
 }
-BASELINES = {"AB": ("A", "B"), "AC": ("A", "C"), "BC": ("B", "C")}
+BASELINES = {"AB": ("A", "B"), "AC": ("A", "C"), "BC": ("B", "C"), "AD": ("A", "D")}
 
 
 def baseline_sites(name: str):

@@ -196,3 +196,21 @@ def test_make_maps_band_validation_on_the_host():
     assert rc == -2
     assert L.sgwb_make_maps_band_workspace_size(10, 8, 768, 1) > L.sgwb_make_maps_workspace_size(10, 8, 768, 1)
     assert L.sgwb_make_maps_band_workspace_size(10, 800, 768, 1) > L.sgwb_make_maps_band_workspace_size(10, 8, 768, 1)
+
+
+def test_short_matrix_core_workspace_is_refused_on_the_host():
+    """With the antipodal flag at df = 1/32 Hz the matrix-core dirty map applies;
+    a workspace too small for it is an error (SGWB_ENOMEM), not a silent switch
+    to the vector units, and the form record then says no dirty map ran."""
+    import paper_1803_08285_amd as sg
+
+    L = sg.lib()
+    fg = sg._FGrid(20.0, 1 / 32)
+    d = ctypes.c_void_p(256)
+    rc = L.sgwb_make_maps(d, d, 8, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1, d, None, d, 256, None)
+    assert rc == -2 and b"matrix-core" in L.sgwb_last_error()
+    form = ctypes.c_int32(-7)
+    assert L.sgwb_last_x_form(ctypes.byref(form)) == 0 and form.value == 0
+    # unknown flag bits are refused before anything else
+    rc = L.sgwb_make_maps(d, d, 8, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1 | 8, d, None, d, 256, None)
+    assert rc == -1 and b"flag" in L.sgwb_last_error()

@@ -91,6 +91,34 @@ def test_server_mix_equals_alone_and_direct(sg, datasets):
     srv.close()
 
 
+def test_server_results_vs_oracle(sg, oracle_mod, datasets):
+    """Served broadband maps against the FP64 oracle (Eq. eq_dirtymap and the
+    Eq. eq_fisher diagonal per bin, summed over the query's band as in Sec. V):
+    Xbb within 1e-5 of the band-summed scale sum_k S, Gbb (the band sum moved
+    into the weights, float64) within 1e-6 relative.  The oracle reads the
+    dataset's stored float32 inputs and the seeds the geometry call writes."""
+    srv = sg.Server(datasets, slots=4, hbm_budget_bytes=2 << 30)
+    tickets = [srv.submit(*q) for q in QUERIES]
+    res = _wait(srv, tickets)
+    for q, t in zip(QUERIES, tickets):
+        assert res[t]["status"] == 0
+        Xbb, Gbb = (a.cpu().numpy().astype(np.float64) for a in srv.fetch(t, res[t]["npix"]))
+        srv.release(t)
+        ds, nside, lo, hi = q
+        d = datasets[ds]
+        g, tau = sg.build_geometry(d.sites, nside, d.tgrid)
+        C = d.C[:, lo:hi].cpu().numpy()
+        w = d.w[:, lo:hi].cpu().numpy()
+        H = d.H[lo:hi].cpu().numpy().astype(np.float64)
+        Xo, Go, S = oracle_mod.maps(C, w, F0, DF, d.k0 + lo, g.cpu().numpy(), tau.cpu().numpy(), with_scale=True)
+        Xbo, Gbo, Sb = Xo.sum(axis=0), (H[:, None] * Go).sum(axis=0), S.sum(axis=0)
+        ex = np.max(np.abs(Xbb - Xbo) / Sb)
+        eg = np.max(np.abs(Gbb - Gbo) / Gbo)
+        print(f"query {q}: Xbb err {ex:.2e}, Gbb err {eg:.2e}")
+        assert ex <= 1e-5 and eg <= 1e-6
+    srv.close()
+
+
 def test_server_rejects_bad_queries_before_device_work(sg, datasets):
     srv = sg.Server(datasets, slots=2, hbm_budget_bytes=1 << 30)
     for bad in [(3, 8, 0, 10), (0, 12, 0, 10), (0, 8, 10, 10), (0, 8, -1, 10), (0, 8, 0, NF + 1)]:
