@@ -336,6 +336,28 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
                         float *Gam, float *Xbb, float *Gbb, void *workspace, size_t workspace_bytes,
                         hipStream_t stream);
 
+/* ---- make_maps_band without allocation ---------------------------------
+ * For callers that cannot allocate device memory or hand over a workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments (minus the workspace), same computation and the
+ * same bits as sgwb_make_maps_band; the workspace is a fixed array of
+ * SGWB_NOALLOC_SCRATCH_BYTES in device memory that the library holds on each
+ * GPU it runs on, from its first use there until the process ends.  Nothing is
+ * allocated or freed.  A call whose sgwb_make_maps_band_workspace_size()
+ * exceeds SGWB_NOALLOC_SCRATCH_BYTES fails with SGWB_ENOMEM before any device
+ * work (at nt = 898: nside 16 up to 4096 bins, nside 32 up to ~3500 bins).
+ * All calls on one GPU share that array, which keeps the last call's contents:
+ * calls that overlap in time on one GPU (several streams or threads) race and
+ * give undefined maps; the caller serialises them.  The first call on a device
+ * looks up the array's device address (hipGetSymbolAddress).
+ * Errors: as sgwb_make_maps_band; SGWB_ENOMEM as above.                      */
+#define SGWB_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int sgwb_make_maps_band_noalloc(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf,
+                                const sgwb_fgrid *fg /*host*/, int64_t k0, const float *gamma,
+                                const double *tau, int32_t npix, uint32_t flags, const float *H,
+                                int32_t k_lo, int32_t k_hi, float *X, float *Gam, float *Xbb, float *Gbb,
+                                hipStream_t stream);
+
 /* ---- batched plans ------------------------------------------------------
  * Several map jobs (baselines, resolutions, uneven bands; Sec. III.C notes
  * that maps of several baselines are made the same way and added) run as one

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsgwb.so")
 
 SGWB_MAPS_ANTIPODAL = 1
 SGWB_MAPS_VALU_X = 2
+SGWB_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 class SgwbError(RuntimeError):
@@ -102,6 +103,8 @@ _SIGNATURES = {
     "sgwb_make_maps_band": ([_VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
                              ctypes.c_uint32, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP],
                             ctypes.c_int),
+    "sgwb_make_maps_band_noalloc": ([_VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
+                                     ctypes.c_uint32, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
     "sgwb_reduce_band_workspace_size": ([_I32, _I32, _I32], ctypes.c_size_t),
     "sgwb_reduce_band": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_reduce_band_f64": ([_VP, _VP, _VP, _I32, _I32, _I32, _I32, _VP, _VP, _VP], ctypes.c_int),
@@ -318,9 +321,12 @@ def band_maps_workspace_bytes(nt: int, nf: int, npix: int, antipodal: bool = Tru
 def make_maps_band(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamma: torch.Tensor,
                    tau: torch.Tensor, H: torch.Tensor | None, k_lo: int, k_hi: int, antipodal: bool = True,
                    want_x: bool = True, want_gamma: bool = True, out=None, workspace: torch.Tensor | None = None,
-                   x_kernel: str = "auto"):
+                   x_kernel: str = "auto", noalloc: bool = False):
     """make_maps and reduce_band over columns [k_lo, k_hi) in one call (float32):
-    returns X, Gam [nf][npix] and Xbb, Gbb [npix] (None where not asked for)."""
+    returns X, Gam [nf][npix] and Xbb, Gbb [npix] (None where not asked for).
+    noalloc=True calls sgwb_make_maps_band_noalloc (the library's fixed scratch
+    array instead of a workspace; pass preallocated outputs in ``out`` for a
+    call that allocates nothing at all)."""
     if C.dim() != 2 or w.dim() != 2:
         raise SgwbError("C and w must be 2-D")
     nt, nf = w.shape
@@ -356,15 +362,23 @@ def make_maps_band(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamm
     flags = (SGWB_MAPS_ANTIPODAL if antipodal else 0) | (SGWB_MAPS_VALU_X if x_kernel == "valu" else 0)
     fg = _FGrid(float(fgrid.f0), float(fgrid.df))
     with torch.cuda.device(dev):
-        if workspace is None:
-            workspace = torch.empty(max(band_maps_workspace_bytes(nt, nf, npix, antipodal), 256), dtype=torch.uint8,
-                                    device=dev)
-        wsz = workspace.numel() * workspace.element_size()
-        rc = lib().sgwb_make_maps_band(_ptr(torch.view_as_real(C)), _ptr(w), int(w.stride(0)), nt, nf,
-                                       ctypes.byref(fg), int(k0), _ptr(gamma), _ptr(tau), npix, flags,
-                                       _ptr(H) if H is not None else None, int(k_lo), int(k_hi), _ptr(X), _ptr(G),
-                                       _ptr(Xbb), _ptr(Gbb), _ptr(workspace), wsz, _stream())
-    _check(rc, "make_maps_band")
+        if noalloc:
+            if workspace is not None:
+                raise SgwbError("make_maps_band: noalloc takes no workspace")
+            rc = lib().sgwb_make_maps_band_noalloc(_ptr(torch.view_as_real(C)), _ptr(w), int(w.stride(0)), nt, nf,
+                                                   ctypes.byref(fg), int(k0), _ptr(gamma), _ptr(tau), npix, flags,
+                                                   _ptr(H) if H is not None else None, int(k_lo), int(k_hi), _ptr(X),
+                                                   _ptr(G), _ptr(Xbb), _ptr(Gbb), _stream())
+        else:
+            if workspace is None:
+                workspace = torch.empty(max(band_maps_workspace_bytes(nt, nf, npix, antipodal), 256),
+                                        dtype=torch.uint8, device=dev)
+            wsz = workspace.numel() * workspace.element_size()
+            rc = lib().sgwb_make_maps_band(_ptr(torch.view_as_real(C)), _ptr(w), int(w.stride(0)), nt, nf,
+                                           ctypes.byref(fg), int(k0), _ptr(gamma), _ptr(tau), npix, flags,
+                                           _ptr(H) if H is not None else None, int(k_lo), int(k_hi), _ptr(X), _ptr(G),
+                                           _ptr(Xbb), _ptr(Gbb), _ptr(workspace), wsz, _stream())
+    _check(rc, "make_maps_band_noalloc" if noalloc else "make_maps_band")
     return X, G, Xbb, Gbb
 
 
