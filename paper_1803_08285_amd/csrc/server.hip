@@ -7,10 +7,12 @@
 // the narrowband maps of the band (Eqs. eq_dirtymap, eq_fisher split per bin).
 //
 // A worker thread owns the device side:
-//   * admission: pending queries are taken in arrival order while a slot (one
-//     HIP stream each) is free and the query's footprint fits in the HBM arena
-//     (a first-fit allocator over one allocation made at creation, so serving
-//     never calls the device allocator);
+//   * admission (serve_policy.h): cost-aware -- at most one heavy query (one
+//     that fills the GPU alone) runs at a time, heavy queries start in arrival
+//     order, light ones run beside it in the other slots (one HIP stream each)
+//     and pass a heavy query waiting for its turn; every query needs its HBM
+//     footprint to fit in the arena (a first-fit allocator over one allocation
+//     made at creation, so serving never calls the device allocator);
 //   * each admitted query's kernels are queued on its slot's stream, so work of
 //     queries that arrive while others run overlaps on the device;
 //   * completion is detected with an event per slot; the narrowband buffers go
@@ -18,6 +20,7 @@
 //     the ticket.
 // Results do not depend on the mix: every kernel has a fixed summation order.
 #include <math.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -31,6 +34,7 @@
 #include <thread>
 #include <vector>
 
+#include "serve_policy.h"
 #include "sgwb_internal.h"
 
 using namespace sgwb;
@@ -39,74 +43,7 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// First-fit allocator over [0, size) with coalescing free ranges (256-B aligned).
-class Arena {
-  public:
-    void init(char *base, size_t size)
-    {
-        base_ = base;
-        size_ = size;
-        free_.clear();
-        free_[0] = size;
-        used_ = 0;
-    }
-    char *alloc(size_t n)
-    {
-        n = (n + 255) / 256 * 256;
-        if (n == 0) n = 256;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= n) {
-                const size_t off = it->first, len = it->second;
-                free_.erase(it);
-                if (len > n) free_[off + n] = len - n;
-                sizes_[off] = n;
-                used_ += n;
-                return base_ + off;
-            }
-        }
-        return nullptr;
-    }
-    void release(char *p)
-    {
-        if (!p) return;
-        const size_t off = (size_t)(p - base_);
-        auto s = sizes_.find(off);
-        if (s == sizes_.end()) return;
-        size_t start = off, len = s->second;
-        used_ -= len;
-        sizes_.erase(s);
-        auto next = free_.lower_bound(start);
-        if (next != free_.end() && next->first == start + len) {
-            len += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == start) {
-                start = prev->first;
-                len += prev->second;
-                free_.erase(prev);
-            }
-        }
-        free_[start] = len;
-    }
-    // would a request of n bytes fit now (first fit)?
-    bool fits(size_t n) const
-    {
-        n = (n + 255) / 256 * 256;
-        for (const auto &kv : free_)
-            if (kv.second >= n) return true;
-        return false;
-    }
-    size_t size() const { return size_; }
-    size_t used() const { return used_; }
-
-  private:
-    char *base_ = nullptr;
-    size_t size_ = 0, used_ = 0;
-    std::map<size_t, size_t> free_;   // offset -> length
-    std::map<size_t, size_t> sizes_;  // offset -> length of live blocks
-};
+using serve::Arena;
 
 struct Geom {
     float *gamma = nullptr;
@@ -128,12 +65,14 @@ struct Query {
     float *Xbb = nullptr, *Gbb = nullptr;                             // result (arena)
     size_t ws_bytes = 0;
     int32_t npix = 0;
+    double cost = 0.0;  // map terms: segments x bins x pixels
 };
 
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     uint64_t ticket = 0;  // 0 = free
+    bool heavy = false;   // the running query is a heavy one
 };
 
 }  // namespace
@@ -153,6 +92,7 @@ struct sgwb_server {
     std::thread worker;
     std::atomic<bool> stop{false};
     Clock::time_point t0;
+    double heavy_terms = serve::kHeavyTermsDefault;
     // statistics
     uint64_t n_done = 0, n_failed = 0;
     double terms_done = 0.0;
@@ -204,10 +144,18 @@ int ensure_geometry(sgwb_server *s, int ds, int nside, hipStream_t st, Geom **ou
         return set_error(SGWB_ENOMEM, "server: no room for the seeds of dataset %d at nside %d", ds, nside);
     }
     int rc = sgwb_build_geometry(&d.bl, nside, &d.tg, g.gamma, g.tau, st);
-    if (rc) return rc;
-    if (hipEventCreateWithFlags(&g.ready, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(g.ready, st) != hipSuccess)
-        return check_hip(hipGetLastError(), "server: geometry event");
+    if (!rc && (hipEventCreateWithFlags(&g.ready, hipEventDisableTiming) != hipSuccess ||
+                hipEventRecord(g.ready, st) != hipSuccess))
+        rc = check_hip(hipGetLastError(), "server: geometry event");
+    if (rc) {
+        // nothing was queued that writes the blocks (the build refused its
+        // arguments on the host, or the event failed after it): make sure, then free
+        (void)hipStreamSynchronize(st);
+        if (g.ready) (void)hipEventDestroy(g.ready);
+        s->arena.release(reinterpret_cast<char *>(g.gamma));
+        s->arena.release(reinterpret_cast<char *>(g.tau));
+        return rc;
+    }
     auto ins = s->geoms.emplace(key, g);
     *out = &ins.first->second;
     return SGWB_OK;
@@ -287,45 +235,72 @@ void worker_loop(sgwb_server *s)
             }
             release_narrowband(s, q);
             sl.ticket = 0;
+            sl.heavy = false;
             progressed = true;
             s->cv.notify_all();
         }
-        // admit pending queries in arrival order
-        while (!s->pending.empty()) {
-            int free_slot = -1;
-            for (size_t k = 0; k < s->slots.size(); ++k)
+        // admit pending queries (serve_policy.h: cost-aware, see the header)
+        for (;;) {
+            int free_slot = -1, nfree = 0;
+            bool any_running = false, heavy_running = false;
+            for (size_t k = 0; k < s->slots.size(); ++k) {
                 if (!s->slots[k].ticket) {
-                    free_slot = (int)k;
+                    if (free_slot < 0) free_slot = (int)k;
+                    ++nfree;
+                } else {
+                    any_running = true;
+                    heavy_running = heavy_running || s->slots[k].heavy;
+                }
+            }
+            if (free_slot < 0 || s->pending.empty()) break;
+            std::vector<serve::PendingView> views;
+            views.reserve(s->pending.size());
+            bool failed = false;
+            for (size_t i = 0; i < s->pending.size(); ++i) {
+                Query &q = s->queries[s->pending[i]];
+                size_t need = query_footprint(s, q.q, &q.ws_bytes);
+                if (!s->geoms.count(std::make_pair(q.q.dataset, q.q.nside)))
+                    need += geom_bytes(s->data[q.q.dataset], q.q.nside);
+                if (need > s->arena.size()) {  // can never run: fail it now, without device work
+                    s->pending.erase(s->pending.begin() + (ptrdiff_t)i);
+                    fail_query(s, q, set_error(SGWB_ENOMEM, "server: query needs %zu bytes, arena holds %zu", need,
+                                               s->arena.size()));
+                    failed = true;
                     break;
                 }
-            if (free_slot < 0) break;
-            Query &q = s->queries[s->pending.front()];
-            size_t need = query_footprint(s, q.q, &q.ws_bytes);
-            const auto gk = std::make_pair(q.q.dataset, q.q.nside);
-            if (!s->geoms.count(gk)) need += geom_bytes(s->data[q.q.dataset], q.q.nside);
-            if (need > s->arena.size()) {
-                s->pending.pop_front();
-                fail_query(s, q, set_error(SGWB_ENOMEM, "server: query needs %zu bytes, arena holds %zu", need,
-                                           s->arena.size()));
+                views.push_back({q.cost, need});
+            }
+            if (failed) {
                 progressed = true;
                 s->cv.notify_all();
                 continue;
             }
-            bool running = false;
-            for (auto &sl : s->slots) running |= sl.ticket != 0;
-            // wait for memory while other queries run (conservative: total free must cover it)
-            if (s->arena.size() - s->arena.used() < need || !s->arena.fits(need)) {
-                if (running) break;
-            }
-            s->pending.pop_front();
+            // with nothing running a query is tried even if the free ranges look
+            // short (launch_query then reports SGWB_ENOMEM for it)
+            const int idx = serve::pick_admission(views, serve::RunningView{nfree, heavy_running}, s->heavy_terms,
+                                                  [&](size_t i) {
+                                                      const size_t n = views[i].need;
+                                                      return !any_running ||
+                                                             (s->arena.size() - s->arena.used() >= n &&
+                                                              s->arena.fits(n));
+                                                  });
+            if (idx == serve::kAdmitNone) break;
+            const uint64_t ticket = s->pending[(size_t)idx];
+            s->pending.erase(s->pending.begin() + idx);
+            Query &q = s->queries[ticket];
             const int rc = launch_query(s, q, free_slot);
             if (rc) {
+                // kernels of this query may already be queued on the slot's
+                // stream (seeds, maps): let them finish before the blocks go back
+                (void)hipStreamSynchronize(s->slots[free_slot].stream);
                 release_narrowband(s, q);
                 s->arena.release(reinterpret_cast<char *>(q.Xbb));
                 s->arena.release(reinterpret_cast<char *>(q.Gbb));
                 q.Xbb = q.Gbb = nullptr;
                 fail_query(s, q, rc);
                 s->cv.notify_all();
+            } else {
+                s->slots[free_slot].heavy = q.cost >= s->heavy_terms;
             }
             s->peak_used = std::max(s->peak_used, s->arena.used());
             progressed = true;
@@ -388,6 +363,10 @@ int sgwb_server_create(const sgwb_server_cfg *cfg, sgwb_server **out)
         }
     }
     s->t0 = Clock::now();
+    if (const char *e = getenv("SGWB_SERVER_HEAVY_TERMS")) {
+        const double v = atof(e);
+        if (v > 0.0) s->heavy_terms = v;
+    }
     int dev = 0;
     (void)hipGetDevice(&dev);
     s->worker = std::thread([s, dev] {
@@ -412,6 +391,7 @@ int sgwb_server_submit(sgwb_server *s, const sgwb_query *q, uint64_t *ticket)
     if ((int64_t)s->pending.size() >= s->queue_capacity) return set_error(SGWB_EBUSY, "server_submit: queue full");
     Query qq;
     qq.q = *q;
+    qq.cost = (double)d.tg.nt * (double)(q->k_hi - q->k_lo) * 12.0 * (double)q->nside * (double)q->nside;
     qq.ticket = s->next_ticket++;
     qq.t_submit = Clock::now();
     s->queries.emplace(qq.ticket, qq);
@@ -483,10 +463,10 @@ int sgwb_server_stats(sgwb_server *s, char *buf, size_t len)
     const int n = snprintf(buf, len,
                            "{\"done\": %llu, \"failed\": %llu, \"pending\": %zu, \"running\": %zu, \"terms_done\": %.6e, "
                            "\"arena_bytes\": %zu, \"arena_used\": %zu, \"arena_peak\": %zu, \"geometries\": %zu, "
-                           "\"slots\": %zu, \"uptime_s\": %.6f}",
+                           "\"slots\": %zu, \"heavy_terms\": %.6e, \"uptime_s\": %.6f}",
                            (unsigned long long)s->n_done, (unsigned long long)s->n_failed, s->pending.size(), running,
                            s->terms_done, s->arena.size(), s->arena.used(), s->peak_used, s->geoms.size(),
-                           s->slots.size(), secs(s, Clock::now()));
+                           s->slots.size(), s->heavy_terms, secs(s, Clock::now()));
     if (n < 0 || (size_t)n >= len) return set_error(SGWB_ENOMEM, "server_stats: buffer too small");
     return SGWB_OK;
 }
