@@ -29,13 +29,16 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X published fp32 vector peak
 PEAK_F16_MFMA_TFLOPS = 2500.0    # MI355X published dense fp16/bf16 matrix peak
 X_FLOPS_PER_TERM = 10            # algorithmic: rotation 6 + Re(y z) accumulation 4 (vector form);
                                  # the matrix form's 5-term contraction is also 10 flops per term
-# Matrix form as issued, f16 products per term per component x 2 flops: the form
-# follows the largest |eta| = 2 pi 31.5 df max|tau| of the seeds (four terms up
-# to 0.07: 8 products; five terms with m = 2 unsplit up to 0.17: 9; else 11).
-def x_mfma_issued_per_term(eta: float) -> int:
-    return 2 * (8 if eta <= 0.07 else 9 if eta <= 0.17 else 11)
+# Matrix form as issued: float16 products per term per component x 2 flops x 2
+# components / 2 pixels per antipodal pair = 2 x products, by the form the call
+# took (four terms: 8 products; five with m = 2 unsplit: 9; split: 11).
+ISSUED_FLOPS_PER_TERM = {"mfma4": 16, "mfma5": 18, "mfma5_split": 22}
 
-CPU_BASELINE_TARGET_S = 15.0
+CPU_BASELINE_TARGET_S = 24.0
+# The arithmetic the path computes in: the dirty map as float16 hi + lo products
+# on the matrix cores with float64 phase reduction, the beam as bfloat16 hi + lo
+# products, both accumulated in float32.
+DTYPE_LABEL = "split-f16 (X) / split-bf16 (Gamma) MFMA, f32 accumulate, f64 phase"
 # Sources of the matrix-core dirty-map kernel: a recorded HBM traffic figure is
 # reported only while these are unchanged since the counters were taken.
 X_KERNEL_SOURCES = ("paper_1803_08285_amd/csrc/dirty_map_mfma.hip", "paper_1803_08285_amd/csrc/sgwb_internal.h")
@@ -93,8 +96,20 @@ def make_inputs(sg, torch, wl, dev):
                 C_host=C.astype(np.complex64).astype(np.complex128), w_host=w.astype(np.float64))
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(inp, wl, target_s=CPU_BASELINE_TARGET_S):
-    """Time the FP64 oracle on a bounded, deterministic sample of the workload."""
+    """The FP64 oracle on a bounded, deterministic sample of the workload: random
+    (bin, pixel) outputs x all segments, X and Gamma.  Median rate of three runs
+    on all host threads, plus one run on a single thread."""
     import oracle
 
     oracle.build()
@@ -104,23 +119,77 @@ def cpu_baseline(inp, wl, target_s=CPU_BASELINE_TARGET_S):
     th = inp["tau"].cpu().numpy()
     threads = oracle.default_threads()
     rng = np.random.default_rng(77)
-    # calibrate on a small sample, then size the timed sample for ~target_s
+
+    def run(n, nthreads):
+        cols = rng.integers(0, fgd.nf, n)
+        pix = rng.integers(0, npix, n)
+        t0 = time.perf_counter()
+        oracle.maps_at(inp["C_host"], inp["w_host"], fgd.f0, fgd.df, fgd.k0, gh, th, cols, pix, nthreads=nthreads)
+        return time.perf_counter() - t0
+
+    # calibrate on a run of at least half a second, then size each timed run
+    # for a quarter of the target
     n0 = 2000
-    cols = rng.integers(0, fgd.nf, n0)
-    pix = rng.integers(0, npix, n0)
-    t0 = time.perf_counter()
-    oracle.maps_at(inp["C_host"], inp["w_host"], fgd.f0, fgd.df, fgd.k0, gh, th, cols, pix, nthreads=threads)
-    dt0 = time.perf_counter() - t0
-    n = int(max(n0, min(4e7, n0 * target_s / max(dt0, 1e-3))))
-    cols = rng.integers(0, fgd.nf, n)
-    pix = rng.integers(0, npix, n)
-    t0 = time.perf_counter()
-    oracle.maps_at(inp["C_host"], inp["w_host"], fgd.f0, fgd.df, fgd.k0, gh, th, cols, pix, nthreads=threads)
-    dt = time.perf_counter() - t0
-    terms = n * tg.nt
-    return {"value": terms / dt, "unit": "terms/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} random (bin, pixel) outputs x all {tg.nt} segments (X and Gam), "
-                      f"{dt:.1f} s wall on {threads} threads"}
+    dt0 = run(n0, threads)
+    while dt0 < 0.5 and n0 < 4e7:
+        n0 *= 4
+        dt0 = run(n0, threads)
+    n = int(max(n0, min(4e7, n0 * 0.25 * target_s / max(dt0, 1e-3))))
+    dts = [run(n, threads) for _ in range(3)]
+    dt = float(np.median(dts))
+    n1 = int(max(200, n / max(threads, 1)))
+    dt1 = run(n1, 1)
+    return {"value": n * tg.nt / dt, "unit": "terms/s", "cores": threads, "kind": "oracle",
+            "single_core_value": n1 * tg.nt / dt1, "cpu_model": cpu_model(),
+            "runs_s": [round(x, 3) for x in dts],
+            "sample": f"{n} random (bin, pixel) outputs x all {tg.nt} segments (X and Gamma) per run, "
+                      f"median of 3 runs on {threads} threads ({dt:.1f} s); single thread: {n1} outputs in {dt1:.1f} s"}
+
+
+def result_errors(sg, torch, inp, wl, X, G, Xbb, Gbb):
+    """Errors of the step's outputs against the FP64 oracle on the same stored
+    inputs, on a deterministic sample: 4 full rows (bins) and 3 full columns
+    (pixels).  X: max |dX| / S (S = sum_t |w gamma| |C|), the row-wise
+    ||dX||_inf / ||X_ref||_inf over the full rows, and the elementwise relative
+    error where |X_ref| >= 0.1 S; Gamma: elementwise relative; the broadband maps
+    at the full columns (Xbb against sum_k S, Gbb relative)."""
+    import oracle
+
+    oracle.build()
+    fgd = wl.fgrid
+    npix = 12 * wl.nside ** 2
+    rows, cols = synth.random_selection(40 + 3, fgd.nf, npix, 4, 3)
+    ri, ci = torch.from_numpy(rows).to(X.device), torch.from_numpy(cols).to(X.device)
+    Xs = X[ri, ci].double().cpu().numpy()
+    Gs = G[ri, ci].double().cpu().numpy()
+    gh, th = inp["gamma"].cpu().numpy(), inp["tau"].cpu().numpy()
+    Xo, Go, S = oracle.maps_at(inp["C_host"], inp["w_host"], fgd.f0, fgd.df, fgd.k0, gh, th, rows, cols)
+    dX = np.abs(Xs - Xo)
+    out = {"x_max_abs_over_S": float(np.max(dX / S)), "gamma_max_rel": float(np.max(np.abs(Gs - Go) / Go))}
+    nrow = np.unique(rows[:4 * npix]).size
+    rw = [float(np.max(dX[i * npix:(i + 1) * npix]) / np.max(np.abs(Xo[i * npix:(i + 1) * npix])))
+          for i in range(nrow)]
+    out["x_rowwise_inf_rel"] = max(rw)
+    big = np.abs(Xo) >= 0.1 * S
+    out["x_elementwise_rel_where_ge_0.1S"] = float(np.max(dX[big] / np.abs(Xo[big]))) if big.any() else None
+    out["x_elements_ge_0.1S"] = int(big.sum())
+    # broadband maps at the full columns (all bins of 3 pixels)
+    c0 = 4 * npix
+    H = synth.spectrum_H(fgd.freqs())
+    pcols = np.unique(cols[c0:])
+    xb, gb, xbe, gbe = [], [], [], []
+    for p in pcols:
+        m = cols[c0:] == p
+        k = rows[c0:][m]
+        xo, go, so = Xo[c0:][m], Go[c0:][m], S[c0:][m]
+        order = np.argsort(k)
+        xbo, gbo, sbo = xo[order].sum(), (H[k[order]] * go[order]).sum(), so[order].sum()
+        xbe.append(abs(float(Xbb[int(p)]) - xbo) / sbo)
+        gbe.append(abs(float(Gbb[int(p)]) - gbo) / gbo)
+    out["xbb_max_abs_over_sumS"] = float(max(xbe))
+    out["gbb_max_rel"] = float(max(gbe))
+    out["sample"] = f"{nrow} full bins x {npix} pixels + {pcols.size} full pixels x {fgd.nf} bins ({rows.size} outputs)"
+    return out
 
 
 def bench_batched(args, torch, sg):
@@ -177,7 +246,7 @@ def bench_batched(args, torch, sg):
     out = {
         "metric": "map terms/s (t*f*pix) for X+Gamma", "value": terms / (ms_plan * 1e-3), "unit": "terms/s",
         "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": ms_plan, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_LABEL, "data": "synthetic",
         "config": {"workload": "batched_AB64_AC32_BC16", "terms_per_step": terms, "jobs": len(jobs),
                    "parallelism": "single GPU"},
         "plain_path": {"value": terms / (ms_plain * 1e-3), "ms_per_step": ms_plain},
@@ -224,7 +293,7 @@ def bench_fisher_overlap(args, torch, sg):
     log(f"overlap-corrected Fisher diagonal: {t_ov:.2f} ms; plain diagonal {t_plain:.2f} ms")
     print(json.dumps({"metric": "overlap-corrected Fisher diagonal terms/s (t*f*pix)", "value": terms / (t_ov * 1e-3),
                       "unit": "terms/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": t_ov,
-                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_LABEL,
                       "data": "synthetic", "config": {"workload": wl.name + "_fisher_overlap", "nt": tg.nt,
                                                       "nf": fgd.nf, "npix": npix, "parallelism": "single GPU"},
                       "plain_diagonal_ms": t_plain}), flush=True)
@@ -255,7 +324,8 @@ def bench_fisher_full(args, torch, sg):
     P = torch.empty(npix, dtype=torch.float32, device=dev)
 
     def full():
-        sg.fisher_full(a, b, inp["H"], fg, fgd.k0, 0, fgd.nf, inp["gamma"], inp["tau"], out=G, workspace=ws)
+        sg.fisher_full(a, b, inp["H"], fg, fgd.k0, 0, fgd.nf, inp["gamma"], inp["tau"], out=G, workspace=ws,
+                       antipodal=not args.fisher_plain)
 
     def clean():
         sg.clean_map_cg(G, Xbb, args.cg_iters, out=P)
@@ -275,14 +345,21 @@ def bench_fisher_full(args, torch, sg):
     t_cg = timed(clean, args.steps)
     resid = float(torch.linalg.norm(G.double() @ P.double() - Xbb.double()) / torch.linalg.norm(Xbb.double()))
     terms = tg.nt * npix * (npix + 1) // 2
-    tbps = terms * FISHER_TABLE_BYTES_PER_TERM / (t_full * 1e-3) / 1e12
+    # table lookups actually made: the whole upper triangle, or with antipodal
+    # seeds the two northern blocks' triangles (about half)
+    nh = npix // 2
+    lookups = tg.nt * (nh * (nh + 1) if not args.fisher_plain else npix * (npix + 1) // 2)
+    tbps = lookups * FISHER_TABLE_BYTES_PER_TERM / (t_full * 1e-3) / 1e12
     log(f"full Fisher matrix {npix}^2 over {tg.nt} segments: {t_full:.2f} ms; CG x{args.cg_iters}: {t_cg:.2f} ms; "
         f"relative residual {resid:.3e}")
     print(json.dumps({"metric": "full Fisher matrix pair-terms/s (t*p*q, q>=p)", "value": terms / (t_full * 1e-3),
                       "unit": "terms/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": t_full,
-                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f32 table lookups, f64 delay table",
                       "data": "synthetic", "config": {"workload": wl.name + "_fisher_full", "nt": tg.nt,
-                                                      "nf": fgd.nf, "npix": npix, "parallelism": "single GPU"},
+                                                      "nf": fgd.nf, "npix": npix, "parallelism": "single GPU",
+                                                      "antipodal_blocks": not args.fisher_plain,
+                                                      "table_lookups": lookups},
                       "roofline": {"bound": "lds", "achieved": tbps * 1e3, "peak": PEAK_LDS_TBPS * 1e3,
                                    "unit": "GB/s", "frac": tbps / PEAK_LDS_TBPS, "traffic": None},
                       "clean_map": {"cg_iters": args.cg_iters, "ms": t_cg, "relative_residual": resid}}),
@@ -354,16 +431,18 @@ def bench_folded(args, torch, sg):
     print(json.dumps({"metric": "folded-pipeline map terms/s (t*f*pix, X + overlap-corrected Gamma)",
                       "value": terms / (ms * 1e-3), "unit": "terms/s", "n_gpus": 1, "steps": args.steps,
                       "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-                      "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "vs_baseline": None, "dtype": DTYPE_LABEL, "data": "synthetic",
                       "config": {"workload": f"{wl.name}_folded_{nd}_days", "days": nd, "nt": nt, "nf": nf,
                                  "npix": npix, "parallelism": "single GPU"},
                       "phases_ms": ph, "fold_GBps": in_bytes / (ph["fold"] * 1e-3) / 1e9}), flush=True)
 
 
-def bench_serve(args, torch, sg):
-    """Serving form: Poisson streams of map queries against three resident
-    baselines, through the continuous-batching server and through the plain
-    per-query path (one query at a time, synchronous), same queries."""
+def serving_sweep(args, torch, sg, rates, duration):
+    """Poisson streams of map queries (200 queries/s x 60 s is the served
+    workload; other rates for a sweep) against three resident baselines, through
+    the continuous-batching server and through the plain per-query path (one
+    query at a time, synchronous), same queries, same accuracy (the same
+    kernels: each served result is bitwise the direct call's)."""
     dev = torch.device("cuda:0")
     datasets = []
     for i, bl in enumerate(("AB", "AC", "BC")):
@@ -375,6 +454,7 @@ def bench_serve(args, torch, sg):
                                    torch.from_numpy(synth.spectrum_H(f).astype(np.float32)).to(dev),
                                    sg.FGrid(fgd.f0, fgd.df), fgd.k0, synth.baseline_sites(bl),
                                    sg.TGrid(tg.nt, tg.t0, tg.stride, tg.dur)))
+        del C, w
         log(f"dataset {bl} resident")
     nt = synth.TGRID_FULL.nt
     srv = sg.Server(datasets, slots=args.slots, hbm_budget_bytes=args.arena_gib << 30)
@@ -399,14 +479,15 @@ def bench_serve(args, torch, sg):
             plain_query(ds, n, 0, 1)
 
     results = []
-    for rate in args.rates:
-        qs = synth.serving_queries(rate, args.duration)
+    for rate in rates:
+        qs = synth.serving_queries(rate, duration)
         terms = sum(nt * (hi - lo) * 12 * n * n for _, _, n, lo, hi in qs)
         # server
         t0 = time.perf_counter()
         tickets = {}
         i = 0
         done = {}
+        next_log = 10.0
         while len(done) < len(qs):
             now = time.perf_counter() - t0
             while i < len(qs) and qs[i][0] <= now:
@@ -421,7 +502,11 @@ def bench_serve(args, torch, sg):
                     done[tk] = r
                     srv.release(tk)
                     del tickets[tk]
+            if now >= next_log:
+                log(f"rate {rate}/s server: {now:.0f} s, {len(done)}/{len(qs)} queries done")
+                next_log += 10.0
             time.sleep(0.0002)
+        assert all(r["status"] == 0 for r in done.values()), "a served query failed"
         lat = np.array([r["t_done"] - r["t_submit"] for r in done.values()]) * 1e3
         span = max(r["t_done"] for r in done.values()) - min(r["t_submit"] for r in done.values())
         st = srv.stats()
@@ -430,27 +515,39 @@ def bench_serve(args, torch, sg):
         # plain per-query path, same arrivals, first come first served
         t0 = time.perf_counter()
         plat = []
+        next_log = 10.0
         for (ta, ds, n, lo, hi) in qs:
             now = time.perf_counter() - t0
             if now < ta:
                 time.sleep(ta - now)
             plain_query(ds, n, lo, hi)
             plat.append((time.perf_counter() - t0 - ta) * 1e3)
+            if now >= next_log:
+                log(f"rate {rate}/s plain: {now:.0f} s, {len(plat)}/{len(qs)} queries done")
+                next_log += 10.0
         pspan = time.perf_counter() - t0 - qs[0][0]
         plat = np.array(plat)
         log(f"rate {rate}/s plain: p50 {np.percentile(plat, 50):.1f} ms, p99 {np.percentile(plat, 99):.1f} ms, "
             f"{terms / pspan:.3e} terms/s")
-        results.append({"rate_hz": rate, "queries": len(qs), "terms": terms,
+        results.append({"rate_hz": rate, "duration_s": duration, "queries": len(qs), "terms": terms,
                         "server": {"terms_per_s": terms / span, "p50_ms": float(np.percentile(lat, 50)),
                                    "p99_ms": float(np.percentile(lat, 99)), "arena_peak_bytes": st["arena_peak"]},
                         "plain": {"terms_per_s": terms / pspan, "p50_ms": float(np.percentile(plat, 50)),
                                   "p99_ms": float(np.percentile(plat, 99))}})
     srv.close()
+    del datasets, geoms
+    torch.cuda.empty_cache()
+    return results
+
+
+def bench_serve(args, torch, sg):
+    """Serving form alone: a rate sweep (--rates, --duration s each)."""
+    results = serving_sweep(args, torch, sg, args.rates, args.duration)
     top = results[-1]
     out = {
         "metric": "map terms/s (t*f*pix) for X+Gamma; p50/p99 query latency", "value": top["server"]["terms_per_s"],
         "unit": "terms/s", "n_gpus": 1, "steps": len(results), "warmup": 1, "ms_per_step": None,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_LABEL, "data": "synthetic",
         "config": {"workload": "serving_poisson", "duration_s": args.duration, "slots": args.slots,
                    "nsides": list(synth.NSIDES_SERVED), "max_band": 4096, "parallelism": "single GPU"},
         "latency_ms": {"p50": top["server"]["p50_ms"], "p99": top["server"]["p99_ms"]},
@@ -464,10 +561,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", type=int, default=2, help="2: full band nside 32; 3: full band nside 64")
+    ap.add_argument("--workload", type=int, default=3, help="3: full band nside 64 (default); 2: full band nside 32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-errors", action="store_true", help="skip the per-result errors against the oracle")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="serving leg of the default run: Poisson queries at 200/s for this long (0: none)")
     ap.add_argument("--batched", action="store_true", help="batched plan of three uneven baseline jobs")
-    ap.add_argument("--serve", action="store_true", help="Poisson query stream through the server")
+    ap.add_argument("--serve", action="store_true", help="Poisson query stream through the server (rate sweep)")
     ap.add_argument("--folded", action="store_true",
                     help="fold --days synthetic days, then X, overlap-corrected Gamma and band sums")
     ap.add_argument("--days", type=int, default=10)
@@ -476,6 +576,8 @@ def main():
     ap.add_argument("--fisher-full", action="store_true",
                     help="full Fisher matrix of the whole band and the CG clean map for --workload")
     ap.add_argument("--cg-iters", type=int, default=50)
+    ap.add_argument("--fisher-plain", action="store_true",
+                    help="full Fisher matrix without the antipodal block decomposition")
     ap.add_argument("--rates", type=float, nargs="+", default=[25.0, 50.0, 100.0, 200.0])
     ap.add_argument("--duration", type=float, default=5.0)
     ap.add_argument("--slots", type=int, default=4)
@@ -523,8 +625,8 @@ def main():
 
     # One step: the dirty map with its band sum, then the beam with its band sum
     # (make_maps_band: the map kernels add their tiles' band sums, one small
-    # kernel per map adds those up).  The band phase below is what is left
-    # between the two calls' ends: nothing.
+    # kernel per map adds those up).  Events are recorded on torch's current
+    # stream, the stream the library's kernels are queued on.
     def step(evs=None):
         if evs:
             evs[0].record()
@@ -536,13 +638,17 @@ def main():
                           want_x=False, out=(None, G, None, Gbb), workspace=ws)
         if evs:
             evs[2].record()
-            evs[3].record()
 
+    # the dirty map's form (read back right after an X call)
+    sg.make_maps_band(inp["C"], inp["w"], fg, fgd.k0, inp["gamma"], inp["tau"], None, 0, fgd.nf,
+                      want_gamma=False, out=(X, None, Xbb, None), workspace=ws)
+    x_form = sg.last_x_form()
+    log(f"dirty-map form: {x_form}")
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -552,27 +658,25 @@ def main():
     log(f"timed {args.steps} steps in {wall:.3f} s")
     t_x = np.array([e[0].elapsed_time(e[1]) for e in evs])
     t_g = np.array([e[1].elapsed_time(e[2]) for e in evs])
-    t_b = np.array([e[2].elapsed_time(e[3]) for e in evs])
-    t_step = np.array([e[0].elapsed_time(e[3]) for e in evs])
+    t_step = np.array([e[0].elapsed_time(e[2]) for e in evs])
     ms_per_step = wall * 1e3 / args.steps
     terms = tg.nt * fgd.nf * npix
     x_tflops = X_FLOPS_PER_TERM * terms / (t_x.mean() * 1e-3) / 1e12
-    matrix_form = fgd.df * 2 * 6.371e6 / 299792458.0 * 2 * np.pi * 31.5 <= 0.29  # where make_maps uses MFMA
-    eta = 2 * np.pi * 31.5 * fgd.df * float(inp["tau"].abs().max())
-    if matrix_form:
+    if x_form and x_form.startswith("mfma"):
         rec = recorded_traffic(wl.name)
-        roofline = {"bound": "mfma", "kernel": "xm_main_kernel (f16 MFMA dirty map)", "achieved": x_tflops,
+        roofline = {"bound": "mfma", "kernel": "xm_main_kernel (split-f16 MFMA dirty map)", "achieved": x_tflops,
                     "peak": PEAK_F16_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": x_tflops / PEAK_F16_MFMA_TFLOPS,
                     "traffic": rec["hbm_bytes"] if rec else None, "flops_per_term": X_FLOPS_PER_TERM,
-                    "launch_ms": float(t_x.mean()),
-                    "issued_tflops": x_mfma_issued_per_term(eta) * terms / (t_x.mean() * 1e-3) / 1e12,
-                    "frac_vs_fp32_vector_peak": x_tflops / PEAK_FP32_VECTOR_TFLOPS}
+                    "x_form": x_form, "launch_ms": float(t_x.mean()),
+                    "issued_flops_per_term": ISSUED_FLOPS_PER_TERM[x_form],
+                    "issued_tflops": ISSUED_FLOPS_PER_TERM[x_form] * terms / (t_x.mean() * 1e-3) / 1e12}
         if rec:
             roofline["traffic_algorithmic_bytes"] = rec["algorithmic_bytes"]
     else:
         roofline = {"bound": "alu", "kernel": "dirty_map_kernel<float, pair>", "achieved": x_tflops,
                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": x_tflops / PEAK_FP32_VECTOR_TFLOPS,
-                    "traffic": None, "flops_per_term": X_FLOPS_PER_TERM, "launch_ms": float(t_x.mean())}
+                    "traffic": None, "flops_per_term": X_FLOPS_PER_TERM, "x_form": x_form,
+                    "launch_ms": float(t_x.mean())}
 
     if args.copy_calib_mib:
         nbytes = args.copy_calib_mib << 20
@@ -584,10 +688,24 @@ def main():
         log(f"copy calibration: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
 
+    errors = None
+    if not args.no_errors:
+        log("errors against the FP64 oracle on a sample of the outputs")
+        errors = result_errors(sg, torch, inp, wl, X, G, Xbb, Gbb)
+        log(f"errors: {errors}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on the host cores")
         cpu = cpu_baseline(inp, wl)
+
+    serving = None
+    if args.serve_seconds > 0:
+        del X, G, ws
+        inp.pop("C_host"), inp.pop("w_host")
+        torch.cuda.empty_cache()
+        log(f"serving leg: 200 queries/s for {args.serve_seconds:.0f} s, server and plain path")
+        serving = serving_sweep(args, torch, sg, [200.0], args.serve_seconds)[0]
 
     out = {
         "metric": "map terms/s (t*f*pix) for X+Gamma",
@@ -600,16 +718,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": DTYPE_LABEL,
         "data": "synthetic (seeded noise model + injected point sources)",
         "config": {"workload": wl.name, "baseline": wl.baseline, "nt": tg.nt, "nf": fgd.nf, "nside": wl.nside,
                    "npix": npix, "f0_hz": fgd.f0, "df_hz": fgd.df, "terms_per_step": terms,
                    "parallelism": "single GPU"},
         "roofline": roofline,
-        "phases_ms": {"dirty_map": float(t_x.mean()), "beam": float(t_g.mean()), "band": float(t_b.mean())},
-        "latency_ms": {"p50": float(np.percentile(t_step, 50)), "p99": float(np.percentile(t_step, 99))},
+        "phases_ms": {"dirty_map": float(t_x.mean()), "beam": float(t_g.mean())},
+        "step_latency_ms": {"p50": float(np.percentile(t_step, 50)), "p99": float(np.percentile(t_step, 99))},
+        "errors_vs_oracle": errors,
         "cpu_baseline": cpu,
     }
+    if serving:
+        out["latency_ms"] = {"p50": serving["server"]["p50_ms"], "p99": serving["server"]["p99_ms"],
+                             "what": "served query latency, Poisson 200 queries/s"}
+        out["serving"] = serving
     print(json.dumps(out), flush=True)
 
 
