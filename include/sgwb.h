@@ -245,8 +245,15 @@ int sgwb_fisher_overlap(const float *v, const float *u, const float *w, int64_t 
  * Gbb for the same w).
  * Inputs (device): a float32 [rank][nt]; b float32 [rank][nf], H float32 [nf]
  * (column c = bin k0 + c); gamma float32, tau float64 [nt][npix] as for
- * sgwb_make_maps (no antipodal pairing: every pixel is a row and a column).
- * 0 <= clo < chi <= nf, 1 <= rank <= 64.
+ * sgwb_make_maps.  0 <= clo < chi <= nf, 1 <= rank <= 64.
+ * flags: 0 (every pixel a row and a column, any seeds), or
+ * SGWB_MAPS_ANTIPODAL: the seeds have the exact antipodal symmetry that
+ * sgwb_build_geometry writes (npix = 12 nside^2), so G(a(p),a(q)) = G(p,q) and
+ * G(p,a(q)) = G(q,a(p)) for the antipode a; only the upper triangles of the
+ * two northern blocks are computed (half the work) and each value is written
+ * to its four entries.  Same tolerance; equal to the flag-free matrix up to
+ * float32 rounding of the weight products.  The promise is spot-checked on the
+ * device (first, middle and last segment); seeds that fail give G = NaN.
  * Output: G float32 [npix][npix] row-major, symmetric (overwritten).
  * Arithmetic, per rank: Wd_r and its derivative tabulated in float64 on 64
  * points per period of the highest band frequency over 0 <= D <= 4 R_earth / c,
@@ -259,13 +266,14 @@ int sgwb_fisher_overlap(const float *v, const float *u, const float *w, int64_t 
  * Workspace: at least sgwb_fisher_full_workspace_size() bytes (0 for
  * arguments out of range), 256-byte aligned, owned by the caller.
  * Errors: SGWB_EINVAL (null pointer, nt/nf/npix < 1, rank out of range, band
- * out of range or reaching above 24 kHz, bad grid, misaligned pointer, more than
+ * out of range or reaching above 24 kHz, bad grid, unknown flag bits or the
+ * antipodal flag with a non-HEALPix npix, misaligned pointer, more than
  * 2^31 - 1 matrix tiles), SGWB_ENOMEM (workspace too small).                 */
 size_t sgwb_fisher_full_workspace_size(const sgwb_fgrid *fg /*host*/, int64_t k0, int32_t chi, int32_t nt,
                                        int32_t npix);
 int sgwb_fisher_full(const float *a, const float *b, int32_t rank, const float *H, int32_t nf,
                      const sgwb_fgrid *fg /*host*/, int64_t k0, int32_t clo, int32_t chi, const float *gamma,
-                     const double *tau, int32_t nt, int32_t npix, float *G, void *workspace,
+                     const double *tau, int32_t nt, int32_t npix, uint32_t flags, float *G, void *workspace,
                      size_t workspace_bytes, hipStream_t stream);
 
 /* ---- clean map: Eq. eq_ML_linear and its footnote ---------------------------
@@ -416,12 +424,18 @@ int sgwb_plan_describe(const sgwb_plan *plan, char *buf, size_t len);
  * [k0, k0 + nf) of grid fg; device memory owned by the caller, kept alive and
  * unchanged until sgwb_server_destroy.  The seeds of each (dataset, nside)
  * are built on first use and kept.
- * A worker thread admits queries in arrival order while one of `slots` HIP
- * streams is free and the query's footprint (two band x npix float32 maps,
- * the beam and band workspaces, the result, and new seeds) fits in an HBM
- * arena of hbm_budget_bytes (0: 60 % of the free memory) reserved at
- * creation; queries that arrive while others run are admitted as slots and
- * memory free up, and their kernels overlap on the device.  A query larger
+ * A worker thread admits queries while one of `slots` HIP streams is free and
+ * the query's footprint (two band x npix float32 maps, the beam and band
+ * workspaces, the result, and new seeds) fits in an HBM arena of
+ * hbm_budget_bytes (0: 60 % of the free memory) reserved at creation; queries
+ * that arrive while others run are admitted as slots and memory free up, and
+ * their kernels overlap on the device.  Admission is cost-aware: a query of at
+ * least 1e10 map terms (segments x bins x pixels; SGWB_SERVER_HEAVY_TERMS in
+ * the environment overrides the threshold) fills the GPU alone, so at most
+ * one such heavy query runs at a time and heavy queries start in arrival
+ * order; lighter queries start in arrival order among themselves, run in the
+ * other slots beside it and may pass a heavy query that waits for its turn; a
+ * query waiting for memory holds back every query behind it.  A query larger
  * than the whole arena fails with SGWB_ENOMEM; nothing is ever allocated
  * after creation.  Results are bitwise the same alone and in any mix.
  * submit is non-blocking (SGWB_EBUSY when queue_capacity queries are

@@ -96,7 +96,7 @@ _SIGNATURES = {
                              ctypes.c_uint32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_fisher_full_workspace_size": ([ctypes.POINTER(_FGrid), _I64, _I32, _I32, _I32], ctypes.c_size_t),
     "sgwb_fisher_full": ([_VP, _VP, _I32, _VP, _I32, ctypes.POINTER(_FGrid), _I64, _I32, _I32, _VP, _VP, _I32, _I32,
-                          _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
+                          ctypes.c_uint32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_clean_map_workspace_size": ([_I32], ctypes.c_size_t),
     "sgwb_clean_map_cg": ([_VP, _VP, _I32, _I32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_make_maps_band_workspace_size": ([_I32, _I32, _I32, ctypes.c_uint32], ctypes.c_size_t),
@@ -508,11 +508,13 @@ def fisher_full_workspace_bytes(fgrid: FGrid, k0: int, khi: int, nt: int, npix: 
 
 
 def fisher_full(a: torch.Tensor, b: torch.Tensor, H: torch.Tensor, fgrid: FGrid, k0: int, klo: int, khi: int,
-                gamma: torch.Tensor, tau: torch.Tensor, out=None, workspace: torch.Tensor | None = None):
+                gamma: torch.Tensor, tau: torch.Tensor, out=None, workspace: torch.Tensor | None = None,
+                antipodal: bool = False):
     """Full Fisher matrix G [npix][npix] of the bins [klo, khi) (Eq. eq_fisher,
     broadband H weighting of Sec. V) for weights w(t,c) = sum_r a[r][t] b[r][c]:
     a float32 [nt] or [rank][nt], b float32 [nf] or [rank][nf], H float32 [nf]
-    (column c = bin k0 + c)."""
+    (column c = bin k0 + c).  antipodal=True: seeds from build_geometry (all
+    12 nside^2 pixels), half the work."""
     nt, npix = gamma.shape
     a2 = a.reshape(1, -1) if a.dim() == 1 else a
     b2 = b.reshape(1, -1) if b.dim() == 1 else b
@@ -535,7 +537,8 @@ def fisher_full(a: torch.Tensor, b: torch.Tensor, H: torch.Tensor, fgrid: FGrid,
             workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
         wsz = workspace.numel() * workspace.element_size()
         rc = lib().sgwb_fisher_full(_ptr(a2), _ptr(b2), rank, _ptr(H), nf, ctypes.byref(fg), int(k0), int(klo),
-                                    int(khi), _ptr(gamma), _ptr(tau), nt, npix, _ptr(G), _ptr(workspace), wsz,
+                                    int(khi), _ptr(gamma), _ptr(tau), nt, npix,
+                                    SGWB_MAPS_ANTIPODAL if antipodal else 0, _ptr(G), _ptr(workspace), wsz,
                                     _stream())
     _check(rc, "fisher_full")
     return G

@@ -412,7 +412,8 @@ size_t sgwb_fisher_full_workspace_size(const sgwb_fgrid *fg, int64_t k0, int32_t
 
 int sgwb_fisher_full(const float *a, const float *b, int32_t rank, const float *H, int32_t nf, const sgwb_fgrid *fg,
                      int64_t k0, int32_t clo, int32_t chi, const float *gamma, const double *tau, int32_t nt,
-                     int32_t npix, float *G, void *workspace, size_t workspace_bytes, hipStream_t stream)
+                     int32_t npix, uint32_t flags, float *G, void *workspace, size_t workspace_bytes,
+                     hipStream_t stream)
 {
     if (!a || !b || !H || !fg || !gamma || !tau || !G) return set_error(SGWB_EINVAL, "fisher_full: null pointer");
     if (nt < 1 || nf < 1 || npix < 1) return set_error(SGWB_EINVAL, "fisher_full: nt, nf, npix must be >= 1");
@@ -426,6 +427,13 @@ int sgwb_fisher_full(const float *a, const float *b, int32_t rank, const float *
     if (((uintptr_t)a % 4) || ((uintptr_t)b % 4) || ((uintptr_t)H % 4) || ((uintptr_t)gamma % 4) ||
         ((uintptr_t)tau % 8) || ((uintptr_t)G % 4))
         return set_error(SGWB_EINVAL, "fisher_full: misaligned pointer");
+    if (flags & ~SGWB_MAPS_ANTIPODAL) return set_error(SGWB_EINVAL, "fisher_full: unknown flag bits");
+    int64_t nside = 0;
+    if (flags & SGWB_MAPS_ANTIPODAL) {
+        nside = nside_of_npix(npix);
+        if (nside == 0)
+            return set_error(SGWB_EINVAL, "fisher_full: SGWB_MAPS_ANTIPODAL needs npix = 12 nside^2, nside a power of two");
+    }
     const int64_t ntile = ((int64_t)npix + 63) / 64;
     if (ntile * (ntile + 1) / 2 > 0x7fffffff) return set_error(SGWB_EINVAL, "fisher_full: npix too large");
     if (!workspace || (uintptr_t)workspace % 256)
@@ -434,7 +442,7 @@ int sgwb_fisher_full(const float *a, const float *b, int32_t rank, const float *
     if (workspace_bytes < need)
         return set_error(SGWB_ENOMEM, "fisher_full: workspace of %zu bytes needed, %zu given", need, workspace_bytes);
     return check_hip(launch_fisher_full(a, b, rank, H, nf, clo, chi, fg->f0_hz, fg->df_hz, k0, gamma, tau, nt, npix,
-                                        G, workspace, stream),
+                                        nside, G, workspace, stream),
                      "full Fisher launch");
 }
 

@@ -13,6 +13,14 @@
 // fixed-point table coordinates (17 fraction bits below 3 kHz), so a delay
 // difference is an exact integer: its high bits pick the interval, its low
 // bits the position in it, and (p,q) and (q,p) do the same arithmetic.
+//
+// Antipodal seeds (gamma(a(p)) = gamma(p), tau(a(p)) = -tau(p), a(p) the
+// antipode) make the delays' fixed-point coordinates mirror exactly,
+// U(a(p)) = 2^31 - U(p), and W is even, so the matrix has two distinct blocks
+// over the northern pixels: G(p,q) = G(a(p),a(q)) with |U_p - U_q|, and
+// G(p,a(q)) = G(q,a(p)) with |U_p - (2^31 - U_q)|.  Only the upper triangles of
+// those two blocks are computed (half the table lookups of the whole upper
+// triangle) and each value is written to its four places.
 #include <cstdlib>
 #include <cstring>
 
@@ -25,6 +33,7 @@ constexpr int kFtSeg = 16;   // segments staged per step
 constexpr int kFracBitsMax = 17;  // fixed-point fraction bits of a delay in table steps
 constexpr int kFracBitsMin = 14;
 constexpr uint32_t kDelayBias = 1u << 30;
+constexpr uint32_t kDelayMirror = 2u * kDelayBias;  // U(a(p)) = kDelayMirror - U(p)
 constexpr double kMaxDelay = 2.0 * kEarthRadius / kLightSpeed;  // |tau| bound on the Earth
 
 // Table step, number of intervals J (|tau_p - tau_q| / delta < J - 1) and the
@@ -137,6 +146,46 @@ __device__ __forceinline__ void store_pair(float *__restrict__ G, int64_t npix, 
     }
 }
 
+// Tile k of the computed triangles: with antipodal seeds (nside > 0) tiles
+// [0, half) are the northern block's upper triangle and [half, 2 half) the
+// northern x southern block's (columns mirrored, ns = true).
+__device__ __forceinline__ void fisher_tile(int64_t k, int64_t nT, bool anti, int64_t &tr, int64_t &tc, bool &ns)
+{
+    const int64_t half = nT * (nT + 1) / 2;
+    ns = anti && k >= half;
+    tri_tile(ns ? k - half : k, nT, tr, tc);
+}
+
+// Matrix entries of the value computed for the pair (p, q), p <= q, of a tile:
+// plain (p,q) and its mirror; antipodal also the antipodes' pair
+// (northern block) or the mirrored-column pairs (p,a(q)) and (q,a(p)).
+__device__ __forceinline__ void store_value(float *__restrict__ G, int64_t npix, int64_t nside, bool ns, int64_t p,
+                                            int64_t q, float v, int32_t accumulate)
+{
+    if (nside == 0) {
+        store_pair(G, npix, p, q, v, accumulate);
+        return;
+    }
+    const int64_t ap = antipode_north(ring_of_north(p, nside), npix);
+    const int64_t aq = antipode_north(ring_of_north(q, nside), npix);
+    if (!ns) {
+        store_pair(G, npix, p, q, v, accumulate);
+        store_pair(G, npix, ap, aq, v, accumulate);
+    } else {
+        store_pair(G, npix, p, aq, v, accumulate);
+        if (p != q) store_pair(G, npix, q, ap, v, accumulate);
+    }
+}
+
+// Seeds failed the antipodal spot check (any of the kSymParts flags set).
+__device__ __forceinline__ bool seeds_rejected(const double *__restrict__ flags)
+{
+    if (!flags) return false;
+    bool bad = false;
+    for (int i = 0; i < kSymParts; ++i) bad = bad || flags[i] != 0.0;
+    return bad;
+}
+
 __device__ __forceinline__ uint32_t abs_diff(uint32_t x, uint32_t y)
 {
     uint32_t d;
@@ -150,28 +199,33 @@ __device__ __forceinline__ uint32_t abs_diff(uint32_t x, uint32_t y)
 // evaluate the cubic, two more weight and accumulate it.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void fisher_full_kernel(const float *__restrict__ a, const float *__restrict__ gamma,
                                                           const uint32_t *__restrict__ U, int32_t nt, int32_t npix,
+                                                          int64_t nside, const double *__restrict__ flags,
                                                           const float4 *__restrict__ cub, int32_t fb, int32_t accumulate,
                                                           float *__restrict__ G)
 {
     __shared__ float gP[kFtSeg][kFt], gQ[kFtSeg][kFt];
     __shared__ uint32_t uP[kFtSeg][kFt], uQ[kFtSeg][kFt];
-    const int64_t nT = (npix + kFt - 1) / kFt;
+    const int64_t nrow = nside > 0 ? npix / 2 : npix;  // rows and columns of the computed blocks
+    const int64_t nT = (nrow + kFt - 1) / kFt;
     int64_t tr, tc;
-    tri_tile(blockIdx.x, nT, tr, tc);
+    bool ns;
+    fisher_tile(blockIdx.x, nT, nside > 0, tr, tc, ns);
     const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
     float acc[4][4] = {};
     const char *cb = reinterpret_cast<const char *>(cub);
-    for (int t0 = 0; t0 < nt; t0 += kFtSeg) {
+    const int ntu = seeds_rejected(flags) ? 0 : nt;
+    for (int t0 = 0; t0 < ntu; t0 += kFtSeg) {
         __syncthreads();
         for (int e = threadIdx.x; e < kFtSeg * kFt; e += 256) {
             const int tt = e / kFt, i = e % kFt, t = t0 + tt;
             const int64_t p = tr * kFt + i, q = tc * kFt + i;
             const bool ok = t < nt;
             const float at = ok ? a[t] : 0.0f;
-            gP[tt][i] = ok && p < npix ? at * gamma[(int64_t)t * npix + p] : 0.0f;
-            uP[tt][i] = ok && p < npix ? U[(int64_t)t * npix + p] : kDelayBias;
-            gQ[tt][i] = ok && q < npix ? gamma[(int64_t)t * npix + q] : 0.0f;
-            uQ[tt][i] = ok && q < npix ? U[(int64_t)t * npix + q] : kDelayBias;
+            gP[tt][i] = ok && p < nrow ? at * gamma[(int64_t)t * npix + p] : 0.0f;
+            uP[tt][i] = ok && p < nrow ? U[(int64_t)t * npix + p] : kDelayBias;
+            gQ[tt][i] = ok && q < nrow ? gamma[(int64_t)t * npix + q] : 0.0f;
+            const uint32_t uq = ok && q < nrow ? U[(int64_t)t * npix + q] : kDelayBias;
+            uQ[tt][i] = ns ? kDelayMirror - uq : uq;
         }
         __syncthreads();
         const int tn = min(kFtSeg, nt - t0);
@@ -206,13 +260,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
                 }
         }
     }
+    if (ntu != nt) {  // rejected seeds: the matrix is NaN
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) acc[i][jj] = __builtin_nanf("");
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
             const int64_t p = tr * kFt + ty * 4 + i, q = tc * kFt + tx * 4 + jj;
             // a diagonal tile writes its upper triangle and the mirror of it
-            if (p < npix && q < npix && (tr != tc || p <= q)) store_pair(G, npix, p, q, acc[i][jj], accumulate);
+            if (p < nrow && q < nrow && (tr != tc || p <= q))
+                store_value(G, npix, nside, ns, p, q, acc[i][jj], accumulate);
         }
 }
 
@@ -226,7 +287,9 @@ constexpr int kLdsTable = 10240;
 __global__ __launch_bounds__(512) void fisher_full_lds_kernel(const float *__restrict__ a,
                                                                const float *__restrict__ gamma,
                                                                const uint32_t *__restrict__ U, int32_t nt,
-                                                               int32_t npix, const float4 *__restrict__ cub,
+                                                               int32_t npix, int64_t nside,
+                                                               const double *__restrict__ flags,
+                                                               const float4 *__restrict__ cub,
                                                                int32_t J, int32_t fb, int64_t ntiles,
                                                                int32_t accumulate, float *__restrict__ G)
 {
@@ -236,19 +299,26 @@ __global__ __launch_bounds__(512) void fisher_full_lds_kernel(const float *__res
     const char *tb = reinterpret_cast<const char *>(tab);
     const int half = threadIdx.x >> 8, lt = threadIdx.x & 255;
     const int ty = lt / 16, tx = lt % 16;
-    const int64_t nT = (npix + kFt - 1) / kFt;
+    const int64_t nrow = nside > 0 ? npix / 2 : npix;  // rows and columns of the computed blocks
+    const int32_t last = (int32_t)nrow - 1;
+    const int64_t nT = (nrow + kFt - 1) / kFt;
+    const int ntu = seeds_rejected(flags) ? 0 : nt;
     for (int64_t k = (int64_t)blockIdx.x * 2 + half; k < ntiles; k += (int64_t)gridDim.x * 2) {
         int64_t tr, tc;
-        tri_tile(k, nT, tr, tc);
+        bool ns;
+        fisher_tile(k, nT, nside > 0, tr, tc, ns);
+        // the mirrored columns of the northern x southern block: U(a(q)) = kDelayMirror - U(q)
+        const uint32_t qm = ns ? kDelayMirror : 0u, qs = ns ? 0u : 1u;
+        auto ucol = [qm, qs](uint32_t u) { return qs ? u : qm - u; };
         int32_t pi[4], qi[4];
         bool pv[4], qv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int64_t p = tr * kFt + ty * 4 + i, q = tc * kFt + tx * 4 + i;
-            pv[i] = p < npix;
-            qv[i] = q < npix;
-            pi[i] = (int32_t)(pv[i] ? p : npix - 1);
-            qi[i] = (int32_t)(qv[i] ? q : npix - 1);
+            pv[i] = p < nrow;
+            qv[i] = q < nrow;
+            pi[i] = (int32_t)(pv[i] ? p : last);
+            qi[i] = (int32_t)(qv[i] ? q : last);
         }
         float acc[4][4] = {};
         float gp[4], gq[4];
@@ -258,9 +328,9 @@ __global__ __launch_bounds__(512) void fisher_full_lds_kernel(const float *__res
             gp[i] = pv[i] ? a[0] * gamma[pi[i]] : 0.0f;
             up[i] = U[pi[i]];
             gq[i] = qv[i] ? gamma[qi[i]] : 0.0f;
-            uq[i] = U[qi[i]];
+            uq[i] = ucol(U[qi[i]]);
         }
-        for (int t = 0; t < nt; ++t) {
+        for (int t = 0; t < ntu; ++t) {
             // next segment's inputs (the last iteration re-reads segment nt - 1)
             const int tn = min(t + 1, nt - 1);
             const int64_t o = (int64_t)tn * npix;
@@ -297,15 +367,22 @@ __global__ __launch_bounds__(512) void fisher_full_lds_kernel(const float *__res
                 gp[i] = pv[i] ? an * gpn[i] : 0.0f;
                 up[i] = upn[i];
                 gq[i] = qv[i] ? gqn[i] : 0.0f;
-                uq[i] = uqn[i];
+                uq[i] = ucol(uqn[i]);
             }
+        }
+        if (ntu != nt) {  // rejected seeds: the matrix is NaN
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) acc[i][jj] = __builtin_nanf("");
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
                 const int64_t p = tr * kFt + ty * 4 + i, q = tc * kFt + tx * 4 + jj;
-                if (pv[i] && q < npix && (tr != tc || p <= q)) store_pair(G, npix, p, q, acc[i][jj], accumulate);
+                if (pv[i] && q < nrow && (tr != tc || p <= q))
+                    store_value(G, npix, nside, ns, p, q, acc[i][jj], accumulate);
             }
     }
 }
@@ -336,12 +413,12 @@ size_t fisher_full_workspace_bytes(double f_max, int32_t nbins, int32_t nt, int3
     fisher_table_geometry(f_max, &delta, &J, &fb);
     const size_t nchunk = ((size_t)nbins + kTabChunk - 1) / kTabChunk;
     return up256(nchunk * (J + 1) * sizeof(double2)) + up256((size_t)J * sizeof(float4)) +
-           up256((size_t)nt * npix * sizeof(uint32_t));
+           up256((size_t)nt * npix * sizeof(uint32_t)) + up256(kSymParts * sizeof(double));
 }
 
 hipError_t launch_fisher_full(const float *a, const float *b, int32_t rank, const float *H, int32_t nf, int32_t clo,
                               int32_t chi, double f0, double df, int64_t k0, const float *gamma, const double *tau,
-                              int32_t nt, int32_t npix, float *G, void *work, hipStream_t s)
+                              int32_t nt, int32_t npix, int64_t nside, float *G, void *work, hipStream_t s)
 {
     const double f_max = f0 + (double)(k0 + chi - 1) * df;
     double delta;
@@ -356,10 +433,19 @@ hipError_t launch_fisher_full(const float *a, const float *b, int32_t rank, cons
     float4 *cub = reinterpret_cast<float4 *>(w);
     w += up256((size_t)J * sizeof(float4));
     uint32_t *U = reinterpret_cast<uint32_t *>(w);
+    w += up256((size_t)nt * npix * sizeof(uint32_t));
+    double *flags = nullptr;
+    if (nside > 0) {
+        flags = reinterpret_cast<double *>(w);
+        const hipError_t e = launch_antipodal_check(gamma, tau, nt, npix, nside, flags, s);
+        if (e != hipSuccess) return e;
+    }
     const int64_t n = (int64_t)nt * npix;
     hipLaunchKernelGGL(fixed_delay_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tau, n,
                        std::ldexp(1.0, fb) / delta, U);
-    const int64_t nT = (npix + kFt - 1) / kFt, ntiles = nT * (nT + 1) / 2;
+    // antipodal: the two triangles of the northern blocks; otherwise the whole upper triangle
+    const int64_t nrow = nside > 0 ? npix / 2 : npix;
+    const int64_t nT = (nrow + kFt - 1) / kFt, ntiles = (nside > 0 ? 2 : 1) * (nT * (nT + 1) / 2);
     if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
     const bool lds = J <= kLdsTable && fisher_full_table_in_lds();
     int cus = 256;
@@ -380,10 +466,10 @@ hipError_t launch_fisher_full(const float *a, const float *b, int32_t rank, cons
         if (lds) {
             const int64_t grid = std::min<int64_t>(cus, (ntiles + 1) / 2);
             hipLaunchKernelGGL(fisher_full_lds_kernel, dim3((unsigned)grid), dim3(512), 0, s, ar, gamma, U, nt, npix,
-                               cub, J, fb, ntiles, (int32_t)(r > 0), G);
+                               nside, flags, cub, J, fb, ntiles, (int32_t)(r > 0), G);
         } else {
             hipLaunchKernelGGL(fisher_full_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, ar, gamma, U, nt, npix,
-                               cub, fb, (int32_t)(r > 0), G);
+                               nside, flags, cub, fb, (int32_t)(r > 0), G);
         }
     }
     return hipGetLastError();

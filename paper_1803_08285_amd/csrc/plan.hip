@@ -7,7 +7,9 @@
 // wave-tile shape and grid of the beam launch) with the autotuner (cache in tune.hip)
 // (timed on the device, cached on disk), and captures the graph.
 // plan_launch replays the graph on the caller's stream: no allocation, no host
-// synchronisation.  Every tunable changes only the schedule, never an output's
+// synchronisation.  The tuner also decides whether the beams run on a branch of
+// their own beside the dirty maps (two graph branches, joined before the
+// broadband sums) or after them on the one stream.  Every tunable changes only the schedule, never an output's
 // summation order, so all choices give bitwise identical maps.
 #include <math.h>
 #include <stdio.h>
@@ -52,6 +54,8 @@ struct sgwb_plan {
     int num_cus = 0;
     int device = 0;
     hipStream_t cap = nullptr;
+    hipStream_t side = nullptr;  // second branch (beams) of the branched schedule
+    hipEvent_t fork = nullptr, join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -186,6 +190,24 @@ static hipError_t enqueue(sgwb_plan *p, hipStream_t s, int parts)
     return hipGetLastError();
 }
 
+// The whole plan.  Branched schedule: the beams go on a second stream forked
+// from s (an event) and joined back before the broadband sums, so they can
+// run beside the dirty maps; under capture the fork becomes two graph branches.
+static hipError_t enqueue_all(sgwb_plan *p, hipStream_t s, int parts)
+{
+    const bool branch = p->tun.branches && (parts & 3) == 3 && !p->bjobs.empty() &&
+                        (p->xm_tiles > 0 || p->x_tiles > 0);
+    if (!branch) return enqueue(p, s, parts);
+    hipError_t e = hipEventRecord(p->fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork, 0);
+    if (e == hipSuccess) e = enqueue(p, p->side, 2);
+    if (e == hipSuccess) e = hipEventRecord(p->join, p->side);
+    if (e == hipSuccess) e = enqueue(p, s, 1);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join, 0);
+    if (e == hipSuccess && (parts & 4)) e = enqueue(p, s, 4);
+    return e;
+}
+
 double time_parts(sgwb_plan *p, hipStream_t s, int parts, int reps)
 {
     hipEvent_t a, b;
@@ -194,7 +216,7 @@ double time_parts(sgwb_plan *p, hipStream_t s, int parts, int reps)
     double best = 1e30;
     for (int r = 0; r < reps; ++r) {
         (void)hipEventRecord(a, s);
-        if (enqueue(p, s, parts) != hipSuccess) {
+        if (enqueue_all(p, s, parts) != hipSuccess) {
             best = -1.0;
             break;
         }
@@ -307,6 +329,24 @@ int autotune_plan(sgwb_plan *p, bool tune)
             }
         best = bb;
     }
+    if (!p->bjobs.empty() && (p->xm_tiles > 0 || p->x_tiles > 0)) {
+        // the whole plan, sequential or with the beams on a branch of their own
+        best_ms = 1e30;
+        int pick = 0;
+        for (int br : {0, 1}) {
+            Tunables c = best;
+            c.branches = br;
+            if ((rc = plan_set_tunables(p, c))) return rc;
+            const double ms = time_parts(p, s, 7, 2);
+            if (ms < 0) return check_hip(hipGetLastError(), "autotune: whole plan");
+            p->tune_ms.push_back(ms);
+            if (ms < best_ms) {
+                best_ms = ms;
+                pick = br;
+            }
+        }
+        best.branches = pick;
+    }
     p->tuned = true;
     tune_cache_store(p->tune_key, best);
     return plan_set_tunables(p, best);
@@ -320,6 +360,9 @@ static void plan_free(sgwb_plan *p)
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->side) (void)hipStreamDestroy(p->side);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->join) (void)hipEventDestroy(p->join);
     if (p->d_xjobs) (void)hipFree(p->d_xjobs);
     if (p->d_xmjobs) (void)hipFree(p->d_xmjobs);
     if (p->xm_ws) (void)hipFree(p->xm_ws);
@@ -423,6 +466,9 @@ int sgwb_plan_create(const sgwb_job *jobs, int32_t njobs, uint32_t flags, sgwb_p
     if (e == hipSuccess && !p->xmjobs.empty()) e = hipMalloc(&p->d_xmjobs, p->xmjobs.size() * sizeof(XmJob));
     if (e == hipSuccess && !p->bjobs.empty()) e = hipMalloc(&p->d_bjobs, p->bjobs.size() * sizeof(BJob));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming);
     if (e != hipSuccess) {
         rc = set_error(SGWB_EDEVICE, "plan_create: %s", hipGetErrorString(e));
         plan_free(p);
@@ -439,7 +485,7 @@ int sgwb_plan_create(const sgwb_job *jobs, int32_t njobs, uint32_t flags, sgwb_p
     if (!(flags & SGWB_PLAN_NO_GRAPH)) {
         e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t qe = enqueue(p, p->cap, 7);
+            hipError_t qe = enqueue_all(p, p->cap, 7);
             e = hipStreamEndCapture(p->cap, &p->graph);
             if (qe != hipSuccess) e = qe;
         }
@@ -458,7 +504,7 @@ int sgwb_plan_launch(sgwb_plan *p, hipStream_t stream)
 {
     if (!p) return set_error(SGWB_EINVAL, "plan_launch: null plan");
     if (p->exec) return check_hip(hipGraphLaunch(p->exec, stream), "plan_launch: hipGraphLaunch");
-    return check_hip(enqueue(p, stream, 7), "plan_launch: enqueue");
+    return check_hip(enqueue_all(p, stream, 7), "plan_launch: enqueue");
 }
 
 void sgwb_plan_destroy(sgwb_plan *p) { plan_free(p); }
@@ -474,11 +520,12 @@ int sgwb_plan_describe(const sgwb_plan *p, char *buf, size_t len)
     }
     int n = snprintf(buf, len,
                      "{\"jobs\": %zu, \"x_tiles\": %lld, \"xm_tiles\": %lld, \"beam_workgroups\": %lld, \"x_strip_major\": %d, "
-                     "\"x_grid_per_cu\": %d, \"xm_per_job\": %d, \"beam_shape\": \"%s\", \"beam_grid_per_cu\": %d, \"tuned\": %s, "
+                     "\"x_grid_per_cu\": %d, \"xm_per_job\": %d, \"beam_shape\": \"%s\", \"beam_grid_per_cu\": %d, "
+                     "\"branches\": %d, \"tuned\": %s, "
                      "\"from_cache\": %s, \"tune_ms\": [%s], \"graph\": %s, \"key\": \"%s\"}",
                      p->jobs.size(), (long long)p->x_tiles, (long long)p->xm_tiles, (long long)p->b_wgs, p->tun.x_strip_major,
                      p->tun.x_grid_per_cu, p->tun.xm_per_job, p->tun.beam_shape == kBeamShape2x4 ? "2x4" : "4x4",
-                     p->tun.beam_grid_per_cu,
+                     p->tun.beam_grid_per_cu, p->tun.branches,
                      p->tuned ? "true" : "false", p->from_cache ? "true" : "false", ms.c_str(),
                      p->exec ? "true" : "false", p->tune_key.c_str());
     if (n < 0 || (size_t)n >= len) return set_error(SGWB_ENOMEM, "plan_describe: buffer too small");

@@ -8,6 +8,7 @@
 #include <string>
 
 #include "sgwb.h"
+#include "tune_cache.h"
 
 namespace sgwb {
 
@@ -160,9 +161,10 @@ hipError_t launch_band_gamma(const float *w, int64_t ldw, int32_t nt, const floa
 // full Fisher matrix of a band for separable weights, and its CG clean map
 size_t fisher_full_workspace_bytes(double f_max, int32_t nbins, int32_t nt, int32_t npix);
 bool fisher_full_band_ok(double f_max);
+// nside > 0: antipodal seeds (only the northern rows and their antipodes are computed)
 hipError_t launch_fisher_full(const float *a, const float *b, int32_t rank, const float *H, int32_t nf, int32_t clo,
                               int32_t chi, double f0, double df, int64_t k0, const float *gamma, const double *tau,
-                              int32_t nt, int32_t npix, float *G, void *work, hipStream_t s);
+                              int32_t nt, int32_t npix, int64_t nside, float *G, void *work, hipStream_t s);
 size_t cg_workspace_bytes(int32_t n);
 hipError_t launch_clean_map_cg(const float *G, const float *X, int32_t n, int32_t niter, float *P, void *work,
                                hipStream_t s);
@@ -189,6 +191,12 @@ constexpr double kXmEtaMax = 0.29;
 // seeds fail the antipodal spot check or exceed the call's delay bound (the
 // map is then written as NaN).
 constexpr int kXFormRejected = -1;
+// Spot check of the exact antipodal symmetry of seeds (first, middle and last
+// segment, every northern pixel): flags[kSymParts] of 0.0 (pass) or 1.0, one per
+// workgroup, no atomics.
+constexpr int kSymParts = 64;
+hipError_t launch_antipodal_check(const float *gamma, const double *tau, int32_t nt, int64_t npix, int64_t nside,
+                                  double *flags, hipStream_t s);
 bool xm_eligible(const MapArgs &a);
 size_t xm_workspace_bytes(int64_t k0, int32_t nt, int32_t nf, int32_t npix);
 // form_rec (optional out): device address of the call's form record
@@ -252,9 +260,8 @@ __host__ __device__ inline FragDims frag_dims(int64_t n, int64_t nt)
 {
     return FragDims{(n + kBlk - 1) / kBlk, (nt + kKs - 1) / kKs};
 }
-// wave-tile shapes of the beam GEMM (blocks of 32 x 32 outputs per wave)
-constexpr int kBeamShape4x4 = 0;
-constexpr int kBeamShape2x4 = 1;
+// wave-tile shapes of the beam GEMM (blocks of 32 x 32 outputs per wave):
+// kBeamShape4x4, kBeamShape2x4 (tune_cache.h)
 struct BJob {
     const uint4 *Wf, *Gf;  // fragment arrays in the job's workspace
     FragDims fm, fn;
@@ -285,13 +292,7 @@ hipError_t launch_band(const T *X, const T *G, const T *H, int32_t nf, int32_t n
 // ---------------------------------------------------------------------------
 // Batched plans and their autotuner
 // ---------------------------------------------------------------------------
-struct Tunables {
-    int x_strip_major = 1;    // dirty-map tiles: column tiles fastest within a strip
-    int x_grid_per_cu = 2;    // persistent dirty-map workgroups per compute unit
-    int beam_shape = kBeamShape2x4;
-    int beam_grid_per_cu = 4; // persistent beam workgroups per compute unit (0: one per tile group)
-    int xm_per_job = 0;       // matrix-core dirty maps: one launch per job instead of one for all
-};
+// struct Tunables: tune_cache.h
 bool tune_cache_load(const std::string &key, Tunables *t);
 void tune_cache_store(const std::string &key, const Tunables &t);
 std::string device_key();

@@ -33,26 +33,14 @@ static std::string cache_path()
 
 static std::map<std::string, Tunables> read_cache(const std::string &path)
 {
-    std::map<std::string, Tunables> m;
+    std::string text;
     FILE *f = path.empty() ? nullptr : fopen(path.c_str(), "r");
-    if (!f) return m;
-    char line[4096];
-    while (fgets(line, sizeof line, f)) {
-        char *q1 = strchr(line, '"');
-        if (!q1) continue;
-        char *q2 = strchr(q1 + 1, '"');
-        if (!q2) continue;
-        std::string key(q1 + 1, q2);
-        Tunables t;
-        // entries without every field (an older format) are left out: a miss retunes
-        if (sscanf(q2 + 1,
-                   ": {\"x_strip_major\": %d, \"x_grid_per_cu\": %d, \"beam_shape\": %d, \"beam_grid_per_cu\": %d, "
-                   "\"xm_per_job\": %d}",
-                   &t.x_strip_major, &t.x_grid_per_cu, &t.beam_shape, &t.beam_grid_per_cu, &t.xm_per_job) == 5)
-            m[key] = t;
-    }
+    if (!f) return {};
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
     fclose(f);
-    return m;
+    return parse_cache_text(text);
 }
 
 static void write_cache(const std::string &path, const std::map<std::string, Tunables> &m)
@@ -61,18 +49,12 @@ static void write_cache(const std::string &path, const std::map<std::string, Tun
     const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
     FILE *f = fopen(tmp.c_str(), "w");
     if (!f) return;
-    fprintf(f, "{\n");
-    size_t i = 0;
-    for (const auto &kv : m) {
-        fprintf(f,
-                "\"%s\": {\"x_strip_major\": %d, \"x_grid_per_cu\": %d, \"beam_shape\": %d, \"beam_grid_per_cu\": %d, "
-                "\"xm_per_job\": %d}%s\n",
-                kv.first.c_str(), kv.second.x_strip_major, kv.second.x_grid_per_cu, kv.second.beam_shape,
-                kv.second.beam_grid_per_cu, kv.second.xm_per_job, ++i < m.size() ? "," : "");
-    }
-    fprintf(f, "}\n");
-    fclose(f);
-    rename(tmp.c_str(), path.c_str());
+    const std::string text = format_cache_text(m);
+    const bool ok = fwrite(text.data(), 1, text.size(), f) == text.size();
+    if (fclose(f) == 0 && ok)
+        rename(tmp.c_str(), path.c_str());
+    else
+        unlink(tmp.c_str());
 }
 
 bool tune_cache_load(const std::string &key, Tunables *t)

@@ -130,22 +130,22 @@ def test_fisher_full_and_clean_map_validation_on_the_host():
     d = ctypes.c_void_p(256)
     big = 1 << 30
     # band outside the columns
-    rc = L.sgwb_fisher_full(d, d, 1, d, 10, ctypes.byref(fg), 0, 4, 11, d, d, 8, 768, d, d, big, None)
+    rc = L.sgwb_fisher_full(d, d, 1, d, 10, ctypes.byref(fg), 0, 4, 11, d, d, 8, 768, 0, d, d, big, None)
     assert rc == -1 and b"band" in L.sgwb_last_error()
-    rc = L.sgwb_fisher_full(d, d, 1, d, 10, ctypes.byref(fg), 0, 5, 5, d, d, 8, 768, d, d, big, None)
+    rc = L.sgwb_fisher_full(d, d, 1, d, 10, ctypes.byref(fg), 0, 5, 5, d, d, 8, 768, 0, d, d, big, None)
     assert rc == -1
     for rank in (0, 65):
-        rc = L.sgwb_fisher_full(d, d, rank, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, d, d, big, None)
+        rc = L.sgwb_fisher_full(d, d, rank, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, 0, d, d, big, None)
         assert rc == -1 and b"rank" in L.sgwb_last_error()
     # null output
-    rc = L.sgwb_fisher_full(d, d, 1, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, None, d, big, None)
+    rc = L.sgwb_fisher_full(d, d, 1, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, 0, None, d, big, None)
     assert rc == -1
     # misaligned tau (float64)
-    rc = L.sgwb_fisher_full(d, d, 1, d, 10, ctypes.byref(fg), 0, 0, 10, d, ctypes.c_void_p(260), 8, 768, d, d, big,
+    rc = L.sgwb_fisher_full(d, d, 1, d, 10, ctypes.byref(fg), 0, 0, 10, d, ctypes.c_void_p(260), 8, 768, 0, d, d, big,
                             None)
     assert rc == -1 and b"misaligned" in L.sgwb_last_error()
     # workspace too small; the table grows with the top frequency of the band
-    rc = L.sgwb_fisher_full(d, d, 1, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, d, d, 256, None)
+    rc = L.sgwb_fisher_full(d, d, 1, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, 0, d, d, 256, None)
     assert rc == -2
     low = L.sgwb_fisher_full_workspace_size(ctypes.byref(fg), 0, 10, 8, 768)
     high = L.sgwb_fisher_full_workspace_size(ctypes.byref(fg), 50000, 10, 8, 768)
@@ -155,7 +155,7 @@ def test_fisher_full_and_clean_map_validation_on_the_host():
     assert L.sgwb_fisher_full_workspace_size(ctypes.byref(bad), 0, 10, 8, 768) == 0
     # the fixed-point delays cover bands up to 24 kHz
     assert L.sgwb_fisher_full_workspace_size(ctypes.byref(fg), 32 * 30000, 10, 8, 768) == 0
-    rc = L.sgwb_fisher_full(d, d, 1, d, 10, ctypes.byref(fg), 32 * 30000, 0, 10, d, d, 8, 768, d, d, big, None)
+    rc = L.sgwb_fisher_full(d, d, 1, d, 10, ctypes.byref(fg), 32 * 30000, 0, 10, d, d, 8, 768, 0, d, d, big, None)
     assert rc == -1 and b"24 kHz" in L.sgwb_last_error()
     # clean map
     rc = L.sgwb_clean_map_cg(d, d, 0, 5, d, d, big, None)

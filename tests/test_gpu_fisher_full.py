@@ -203,3 +203,58 @@ def test_fisher_full_rank_r_weights_vs_oracle(sg, oracle_mod, rank, nside, k0, n
     S = sum(_scale(a[r], b[r], H, klo, khi, gh[:, sel]) for r in range(rank))
     assert np.max(np.abs(Gg[np.ix_(sel, sel)] - Go) / S) <= 1e-5
     assert np.array_equal(Gg, Gg.T)
+
+
+ANTI_CASES = [  # baseline, nside, nt, k0, nf, band, df, rank
+    ("AB", 2, 24, 10, 40, (0, 40), 0.25, 1),          # one ragged tile per block (24 northern pixels)
+    ("AC", 4, 40, 100, 64, (5, 60), 0.25, 1),         # 2 x 2 tiles per block, sub-band
+    ("AB", 8, 60, 53000, 64, (0, 64), 1 / 32, 1),     # 1.68 kHz, 6 x 6 tiles per block
+    ("BC", 2, 20, 39000, 50, (3, 47), 0.125, 1),      # 4.9 kHz: global-memory table
+    ("AC", 4, 40, 100, 64, (2, 61), 0.25, 3),         # three ranks: the later passes add
+]
+
+
+@pytest.mark.parametrize("case", ANTI_CASES, ids=[f"{c[0]}-{c[1]}-{c[3]}-r{c[7]}" for c in ANTI_CASES])
+def test_fisher_full_antipodal_vs_oracle_and_plain(sg, oracle_mod, case):
+    """Antipodal seeds: only the northern blocks' triangles are computed.  Against
+    the oracle at the usual bound, against the flag-free matrix within float32
+    rounding of the weight products (1e-6 of S), exactly symmetric, and with the
+    block structure G(a(p),a(q)) = G(p,q), G(p,a(q)) = G(q,a(p)) bit for bit."""
+    bl, nside, nt, k0, nf, (klo, khi), df, rank = case
+    g, t, _, _, H = _inputs(sg, bl, nside, None, nt, k0, nf, df, 31)
+    rng = np.random.default_rng(32)
+    f = freqs(F0, df, k0, nf)
+    a = rng.uniform(0.2, 1.0, (rank, nt)).astype(np.float32)
+    b = np.stack([(synth.spectrum_H(f) / synth.noise_psd(f) ** 2) * rng.uniform(0.5, 1.5, nf)
+                  for _ in range(rank)]).astype(np.float32)
+    ad, bd, Hd = (torch.from_numpy(x).cuda() for x in (a, b, H))
+    Ga = sg.fisher_full(ad, bd, Hd, sg.FGrid(F0, df), k0, klo, khi, g, t, antipodal=True)
+    Gp = sg.fisher_full(ad, bd, Hd, sg.FGrid(F0, df), k0, klo, khi, g, t, antipodal=False)
+    _, anti = sg.healpix_centres(nside)
+    torch.cuda.synchronize()
+    A = Ga.cpu().numpy().astype(np.float64)
+    P = Gp.cpu().numpy().astype(np.float64)
+    gh, th = g.cpu().numpy().astype(np.float64), t.cpu().numpy()
+    npix = gh.shape[1]
+    S_all = sum(_scale(a[r], b[r], H, klo, khi, gh) for r in range(rank))
+    assert np.array_equal(A, A.T)
+    am = anti.cpu().numpy().astype(np.int64)
+    assert np.array_equal(A[np.ix_(am, am)], A)  # G(a(p), a(q)) = G(p, q)
+    assert np.max(np.abs(A - P) / S_all) <= 1e-6
+    sel = np.arange(npix) if npix <= 200 else np.sort(np.random.default_rng(6).choice(npix, 48, replace=False))
+    w = sum(np.outer(a[r].astype(np.float64), b[r].astype(np.float64)) for r in range(rank))
+    Go = oracle_mod.fisher_full(w, H.astype(np.float64), F0, df, k0, klo, khi, gh[:, sel], th[:, sel])
+    assert np.max(np.abs(A[np.ix_(sel, sel)] - Go) / S_all[np.ix_(sel, sel)]) <= 1e-5
+
+
+def test_fisher_full_antipodal_rejects_broken_seeds(sg):
+    """A delay changed at one pixel of the middle segment breaks the antipodal
+    promise: the device check rejects the seeds and the matrix is NaN."""
+    nt, nside, k0, nf, df = 20, 4, 100, 32, 0.25
+    g, t, a, b, H = _inputs(sg, "AB", nside, None, nt, k0, nf, df, 33)
+    t = t.clone()
+    t[nt // 2, 3] += 1e-7
+    ad, bd, Hd = (torch.from_numpy(x).cuda() for x in (a, b, H))
+    G = sg.fisher_full(ad, bd, Hd, sg.FGrid(F0, df), k0, 0, nf, g, t, antipodal=True)
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(G).all())

@@ -111,13 +111,16 @@ def test_plan_every_schedule_gives_the_same_maps(sg, tmp_path, monkeypatch):
         plan.close()
 
 
-@pytest.mark.parametrize("xm_per_job,beam_shape,beam_grid", [(1, 1, 0), (0, 1, 0), (1, 0, 2), (0, 0, 8)])
-def test_plan_forced_schedules_give_the_same_maps(sg, tmp_path, monkeypatch, xm_per_job, beam_shape, beam_grid):
+@pytest.mark.parametrize("xm_per_job,beam_shape,beam_grid,branches",
+                         [(1, 1, 0, 0), (0, 1, 0, 1), (1, 0, 2, 1), (0, 0, 8, 0)])
+def test_plan_forced_schedules_give_the_same_maps(sg, tmp_path, monkeypatch, xm_per_job, beam_shape, beam_grid,
+                                                  branches):
     """Each schedule candidate, forced through the tuning cache: identical bits.
 
     beam_shape 1 is the 2x4 wave tile, 0 the 4x4; beam_grid 0 is one workgroup per
     tile group (no persistent loop); xm_per_job 1 launches the single-call
-    dirty-map kernel once per job instead of the multi-job kernel."""
+    dirty-map kernel once per job instead of the multi-job kernel; branches 1
+    puts the beams on a second graph branch beside the dirty maps."""
     cache = tmp_path / "tune.json"
     monkeypatch.setenv("SGWB_TUNE_CACHE", str(cache))
     jobs, refs, _ = _make_jobs(sg)
@@ -125,10 +128,12 @@ def test_plan_forced_schedules_give_the_same_maps(sg, tmp_path, monkeypatch, xm_
     key = p0.describe()["key"]
     p0.close()
     cache.write_text(json.dumps({key: {"x_strip_major": 0, "x_grid_per_cu": 4, "beam_shape": beam_shape,
-                                       "beam_grid_per_cu": beam_grid, "xm_per_job": xm_per_job}}))
+                                       "beam_grid_per_cu": beam_grid, "xm_per_job": xm_per_job,
+                                       "branches": branches}}))
     plan = sg.Plan(jobs, autotune=True)
     d = plan.describe()
     assert d["from_cache"] and d["xm_per_job"] == xm_per_job and d["beam_grid_per_cu"] == beam_grid
+    assert d["branches"] == branches
     assert d["beam_shape"] == ("2x4" if beam_shape == 1 else "4x4")
     for j in jobs:
         for t in (j.X, j.G, j.Xbb, j.Gbb):
