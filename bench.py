@@ -192,9 +192,11 @@ def result_errors(sg, torch, inp, wl, X, G, Xbb, Gbb):
     return out
 
 
-def bench_batched(args, torch, sg):
-    """Batched form: three baselines with uneven jobs in one plan (graph replay)
-    against the plain path (one make_maps_band call per job)."""
+def batched_measure(torch, sg, steps):
+    """Batched form (three baselines with uneven jobs: AB nside 64 full band, AC
+    nside 32 20-500 Hz, BC nside 16 100-300 Hz) as one autotuned plan replayed
+    from a HIP graph, against the plain path (one make_maps_band call per job),
+    same box, same inputs; the outputs of the two are compared bit for bit."""
     dev = torch.device("cuda:0")
     jobs, terms = [], 0
     for wl in synth.batched_jobs():
@@ -239,18 +241,35 @@ def bench_batched(args, torch, sg):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / k
 
-    ms_plan = timed(plan.launch, args.steps)
+    ms_plan = timed(plan.launch, steps)
     log(f"plan: {ms_plan:.2f} ms per launch")
-    ms_plain = timed(plain, args.steps)
+    ms_plain = timed(plain, steps)
     log(f"plain path: {ms_plain:.2f} ms per pass")
+    # the plain path's outputs (last) against one more plan replay
+    ref = [[t.clone() for t in (j.X, j.G, j.Xbb, j.Gbb)] for j in jobs]
+    plan.launch()
+    torch.cuda.synchronize()
+    equal = all(torch.equal(t, r) for j, rr in zip(jobs, ref) for t, r in zip((j.X, j.G, j.Xbb, j.Gbb), rr))
+    out = {"workload": "batched_AB64_AC32_BC16", "terms_per_step": terms, "jobs": len(jobs),
+           "plan": {"value": terms / (ms_plan * 1e-3), "ms_per_step": ms_plan},
+           "plain_path": {"value": terms / (ms_plain * 1e-3), "ms_per_step": ms_plain},
+           "outputs_bitwise_equal": bool(equal), "schedule": plan.describe()}
+    plan.close()
+    del jobs, ws, ref
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_batched(args, torch, sg):
+    """Batched form alone (see batched_measure)."""
+    r = batched_measure(torch, sg, args.steps)
     out = {
-        "metric": "map terms/s (t*f*pix) for X+Gamma", "value": terms / (ms_plan * 1e-3), "unit": "terms/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": ms_plan, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_LABEL, "data": "synthetic",
-        "config": {"workload": "batched_AB64_AC32_BC16", "terms_per_step": terms, "jobs": len(jobs),
+        "metric": "map terms/s (t*f*pix) for X+Gamma", "value": r["plan"]["value"], "unit": "terms/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": r["plan"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_LABEL, "data": "synthetic",
+        "config": {"workload": r["workload"], "terms_per_step": r["terms_per_step"], "jobs": r["jobs"],
                    "parallelism": "single GPU"},
-        "plain_path": {"value": terms / (ms_plain * 1e-3), "ms_per_step": ms_plain},
-        "plan": plan.describe(),
+        "plain_path": r["plain_path"], "outputs_bitwise_equal": r["outputs_bitwise_equal"], "plan": r["schedule"],
     }
     print(json.dumps(out), flush=True)
 
@@ -567,6 +586,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="serving leg of the default run: Poisson queries at 200/s for this long (0: none)")
     ap.add_argument("--batched", action="store_true", help="batched plan of three uneven baseline jobs")
+    ap.add_argument("--no-batched-leg", action="store_true", help="leave the batched form out of the default run")
     ap.add_argument("--serve", action="store_true", help="Poisson query stream through the server (rate sweep)")
     ap.add_argument("--folded", action="store_true",
                     help="fold --days synthetic days, then X, overlap-corrected Gamma and band sums")
@@ -699,11 +719,16 @@ def main():
         log("timing the oracle on the host cores")
         cpu = cpu_baseline(inp, wl)
 
+    del X, G, ws
+    inp.pop("C_host"), inp.pop("w_host")
+    torch.cuda.empty_cache()
+    batched = None
+    if not args.no_batched_leg:
+        log("batched leg: three uneven jobs as one plan against one call per job")
+        batched = batched_measure(torch, sg, args.steps)
+
     serving = None
     if args.serve_seconds > 0:
-        del X, G, ws
-        inp.pop("C_host"), inp.pop("w_host")
-        torch.cuda.empty_cache()
         log(f"serving leg: 200 queries/s for {args.serve_seconds:.0f} s, server and plain path")
         serving = serving_sweep(args, torch, sg, [200.0], args.serve_seconds)[0]
 
@@ -729,6 +754,8 @@ def main():
         "errors_vs_oracle": errors,
         "cpu_baseline": cpu,
     }
+    if batched:
+        out["batched"] = batched
     if serving:
         out["latency_ms"] = {"p50": serving["server"]["p50_ms"], "p99": serving["server"]["p99_ms"],
                              "what": "served query latency, Poisson 200 queries/s"}
