@@ -323,9 +323,12 @@ FISHER_TABLE_BYTES_PER_TERM = 16          # one float4 cubic per (t, p, q) term
 
 
 def bench_fisher_full(args, torch, sg):
-    """Full Fisher matrix of the whole band (Eq. eq_fisher, separable weights) and
-    --cg-iters conjugate-gradient steps towards the clean map, for one folded day
-    of --workload; the dirty map comes from make_maps + reduce_band (untimed)."""
+    """Full Fisher matrix of the whole band (Eq. eq_fisher) and --cg-iters
+    conjugate-gradient steps towards the clean map, for one folded day of
+    --workload; the dirty map comes from make_maps + reduce_band (untimed).
+    --fisher-weights separable: w = a(t) b(f) (one delay table); general: the
+    non-stationary weights of synth.nonstationary_weights (full rank, one table
+    per segment, sgwb_fisher_full_general)."""
     dev = torch.device("cuda:0")
     wl = synth.workload(args.workload)
     tg, fgd = wl.tgrid, wl.fgrid
@@ -339,12 +342,26 @@ def bench_fisher_full(args, torch, sg):
     Xbb, _ = sg.reduce_band(X, Gk, inp["H"], 0, fgd.nf)
     del X, Gk
     G = torch.empty((npix, npix), dtype=torch.float32, device=dev)
-    ws = torch.empty(sg.fisher_full_workspace_bytes(fg, fgd.k0, fgd.nf, tg.nt, npix), dtype=torch.uint8, device=dev)
     P = torch.empty(npix, dtype=torch.float32, device=dev)
+    general = args.fisher_weights == "general"
+    if general:
+        del a, b
+        wg = torch.from_numpy(synth.nonstationary_weights(f, tg.nt, wl.nonstationary_seed or 1)
+                              .astype(np.float32)).to(dev)
+        ws = torch.empty(sg.fisher_full_general_workspace_bytes(fg, fgd.k0, 0, fgd.nf, tg.nt, npix,
+                                                                not args.fisher_plain),
+                         dtype=torch.uint8, device=dev)
 
-    def full():
-        sg.fisher_full(a, b, inp["H"], fg, fgd.k0, 0, fgd.nf, inp["gamma"], inp["tau"], out=G, workspace=ws,
-                       antipodal=not args.fisher_plain)
+        def full():
+            sg.fisher_full_general(wg, inp["H"], fg, fgd.k0, 0, fgd.nf, inp["gamma"], inp["tau"], out=G,
+                                   workspace=ws, antipodal=not args.fisher_plain)
+    else:
+        ws = torch.empty(sg.fisher_full_workspace_bytes(fg, fgd.k0, fgd.nf, tg.nt, npix), dtype=torch.uint8,
+                         device=dev)
+
+        def full():
+            sg.fisher_full(a, b, inp["H"], fg, fgd.k0, 0, fgd.nf, inp["gamma"], inp["tau"], out=G, workspace=ws,
+                           antipodal=not args.fisher_plain)
 
     def clean():
         sg.clean_map_cg(G, Xbb, args.cg_iters, out=P)
@@ -374,10 +391,12 @@ def bench_fisher_full(args, torch, sg):
     print(json.dumps({"metric": "full Fisher matrix pair-terms/s (t*p*q, q>=p)", "value": terms / (t_full * 1e-3),
                       "unit": "terms/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": t_full,
                       "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-                      "dtype": "f32 table lookups, f64 delay table",
+                      "dtype": "f32 table lookups, f64 delay table" + ("s (f64 MFMA)" if general else ""),
                       "data": "synthetic", "config": {"workload": wl.name + "_fisher_full", "nt": tg.nt,
                                                       "nf": fgd.nf, "npix": npix, "parallelism": "single GPU",
                                                       "antipodal_blocks": not args.fisher_plain,
+                                                      "weights": args.fisher_weights,
+                                                      "workspace_bytes": int(ws.numel()),
                                                       "table_lookups": lookups},
                       "roofline": {"bound": "lds", "achieved": tbps * 1e3, "peak": PEAK_LDS_TBPS * 1e3,
                                    "unit": "GB/s", "frac": tbps / PEAK_LDS_TBPS, "traffic": None},
@@ -596,6 +615,8 @@ def main():
     ap.add_argument("--fisher-full", action="store_true",
                     help="full Fisher matrix of the whole band and the CG clean map for --workload")
     ap.add_argument("--cg-iters", type=int, default=50)
+    ap.add_argument("--fisher-weights", choices=["separable", "general"], default="separable",
+                    help="full Fisher matrix weights: a(t) b(f), or general non-stationary w(t,f)")
     ap.add_argument("--fisher-plain", action="store_true",
                     help="full Fisher matrix without the antipodal block decomposition")
     ap.add_argument("--rates", type=float, nargs="+", default=[25.0, 50.0, 100.0, 200.0])

@@ -276,6 +276,43 @@ int sgwb_fisher_full(const float *a, const float *b, int32_t rank, const float *
                      const double *tau, int32_t nt, int32_t npix, uint32_t flags, float *G, void *workspace,
                      size_t workspace_bytes, hipStream_t stream);
 
+/* ---- full Fisher matrix for general weights: Eq. eq_fisher ------------------
+ * The same matrix as sgwb_fisher_full, for weights w(t,c) given whole (the
+ * folded w = H / P^2 of every segment and bin, of any rank):
+ *   G(p,q) = sum_{c in [clo,chi)} H(c) sum_t w(t,c) gamma(t,p) gamma(t,q)
+ *              cos 2 pi f_{k0+c} (tau(t,p) - tau(t,q))
+ *          = sum_t gamma(t,p) gamma(t,q) Wd_t(tau(t,p) - tau(t,q)),
+ *   Wd_t(D) = sum_{c in [clo,chi)} H(c) w(t,c) cos 2 pi f_{k0+c} D.
+ * Inputs (device): w float32 [nt][ldw] (ldw >= nf; column c = bin k0 + c, as
+ * the weights of sgwb_make_maps), H float32 [nf]; gamma float32, tau float64
+ * [nt][npix]; 0 <= clo < chi <= nf, 1 <= nt <= 65535.  flags: 0 or
+ * SGWB_MAPS_ANTIPODAL, as for sgwb_fisher_full (same spot check; seeds that
+ * fail give G = NaN).
+ * Output: G float32 [npix][npix] row-major, symmetric (overwritten).
+ * Arithmetic: one table Wd_t per segment on the grid of sgwb_fisher_full, its
+ * values and derivatives summed over the band's bins in float64 on the matrix
+ * cores (a product of the [nt][nbins] weights with cosines and sines generated
+ * in float64), then the same float32 cubic interpolants, fixed-point delays
+ * and float32 accumulation over t; same tolerance.  When the tables of several
+ * segments fit the 160 KiB of LDS together (bands up to 1.88 kHz) the matrix
+ * is built in passes over groups of segments, its running sums kept in the
+ * workspace between passes.
+ * Workspace: at least sgwb_fisher_full_general_workspace_size() bytes (0 for
+ * arguments out of range), 256-byte aligned, owned by the caller; it grows
+ * with nt x the table length (about 0.2 MB per segment for the full
+ * 20-1726 Hz band) and, for more than one pass, with the computed blocks
+ * (npix^2 float32, a quarter of that with SGWB_MAPS_ANTIPODAL).
+ * Errors: SGWB_EINVAL (null pointer, nt/nf/npix out of range, ldw < nf, band
+ * out of range or reaching above 24 kHz, bad grid, unknown flag bits or the
+ * antipodal flag with a non-HEALPix npix, misaligned pointer, more than
+ * 2^31 - 1 matrix tiles), SGWB_ENOMEM (workspace too small).                 */
+size_t sgwb_fisher_full_general_workspace_size(const sgwb_fgrid *fg /*host*/, int64_t k0, int32_t clo, int32_t chi,
+                                               int32_t nt, int32_t npix, uint32_t flags);
+int sgwb_fisher_full_general(const float *w, int64_t ldw, const float *H, int32_t nf,
+                             const sgwb_fgrid *fg /*host*/, int64_t k0, int32_t clo, int32_t chi,
+                             const float *gamma, const double *tau, int32_t nt, int32_t npix, uint32_t flags,
+                             float *G, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* ---- clean map: Eq. eq_ML_linear and its footnote ---------------------------
  * The maximum-likelihood map P solves G P = X; G is poorly conditioned, so the
  * clean map is the conjugate-gradient iterate after niter steps from P = 0

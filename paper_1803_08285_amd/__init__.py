@@ -97,6 +97,10 @@ _SIGNATURES = {
     "sgwb_fisher_full_workspace_size": ([ctypes.POINTER(_FGrid), _I64, _I32, _I32, _I32], ctypes.c_size_t),
     "sgwb_fisher_full": ([_VP, _VP, _I32, _VP, _I32, ctypes.POINTER(_FGrid), _I64, _I32, _I32, _VP, _VP, _I32, _I32,
                           ctypes.c_uint32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
+    "sgwb_fisher_full_general_workspace_size": ([ctypes.POINTER(_FGrid), _I64, _I32, _I32, _I32, _I32,
+                                                 ctypes.c_uint32], ctypes.c_size_t),
+    "sgwb_fisher_full_general": ([_VP, _I64, _VP, _I32, ctypes.POINTER(_FGrid), _I64, _I32, _I32, _VP, _VP, _I32,
+                                  _I32, ctypes.c_uint32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_clean_map_workspace_size": ([_I32], ctypes.c_size_t),
     "sgwb_clean_map_cg": ([_VP, _VP, _I32, _I32, _VP, _VP, ctypes.c_size_t, _VP], ctypes.c_int),
     "sgwb_make_maps_band_workspace_size": ([_I32, _I32, _I32, ctypes.c_uint32], ctypes.c_size_t),
@@ -541,6 +545,50 @@ def fisher_full(a: torch.Tensor, b: torch.Tensor, H: torch.Tensor, fgrid: FGrid,
                                     SGWB_MAPS_ANTIPODAL if antipodal else 0, _ptr(G), _ptr(workspace), wsz,
                                     _stream())
     _check(rc, "fisher_full")
+    return G
+
+
+def fisher_full_general_workspace_bytes(fgrid: FGrid, k0: int, klo: int, khi: int, nt: int, npix: int,
+                                       antipodal: bool = False) -> int:
+    fg = _FGrid(float(fgrid.f0), float(fgrid.df))
+    return int(lib().sgwb_fisher_full_general_workspace_size(ctypes.byref(fg), int(k0), int(klo), int(khi), int(nt),
+                                                             int(npix), SGWB_MAPS_ANTIPODAL if antipodal else 0))
+
+
+def fisher_full_general(w: torch.Tensor, H: torch.Tensor, fgrid: FGrid, k0: int, klo: int, khi: int,
+                        gamma: torch.Tensor, tau: torch.Tensor, out=None, workspace: torch.Tensor | None = None,
+                        antipodal: bool = False):
+    """Full Fisher matrix G [npix][npix] of the bins [klo, khi) (Eq. eq_fisher,
+    broadband H weighting of Sec. V) for general weights: w float32 [nt][nf]
+    (rows may be padded: w.stride(0) >= nf), H float32 [nf] (column c = bin
+    k0 + c).  antipodal=True: seeds from build_geometry, half the work."""
+    nt, npix = gamma.shape
+    if w.dim() != 2 or w.shape[0] != nt:
+        raise SgwbError(f"w must be [nt={nt}][nf], got {tuple(w.shape)}")
+    nf = w.shape[1]
+    _require(w, "w", torch.float32, (nt, nf))
+    if w.stride(1) != 1 or w.stride(0) < nf:
+        raise SgwbError("w must have unit column stride and row stride >= nf")
+    _require(H, "H", torch.float32, (nf,))
+    _require(gamma, "gamma", torch.float32, (nt, npix))
+    _require(tau, "tau", torch.float64, (nt, npix))
+    for name, t in (("H", H), ("gamma", gamma), ("tau", tau)):
+        _require_contig(t, name)
+    dev = gamma.device
+    G = out if out is not None else torch.empty((npix, npix), dtype=torch.float32, device=dev)
+    _require(G, "G", torch.float32, (npix, npix))
+    _require_contig(G, "G")
+    fg = _FGrid(float(fgrid.f0), float(fgrid.df))
+    with torch.cuda.device(dev):
+        if workspace is None:
+            need = fisher_full_general_workspace_bytes(fgrid, k0, klo, khi, nt, npix, antipodal)
+            workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        wsz = workspace.numel() * workspace.element_size()
+        rc = lib().sgwb_fisher_full_general(_ptr(w), int(w.stride(0)), _ptr(H), nf, ctypes.byref(fg), int(k0),
+                                            int(klo), int(khi), _ptr(gamma), _ptr(tau), nt, npix,
+                                            SGWB_MAPS_ANTIPODAL if antipodal else 0, _ptr(G), _ptr(workspace), wsz,
+                                            _stream())
+    _check(rc, "fisher_full_general")
     return G
 
 

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include "fisher_general.h"
 #include "sgwb_internal.h"
 
 namespace sgwb {
@@ -444,6 +445,66 @@ int sgwb_fisher_full(const float *a, const float *b, int32_t rank, const float *
     return check_hip(launch_fisher_full(a, b, rank, H, nf, clo, chi, fg->f0_hz, fg->df_hz, k0, gamma, tau, nt, npix,
                                         nside, G, workspace, stream),
                      "full Fisher launch");
+}
+
+// Checks shared by the general-weights size query and entry point; 0 or an
+// error code (with the message set).
+static int check_fisher_general(const sgwb_fgrid *fg, int64_t k0, int32_t clo, int32_t chi, int32_t nf, int32_t nt,
+                                int32_t npix, uint32_t flags, int64_t *nside)
+{
+    if (!fg) return set_error(SGWB_EINVAL, "fisher_full_general: null pointer");
+    if (nt < 1 || nf < 1 || npix < 1) return set_error(SGWB_EINVAL, "fisher_full_general: nt, nf, npix must be >= 1");
+    if (nt > 65535) return set_error(SGWB_EINVAL, "fisher_full_general: nt above 65535");
+    if (!(0 <= clo && clo < chi && chi <= nf))
+        return set_error(SGWB_EINVAL, "fisher_full_general: band [%d, %d) not inside [0, %d)", clo, chi, nf);
+    if (!std::isfinite(fg->f0_hz) || !std::isfinite(fg->df_hz) || fg->df_hz <= 0.0 || fg->f0_hz < 0.0 || k0 < 0)
+        return set_error(SGWB_EINVAL, "fisher_full_general: bad frequency grid");
+    if (!fisher_full_band_ok(fg->f0_hz + (double)(k0 + chi - 1) * fg->df_hz))
+        return set_error(SGWB_EINVAL, "fisher_full_general: band reaches above 24 kHz");
+    if (flags & ~SGWB_MAPS_ANTIPODAL) return set_error(SGWB_EINVAL, "fisher_full_general: unknown flag bits");
+    *nside = 0;
+    if (flags & SGWB_MAPS_ANTIPODAL) {
+        *nside = nside_of_npix(npix);
+        if (*nside == 0)
+            return set_error(SGWB_EINVAL,
+                             "fisher_full_general: SGWB_MAPS_ANTIPODAL needs npix = 12 nside^2, nside a power of two");
+    }
+    const int64_t ntile = ((int64_t)npix + 63) / 64;
+    if (ntile * (ntile + 1) / 2 > 0x7fffffff) return set_error(SGWB_EINVAL, "fisher_full_general: npix too large");
+    return SGWB_OK;
+}
+
+size_t sgwb_fisher_full_general_workspace_size(const sgwb_fgrid *fg, int64_t k0, int32_t clo, int32_t chi,
+                                               int32_t nt, int32_t npix, uint32_t flags)
+{
+    int64_t nside = 0;
+    if (!fg || check_fisher_general(fg, k0, clo, chi, chi, nt, npix, flags, &nside)) return 0;
+    return fisher_full_general_workspace_bytes(fg->f0_hz + (double)(k0 + chi - 1) * fg->df_hz, chi - clo, nt, npix,
+                                               nside);
+}
+
+int sgwb_fisher_full_general(const float *w, int64_t ldw, const float *H, int32_t nf, const sgwb_fgrid *fg,
+                             int64_t k0, int32_t clo, int32_t chi, const float *gamma, const double *tau, int32_t nt,
+                             int32_t npix, uint32_t flags, float *G, void *workspace, size_t workspace_bytes,
+                             hipStream_t stream)
+{
+    if (!w || !H || !fg || !gamma || !tau || !G) return set_error(SGWB_EINVAL, "fisher_full_general: null pointer");
+    int64_t nside = 0;
+    int rc = check_fisher_general(fg, k0, clo, chi, nf, nt, npix, flags, &nside);
+    if (rc) return rc;
+    if (ldw < nf) return set_error(SGWB_EINVAL, "fisher_full_general: ldw < nf");
+    if (((uintptr_t)w % 4) || ((uintptr_t)H % 4) || ((uintptr_t)gamma % 4) || ((uintptr_t)tau % 8) ||
+        ((uintptr_t)G % 4))
+        return set_error(SGWB_EINVAL, "fisher_full_general: misaligned pointer");
+    if (!workspace || (uintptr_t)workspace % 256)
+        return set_error(SGWB_EINVAL, "fisher_full_general: workspace null or not 256-byte aligned");
+    const size_t need = sgwb_fisher_full_general_workspace_size(fg, k0, clo, chi, nt, npix, flags);
+    if (workspace_bytes < need)
+        return set_error(SGWB_ENOMEM, "fisher_full_general: workspace of %zu bytes needed, %zu given", need,
+                         workspace_bytes);
+    return check_hip(launch_fisher_full_general(w, ldw, H, clo, chi, fg->f0_hz, fg->df_hz, k0, gamma, tau, nt, npix,
+                                                nside, G, workspace, stream),
+                     "full Fisher (general weights) launch");
 }
 
 size_t sgwb_clean_map_workspace_size(int32_t n)

@@ -24,7 +24,7 @@
 #include <cstdlib>
 #include <cstring>
 
-#include "sgwb_internal.h"
+#include "fisher_general.h"
 
 namespace sgwb {
 
@@ -87,18 +87,21 @@ __global__ __launch_bounds__(256) void delay_table_kernel(const float *__restric
     part[(size_t)blockIdx.y * (J + 1) + j] = make_double2(sw, sd * delta);
 }
 
-// Pass 2, interval j < J: the chunk sums at both ends (chunk order fixed), then
-// the cubic Hermite interpolant of W on [D_j, D_j+1] written as a polynomial in
-// x = 1 + s, s in [0, 1) the position inside the interval (x is what the
-// assembly kernel builds from the fraction bits).
-__global__ __launch_bounds__(256) void delay_cubic_kernel(const double2 *__restrict__ part, int32_t nchunk, int32_t J,
-                                                          float4 *__restrict__ cub)
+// Pass 2, interval j < J of table blockIdx.y: the chunk sums at both ends
+// (chunk order fixed; chunk q of table y at part + (q stride + y (J + 1))),
+// then the cubic Hermite interpolant of W on [D_j, D_j+1] written as a
+// polynomial in x = 1 + s, s in [0, 1) the position inside the interval (x is
+// what the assembly kernel builds from the fraction bits).
+__global__ __launch_bounds__(256) void delay_cubic_kernel(const double2 *__restrict__ part, int32_t nchunk,
+                                                          int64_t stride, int32_t J, float4 *__restrict__ cub)
 {
     const int32_t j = blockIdx.x * 256 + threadIdx.x;
     if (j >= J) return;
+    part += (size_t)blockIdx.y * (J + 1);
+    cub += (size_t)blockIdx.y * J;
     double2 a = make_double2(0.0, 0.0), b = a;
     for (int32_t q = 0; q < nchunk; ++q) {
-        const double2 u = part[(size_t)q * (J + 1) + j], v = part[(size_t)q * (J + 1) + j + 1];
+        const double2 u = part[(size_t)q * stride + j], v = part[(size_t)q * stride + j + 1];
         a.x += u.x;
         a.y += u.y;
         b.x += v.x;
@@ -109,6 +112,112 @@ __global__ __launch_bounds__(256) void delay_cubic_kernel(const double2 *__restr
     // re-expanded around s = x - 1
     cub[j] = make_float4((float)(c0 - c1 + c2 - c3), (float)(c1 - 2.0 * c2 + 3.0 * c3), (float)(c2 - 3.0 * c3),
                          (float)c3);
+}
+
+// General weights (any w(t,c), not a sum of a few products): one table per
+// segment,
+//   Wd_t(D_j) = sum_{c in band} H_c w(t,c) cos 2 pi f_c D_j,   delta Wd_t'(D_j),
+// for every segment t and grid point j <= J at once.  That is a dense
+// contraction over the band's bins, [nt x nbins] . [nbins x (J + 1)], twice
+// (cosine and sine), so it runs on the float64 matrix cores
+// (v_mfma_f64_16x16x4): per workgroup a 64-segment x 64-point tile, the
+// cosine / sine operand of each 32-bin chunk generated into LDS (a float64
+// phase reduced exactly at the chunk's first bin of each 8, then advanced by a
+// float64 rotation), the weight operand H_c w(t,c) (and -2 pi delta f_c times
+// it for the derivative) built in registers from w.  The bins split into
+// blockIdx.z ranges whose float64 partial sums delay_cubic_kernel adds in a
+// fixed order.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTgM = 64;  // segments per workgroup tile (16 per wave)
+constexpr int kTgN = 64;  // grid points per workgroup tile (four 16-wide blocks)
+constexpr int kTgK = 32;  // bins per chunk (eight 4-deep matrix-core steps)
+
+__global__ __launch_bounds__(256) void delay_table_gemm_kernel(const float *__restrict__ w, int64_t ldw,
+                                                               const float *__restrict__ H, int32_t nt, int32_t clo,
+                                                               int32_t chi, int32_t split_bins, double f0, double df,
+                                                               int64_t k0, double delta, int32_t J,
+                                                               double2 *__restrict__ part)
+{
+    __shared__ double bc[kTgK][kTgN], bs[kTgK][kTgN];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int32_t j0 = blockIdx.x * kTgN, t0 = blockIdx.y * kTgM;
+    const int32_t nb = chi - clo;
+    const int32_t cbeg = blockIdx.z * split_bins, cend = min(nb, cbeg + split_bins);
+    // operand generation: grid point j0 + gj, bins 8 gg .. 8 gg + 7 of a chunk
+    const int gj = threadIdx.x & 63, gg = threadIdx.x >> 6;
+    const double D = (double)(j0 + gj) * delta;
+    double er, ei;
+    sincospi(2.0 * df * D, &ei, &er);
+    // weight operand: segment t0 + 16 wv + lane % 16, bin c0 + 4 ks + lane / 16
+    const int32_t trow = t0 + 16 * wv + (lane & 15);
+    const bool rok = trow < nt;
+    const float *wr = w + (int64_t)(rok ? trow : 0) * ldw + clo;
+    const float *hr = H + clo;
+    const int kq = lane >> 4;
+    dbl4 av[4], ad[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) av[n] = ad[n] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int32_t c0 = cbeg; c0 < cend; c0 += kTgK) {
+        // this chunk's weights first, so their loads overlap the generation
+        float wk[kTgK / 4], hk[kTgK / 4];
+#pragma unroll
+        for (int ks = 0; ks < kTgK / 4; ++ks) {
+            const int32_t c = c0 + 4 * ks + kq;
+            const bool ok = rok && c < cend;
+            wk[ks] = ok ? wr[c] : 0.0f;
+            hk[ks] = ok ? hr[c] : 0.0f;
+        }
+        __syncthreads();
+        {
+            const int32_t cs = c0 + 8 * gg;
+            const double x = (f0 + (double)(k0 + clo + cs) * df) * D, r = x - rint(x);
+            double zr, zi;
+            sincospi(2.0 * r, &zi, &zr);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                bc[8 * gg + i][gj] = zr;
+                bs[8 * gg + i][gj] = zi;
+                const double nr = zr * er - zi * ei, ni = zr * ei + zi * er;
+                zr = nr;
+                zi = ni;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kTgK / 4; ++ks) {
+            const int32_t c = c0 + 4 * ks + kq;
+            const double h = (double)hk[ks] * (double)wk[ks];
+            const double hd = -kTwoPi * delta * (f0 + (double)(k0 + clo + c) * df) * h;
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                const double b1 = bc[4 * ks + kq][16 * n + (lane & 15)];
+                const double b2 = bs[4 * ks + kq][16 * n + (lane & 15)];
+                av[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(h, b1, av[n], 0, 0, 0);
+                ad[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(hd, b2, ad[n], 0, 0, 0);
+            }
+        }
+    }
+    // result layout (measured): register r of a lane holds row lane / 16 + 4 r
+    // of the wave's 16, column lane % 16 of each block
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int32_t t = t0 + 16 * wv + kq + 4 * r, j = j0 + 16 * n + (lane & 15);
+            if (t < nt && j <= J) part[((size_t)blockIdx.z * nt + t) * (J + 1) + j] = make_double2(av[n][r], ad[n][r]);
+        }
+}
+
+// Bin ranges of the table contraction: enough workgroups to fill the chip
+// twice over, at least 16 chunks per range, at most 16 ranges.
+static int32_t general_table_splits(int32_t J, int32_t nt, int32_t nbins)
+{
+    const int64_t tiles = (int64_t)((J + 1 + kTgN - 1) / kTgN) * ((nt + kTgM - 1) / kTgM);
+    const int32_t nchunk = (nbins + kTgK - 1) / kTgK;
+    int64_t s = (2048 + tiles - 1) / tiles;
+    s = std::min<int64_t>(s, std::max(1, nchunk / 16));
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(s, 16));
 }
 
 // Delays as biased fixed-point table coordinates: U = round(tau / delta 2^fb) + 2^30,
@@ -196,12 +305,14 @@ __device__ __forceinline__ uint32_t abs_diff(uint32_t x, uint32_t y)
 // G tile (r, c) of the upper triangle; 256 threads, 4 x 4 entries each.  Per
 // (t, p, q): |U_p - U_q| gives the table interval (high bits) and the position
 // in it (low fb bits, placed in the mantissa of x in [1, 2)); three FMAs
-// evaluate the cubic, two more weight and accumulate it.
+// evaluate the cubic, two more weight and accumulate it.  Segment t reads the
+// table at cub + t seg_stride (0: one table for all, weighted by a[t]; J: one
+// table per segment, a null).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void fisher_full_kernel(const float *__restrict__ a, const float *__restrict__ gamma,
                                                           const uint32_t *__restrict__ U, int32_t nt, int32_t npix,
                                                           int64_t nside, const double *__restrict__ flags,
-                                                          const float4 *__restrict__ cub, int32_t fb, int32_t accumulate,
-                                                          float *__restrict__ G)
+                                                          const float4 *__restrict__ cub, int64_t seg_stride,
+                                                          int32_t fb, int32_t accumulate, float *__restrict__ G)
 {
     __shared__ float gP[kFtSeg][kFt], gQ[kFtSeg][kFt];
     __shared__ uint32_t uP[kFtSeg][kFt], uQ[kFtSeg][kFt];
@@ -220,7 +331,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
             const int tt = e / kFt, i = e % kFt, t = t0 + tt;
             const int64_t p = tr * kFt + i, q = tc * kFt + i;
             const bool ok = t < nt;
-            const float at = ok ? a[t] : 0.0f;
+            const float at = ok ? (a ? a[t] : 1.0f) : 0.0f;
             gP[tt][i] = ok && p < nrow ? at * gamma[(int64_t)t * npix + p] : 0.0f;
             uP[tt][i] = ok && p < nrow ? U[(int64_t)t * npix + p] : kDelayBias;
             gQ[tt][i] = ok && q < nrow ? gamma[(int64_t)t * npix + q] : 0.0f;
@@ -230,6 +341,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
         __syncthreads();
         const int tn = min(kFtSeg, nt - t0);
         for (int tt = 0; tt < tn; ++tt) {
+            const char *ct = cb + (size_t)(t0 + tt) * seg_stride * sizeof(float4);
             float gp[4], gq[4];
             uint32_t up[4], uq[4];
 #pragma unroll
@@ -247,7 +359,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     const uint32_t d = abs_diff(up[i], uq[jj]);
-                    c[i][jj] = *reinterpret_cast<const float4 *>(cb + ((size_t)(d >> fb) << 4));
+                    c[i][jj] = *reinterpret_cast<const float4 *>(ct + ((size_t)(d >> fb) << 4));
                     x[i][jj] = __uint_as_float(((d << (23 - fb)) & 0x007fffffu) | 0x3f800000u);
                 }
 #pragma unroll
@@ -387,6 +499,131 @@ __global__ __launch_bounds__(512) void fisher_full_lds_kernel(const float *__res
     }
 }
 
+// General weights, LDS form: one pass per group of S = t1 - t0 segments whose
+// tables fit in LDS together (S J <= kLdsTable).  Each tile's sums over the
+// group are added to its running sums, kept between passes in acc
+// (tile-major: thread lt of tile k holds its 4 x 4 entries at
+// acc[(k 256 + lt) 16 ..], four float4, so every pass reads and writes acc
+// fully coalesced); the last pass writes the totals to their matrix entries.
+// Same walk, one-ahead loads and arithmetic per term as fisher_full_lds_kernel,
+// the table of segment t at tab + (t - t0) J.
+__global__ __launch_bounds__(512) void fisher_full_seg_lds_kernel(const float *__restrict__ gamma,
+                                                                   const uint32_t *__restrict__ U, int32_t nt,
+                                                                   int32_t npix, int64_t nside,
+                                                                   const double *__restrict__ flags,
+                                                                   const float4 *__restrict__ cub, int32_t J,
+                                                                   int32_t fb, int32_t t0, int32_t t1,
+                                                                   int64_t ntiles, int32_t first, int32_t last,
+                                                                   float4 *__restrict__ acc, float *__restrict__ G)
+{
+    __shared__ float4 tab[kLdsTable];
+    const int32_t ntab = (t1 - t0) * J;
+    for (int j = threadIdx.x; j < ntab; j += 512) tab[j] = cub[(int64_t)t0 * J + j];
+    __syncthreads();
+    const char *tb = reinterpret_cast<const char *>(tab);
+    const int half = threadIdx.x >> 8, lt = threadIdx.x & 255;
+    const int ty = lt / 16, tx = lt % 16;
+    const int64_t nrow = nside > 0 ? npix / 2 : npix;
+    const int32_t last_row = (int32_t)nrow - 1;
+    const int64_t nT = (nrow + kFt - 1) / kFt;
+    const bool rejected = seeds_rejected(flags);
+    const int32_t te = rejected ? t0 : t1;
+    for (int64_t k = (int64_t)blockIdx.x * 2 + half; k < ntiles; k += (int64_t)gridDim.x * 2) {
+        int64_t tr, tc;
+        bool ns;
+        fisher_tile(k, nT, nside > 0, tr, tc, ns);
+        const uint32_t qm = ns ? kDelayMirror : 0u, qs = ns ? 0u : 1u;
+        auto ucol = [qm, qs](uint32_t u) { return qs ? u : qm - u; };
+        int32_t pi[4], qi[4];
+        bool pv[4], qv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t p = tr * kFt + ty * 4 + i, q = tc * kFt + tx * 4 + i;
+            pv[i] = p < nrow;
+            qv[i] = q < nrow;
+            pi[i] = (int32_t)(pv[i] ? p : last_row);
+            qi[i] = (int32_t)(qv[i] ? q : last_row);
+        }
+        float4 *ak = acc + ((size_t)k * 256 + lt) * 4;
+        float acs[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float4 v = first ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : ak[i];
+            acs[i][0] = v.x;
+            acs[i][1] = v.y;
+            acs[i][2] = v.z;
+            acs[i][3] = v.w;
+        }
+        float gp[4], gq[4];
+        uint32_t up[4], uq[4];
+        const int64_t o0 = (int64_t)t0 * npix;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            gp[i] = pv[i] ? gamma[o0 + pi[i]] : 0.0f;
+            up[i] = U[o0 + pi[i]];
+            gq[i] = qv[i] ? gamma[o0 + qi[i]] : 0.0f;
+            uq[i] = ucol(U[o0 + qi[i]]);
+        }
+        for (int32_t t = t0; t < te; ++t) {
+            // next segment's inputs (the last iteration re-reads segment t1 - 1)
+            const int64_t o = (int64_t)min(t + 1, t1 - 1) * npix;
+            float gpn[4], gqn[4];
+            uint32_t upn[4], uqn[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                gpn[i] = gamma[o + pi[i]];
+                upn[i] = U[o + pi[i]];
+                gqn[i] = gamma[o + qi[i]];
+                uqn[i] = U[o + qi[i]];
+            }
+            const char *ts = tb + (size_t)(t - t0) * J * sizeof(float4);
+            float4 c[4][4];
+            float x[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const uint32_t d = abs_diff(up[i], uq[jj]);
+                    c[i][jj] = *reinterpret_cast<const float4 *>(ts + ((d >> fb) << 4));
+                    x[i][jj] = __uint_as_float(((d << (23 - fb)) & 0x007fffffu) | 0x3f800000u);
+                }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const float4 cc = c[i][jj];
+                    const float W = fmaf(fmaf(fmaf(cc.w, x[i][jj], cc.z), x[i][jj], cc.y), x[i][jj], cc.x);
+                    acs[i][jj] = fmaf(gp[i] * gq[jj], W, acs[i][jj]);
+                }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                gp[i] = pv[i] ? gpn[i] : 0.0f;
+                up[i] = upn[i];
+                gq[i] = qv[i] ? gqn[i] : 0.0f;
+                uq[i] = ucol(uqn[i]);
+            }
+        }
+        if (!last) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ak[i] = make_float4(acs[i][0], acs[i][1], acs[i][2], acs[i][3]);
+            continue;
+        }
+        if (rejected) {  // the matrix is NaN
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) acs[i][jj] = __builtin_nanf("");
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int64_t p = tr * kFt + ty * 4 + i, q = tc * kFt + tx * 4 + jj;
+                if (pv[i] && q < nrow && (tr != tc || p <= q)) store_value(G, npix, nside, ns, p, q, acs[i][jj], 0);
+            }
+    }
+}
+
 bool fisher_full_band_ok(double f_max)
 {
     double delta;
@@ -461,16 +698,107 @@ hipError_t launch_fisher_full(const float *a, const float *b, int32_t rank, cons
         const float *ar = a + (int64_t)r * nt, *br = b + (int64_t)r * nf;
         hipLaunchKernelGGL(delay_table_kernel, dim3((unsigned)((J + 1 + 255) / 256), (unsigned)nchunk), dim3(256), 0,
                            s, H, br, clo, chi, f0, df, k0, delta, J, part);
-        hipLaunchKernelGGL(delay_cubic_kernel, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, s, part, nchunk, J,
-                           cub);
+        hipLaunchKernelGGL(delay_cubic_kernel, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, s, part, nchunk,
+                           (int64_t)J + 1, J, cub);
         if (lds) {
             const int64_t grid = std::min<int64_t>(cus, (ntiles + 1) / 2);
             hipLaunchKernelGGL(fisher_full_lds_kernel, dim3((unsigned)grid), dim3(512), 0, s, ar, gamma, U, nt, npix,
                                nside, flags, cub, J, fb, ntiles, (int32_t)(r > 0), G);
         } else {
             hipLaunchKernelGGL(fisher_full_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, ar, gamma, U, nt, npix,
-                               nside, flags, cub, fb, (int32_t)(r > 0), G);
+                               nside, flags, cub, (int64_t)0, fb, (int32_t)(r > 0), G);
         }
+    }
+    return hipGetLastError();
+}
+
+// ---- general weights: workspace layout and launch ----
+struct GeneralLayout {
+    int32_t J = 0, fb = 0, nsplit = 1, split_bins = 0, seg_per_pass = 0;
+    int64_t ntiles = 0;
+    size_t part = 0, cub = 0, U = 0, flags = 0, acc = 0, total = 0;  // byte offsets (total: size)
+};
+
+static GeneralLayout general_layout(double f_max, int32_t nbins, int32_t nt, int32_t npix, int64_t nside)
+{
+    GeneralLayout L;
+    double delta;
+    fisher_table_geometry(f_max, &delta, &L.J, &L.fb);
+    L.nsplit = general_table_splits(L.J, nt, nbins);
+    const int32_t nchunk = (nbins + kTgK - 1) / kTgK;
+    L.split_bins = ((nchunk + L.nsplit - 1) / L.nsplit) * kTgK;
+    L.nsplit = (nbins + L.split_bins - 1) / L.split_bins;
+    const int64_t nrow = nside > 0 ? npix / 2 : npix;
+    const int64_t nT = (nrow + kFt - 1) / kFt;
+    L.ntiles = (nside > 0 ? 2 : 1) * (nT * (nT + 1) / 2);
+    L.seg_per_pass = L.J <= kLdsTable ? kLdsTable / L.J : 0;
+    size_t o = 0;
+    L.part = o;
+    o += up256((size_t)L.nsplit * nt * (L.J + 1) * sizeof(double2));
+    L.cub = o;
+    o += up256((size_t)nt * L.J * sizeof(float4));
+    L.U = o;
+    o += up256((size_t)nt * npix * sizeof(uint32_t));
+    L.flags = o;
+    o += up256(kSymParts * sizeof(double));
+    L.acc = o;
+    // running sums between passes of the LDS form (none if one pass holds every segment)
+    if (L.seg_per_pass > 0 && L.seg_per_pass < nt) o += (size_t)L.ntiles * kFt * kFt * sizeof(float);
+    L.total = o;
+    return L;
+}
+
+size_t fisher_full_general_workspace_bytes(double f_max, int32_t nbins, int32_t nt, int32_t npix, int64_t nside)
+{
+    return general_layout(f_max, nbins, nt, npix, nside).total;
+}
+
+hipError_t launch_fisher_full_general(const float *w, int64_t ldw, const float *H, int32_t clo, int32_t chi,
+                                      double f0, double df, int64_t k0, const float *gamma, const double *tau,
+                                      int32_t nt, int32_t npix, int64_t nside, float *G, void *work, hipStream_t s)
+{
+    const double f_max = f0 + (double)(k0 + chi - 1) * df;
+    const int32_t nbins = chi - clo;
+    const GeneralLayout L = general_layout(f_max, nbins, nt, npix, nside);
+    if (L.fb < kFracBitsMin || L.ntiles > 0x7fffffff) return hipErrorInvalidValue;
+    double delta;
+    int32_t J, fb;
+    fisher_table_geometry(f_max, &delta, &J, &fb);
+    char *base = reinterpret_cast<char *>(work);
+    double2 *part = reinterpret_cast<double2 *>(base + L.part);
+    float4 *cub = reinterpret_cast<float4 *>(base + L.cub);
+    uint32_t *U = reinterpret_cast<uint32_t *>(base + L.U);
+    double *flags = nullptr;
+    if (nside > 0) {
+        flags = reinterpret_cast<double *>(base + L.flags);
+        const hipError_t e = launch_antipodal_check(gamma, tau, nt, npix, nside, flags, s);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t n = (int64_t)nt * npix;
+    hipLaunchKernelGGL(fixed_delay_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tau, n,
+                       std::ldexp(1.0, fb) / delta, U);
+    hipLaunchKernelGGL(delay_table_gemm_kernel,
+                       dim3((unsigned)((J + 1 + kTgN - 1) / kTgN), (unsigned)((nt + kTgM - 1) / kTgM),
+                            (unsigned)L.nsplit),
+                       dim3(256), 0, s, w, ldw, H, nt, clo, chi, L.split_bins, f0, df, k0, delta, J, part);
+    hipLaunchKernelGGL(delay_cubic_kernel, dim3((unsigned)((J + 255) / 256), (unsigned)nt), dim3(256), 0, s, part,
+                       L.nsplit, (int64_t)nt * (J + 1), J, cub);
+    const bool lds = L.seg_per_pass > 0 && fisher_full_table_in_lds();
+    if (!lds) {
+        hipLaunchKernelGGL(fisher_full_kernel, dim3((unsigned)L.ntiles), dim3(256), 0, s, (const float *)nullptr,
+                           gamma, U, nt, npix, nside, flags, cub, (int64_t)J, fb, (int32_t)0, G);
+        return hipGetLastError();
+    }
+    int cus = 256, dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    const int64_t grid = std::min<int64_t>(cus, (L.ntiles + 1) / 2);
+    float4 *acc = reinterpret_cast<float4 *>(base + L.acc);
+    for (int32_t t0 = 0; t0 < nt; t0 += L.seg_per_pass) {
+        const int32_t t1 = std::min(nt, t0 + L.seg_per_pass);
+        hipLaunchKernelGGL(fisher_full_seg_lds_kernel, dim3((unsigned)grid), dim3(512), 0, s, gamma, U, nt, npix,
+                           nside, flags, cub, J, fb, t0, t1, L.ntiles, (int32_t)(t0 == 0), (int32_t)(t1 == nt), acc,
+                           G);
     }
     return hipGetLastError();
 }

@@ -134,6 +134,34 @@ def weights(f, a_t):
     return np.outer(a_t, spectrum_H(f) / noise_psd(f) ** 2)
 
 
+def nonstationary_weights(f, nt: int, seed: int):
+    """Folded weights of a day whose noise changes shape, not only level, from
+    segment to segment: w(t,f) = H(f) / (P_t(f) Q_t(f)) with per-detector
+    spectra P_t = s_t P(f) (f / 100 Hz)^(e_t) g_t(f) and Q_t likewise: seeded
+    level s_t in U[0.5, 1.5], tilt e_t in U[-0.3, 0.3], the scatter g_t(f) of a
+    16-average spectral estimate (Gamma(16, 1/16) per bin), and a few narrow
+    lines (a bin-wide power excess of 10-100x) switching on and off across the
+    day.  float64 [nt][nf], of full rank (min(nt, nf)): no sum of a few
+    products a(t) b(f) equals it."""
+    f = np.asarray(f, dtype=np.float64)
+    rng = np.random.default_rng(seed)
+    P0 = noise_psd(f)
+    out = np.empty((nt, f.size))
+    nlines = max(1, f.size // 200)
+    lines = rng.choice(f.size, size=min(nlines, f.size), replace=False)
+    for t in range(nt):
+        psd = []
+        for _ in range(2):
+            level = rng.uniform(0.5, 1.5)
+            tilt = rng.uniform(-0.3, 0.3)
+            P = level * P0 * (f / 100.0) ** tilt * rng.gamma(16.0, 1.0 / 16.0, f.size)
+            on = lines[rng.random(lines.size) < 0.5]
+            P[on] *= rng.uniform(10.0, 100.0, on.size)
+            psd.append(P)
+        out[t] = spectrum_H(f) / (psd[0] * psd[1])
+    return out
+
+
 # Neighbour weight of 50%-overlapping Hann windows (Sec. II.B).
 HANN_OVERLAP_W = 3.0 / 70.0
 

@@ -167,6 +167,52 @@ def test_fisher_full_and_clean_map_validation_on_the_host():
     assert L.sgwb_clean_map_workspace_size(0) == 0 < L.sgwb_clean_map_workspace_size(10)
 
 
+def test_fisher_full_general_validation_on_the_host():
+    import paper_1803_08285_amd as sg
+
+    L = sg.lib()
+    fg = sg._FGrid(20.0, 1 / 32)
+    d = ctypes.c_void_p(256)
+    big = 1 << 40
+    F = L.sgwb_fisher_full_general
+    # band outside the columns, empty band
+    rc = F(d, 10, d, 10, ctypes.byref(fg), 0, 4, 11, d, d, 8, 768, 0, d, d, big, None)
+    assert rc == -1 and b"band" in L.sgwb_last_error()
+    assert F(d, 10, d, 10, ctypes.byref(fg), 0, 5, 5, d, d, 8, 768, 0, d, d, big, None) == -1
+    # row stride below the row length
+    rc = F(d, 9, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, 0, d, d, big, None)
+    assert rc == -1 and b"ldw" in L.sgwb_last_error()
+    # segment count beyond the table grid
+    rc = F(d, 10, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 65536, 768, 0, d, d, big, None)
+    assert rc == -1 and b"65535" in L.sgwb_last_error()
+    # null weights, null output, misaligned tau
+    assert F(None, 10, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, 0, d, d, big, None) == -1
+    assert F(d, 10, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, 0, None, d, big, None) == -1
+    rc = F(d, 10, d, 10, ctypes.byref(fg), 0, 0, 10, d, ctypes.c_void_p(260), 8, 768, 0, d, d, big, None)
+    assert rc == -1 and b"misaligned" in L.sgwb_last_error()
+    # flags: unknown bits; antipodal with a non-HEALPix pixel count
+    rc = F(d, 10, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, 4, d, d, big, None)
+    assert rc == -1 and b"flag" in L.sgwb_last_error()
+    rc = F(d, 10, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 700, 1, d, d, big, None)
+    assert rc == -1 and b"12 nside^2" in L.sgwb_last_error()
+    # workspace too small, or misaligned
+    assert F(d, 10, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, 0, d, d, 256, None) == -2
+    assert F(d, 10, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, 0, d, ctypes.c_void_p(260), big, None) == -1
+    # sizes: grow with the top frequency (table length) and with the segment
+    # count; the antipodal blocks hold fewer running sums; out of range -> 0
+    W = L.sgwb_fisher_full_general_workspace_size
+    low = W(ctypes.byref(fg), 0, 0, 10, 8, 768, 0)
+    high = W(ctypes.byref(fg), 50000, 0, 10, 8, 768, 0)
+    more = W(ctypes.byref(fg), 50000, 0, 10, 9, 768, 0)
+    assert 0 < low < high < more
+    assert W(ctypes.byref(fg), 50000, 0, 10, 64, 768, 1) < W(ctypes.byref(fg), 50000, 0, 10, 64, 768, 0)
+    bad = sg._FGrid(20.0, 0.0)
+    assert W(ctypes.byref(bad), 0, 0, 10, 8, 768, 0) == 0
+    assert W(ctypes.byref(fg), 32 * 30000, 0, 10, 8, 768, 0) == 0
+    rc = F(d, 10, d, 10, ctypes.byref(fg), 32 * 30000, 0, 10, d, d, 8, 768, 0, d, d, big, None)
+    assert rc == -1 and b"24 kHz" in L.sgwb_last_error()
+
+
 def test_make_maps_band_validation_on_the_host():
     import paper_1803_08285_amd as sg
 
