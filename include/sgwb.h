@@ -293,15 +293,17 @@ int sgwb_fisher_full(const float *a, const float *b, int32_t rank, const float *
  * values and derivatives summed over the band's bins in float64 on the matrix
  * cores (a product of the [nt][nbins] weights with cosines and sines generated
  * in float64), then the same float32 cubic interpolants, fixed-point delays
- * and float32 accumulation over t; same tolerance.  When the tables of several
- * segments fit the 160 KiB of LDS together (bands up to 1.88 kHz) the matrix
- * is built in passes over groups of segments, its running sums kept in the
- * workspace between passes.
+ * and float32 accumulation over t; same tolerance.  The tables stop at the
+ * largest delay difference the seeds can have, 2 max|tau| (found on the
+ * device; |x_A - x_B| / c for seeds of sgwb_build_geometry), not at the
+ * Earth's 4 R_earth / c.  For bands up to 1.88 kHz the tables stream through
+ * LDS while each workgroup keeps its matrix tiles' sums in registers over all
+ * segments; above, the tables are read from global memory.
  * Workspace: at least sgwb_fisher_full_general_workspace_size() bytes (0 for
- * arguments out of range), 256-byte aligned, owned by the caller; it grows
- * with nt x the table length (about 0.2 MB per segment for the full
- * 20-1726 Hz band) and, for more than one pass, with the computed blocks
- * (npix^2 float32, a quarter of that with SGWB_MAPS_ANTIPODAL).
+ * arguments out of range), 256-byte aligned, owned by the caller: the tables
+ * and the partial sums of their band sums, sized for the Earth bound (about
+ * 0.75 MB per segment for the full 20-1726 Hz band), and the fixed-point
+ * delays (4 bytes per seed).
  * Errors: SGWB_EINVAL (null pointer, nt/nf/npix out of range, ldw < nf, band
  * out of range or reaching above 24 kHz, bad grid, unknown flag bits or the
  * antipodal flag with a non-HEALPix npix, misaligned pointer, more than

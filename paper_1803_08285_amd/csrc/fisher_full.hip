@@ -47,6 +47,48 @@ void fisher_table_geometry(double f_max, double *delta, int32_t *J, int32_t *fb)
     *fb = b;
 }
 
+// Delay bound of a seed set, for tables no longer than its delay differences
+// need: max |tau| over all seeds (NaN counted as the Earth bound), as the bit
+// pattern of a non-negative double (ordered like the value), reduced with an
+// integer atomic max into *bound, which delay_bound_init_kernel zeroes first.
+__global__ __launch_bounds__(64) void delay_bound_init_kernel(unsigned long long *__restrict__ bound)
+{
+    if (threadIdx.x == 0) *bound = 0ull;
+}
+
+__global__ __launch_bounds__(256) void delay_bound_kernel(const double *__restrict__ tau, int64_t n,
+                                                          unsigned long long *__restrict__ bound)
+{
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double v = tau[i];
+        m = fmax(m, v != v ? kMaxDelay : fabs(v));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(bound, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+// Table intervals the seeds can reach: |tau_p - tau_q| <= 2 m with m their
+// delay bound (clamped to the Earth bound, as the delays are), so an interval
+// index (|U_p - U_q| >> fb, rounding included) stays <= ceil(2 m / delta) and
+// ceil(2 m / delta) + 2 intervals suffice; J (the Earth bound's count) without
+// a bound.
+__device__ __forceinline__ int32_t table_intervals(const unsigned long long *__restrict__ bound, double delta,
+                                                   int32_t J)
+{
+    if (!bound) return J;
+    const double m = fmin(__longlong_as_double((long long)*bound), kMaxDelay);
+    return min(J, (int32_t)ceil(2.0 * m / delta) + 2);
+}
+
+constexpr int kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt left at their maxima
+
 // Pass 1, entry j <= J and one chunk of kTabChunk bins: the chunk's share of
 // W(D_j) and delta dW/dD (D_j) in float64, D_j = j delta.  Phases are reduced
 // in float64 at every 64th bin and advanced by a float64 rotation in between.
@@ -87,137 +129,201 @@ __global__ __launch_bounds__(256) void delay_table_kernel(const float *__restric
     part[(size_t)blockIdx.y * (J + 1) + j] = make_double2(sw, sd * delta);
 }
 
-// Pass 2, interval j < J of table blockIdx.y: the chunk sums at both ends
-// (chunk order fixed; chunk q of table y at part + (q stride + y (J + 1))),
-// then the cubic Hermite interpolant of W on [D_j, D_j+1] written as a
-// polynomial in x = 1 + s, s in [0, 1) the position inside the interval (x is
-// what the assembly kernel builds from the fraction bits).
-__global__ __launch_bounds__(256) void delay_cubic_kernel(const double2 *__restrict__ part, int32_t nchunk,
-                                                          int64_t stride, int32_t J, float4 *__restrict__ cub)
+// Cubic Hermite interpolant of W on [D_j, D_j+1] from (W, delta W') at both
+// ends, written as a polynomial in x = 1 + s, s in [0, 1) the position inside
+// the interval (x is what the assembly kernels build from the fraction bits).
+__device__ __forceinline__ float4 hermite_cubic(double2 a, double2 b)
+{
+    // polynomial in s
+    const double c0 = a.x, c1 = a.y, c2 = 3.0 * (b.x - a.x) - 2.0 * a.y - b.y, c3 = 2.0 * (a.x - b.x) + a.y + b.y;
+    // re-expanded around s = x - 1
+    return make_float4((float)(c0 - c1 + c2 - c3), (float)(c1 - 2.0 * c2 + 3.0 * c3), (float)(c2 - 3.0 * c3),
+                       (float)c3);
+}
+
+// Pass 2, interval j < J: the chunk sums at both ends (chunk order fixed),
+// then the interval's cubic.
+__global__ __launch_bounds__(256) void delay_cubic_kernel(const double2 *__restrict__ part, int32_t nchunk, int32_t J,
+                                                          float4 *__restrict__ cub)
 {
     const int32_t j = blockIdx.x * 256 + threadIdx.x;
     if (j >= J) return;
-    part += (size_t)blockIdx.y * (J + 1);
-    cub += (size_t)blockIdx.y * J;
     double2 a = make_double2(0.0, 0.0), b = a;
     for (int32_t q = 0; q < nchunk; ++q) {
-        const double2 u = part[(size_t)q * stride + j], v = part[(size_t)q * stride + j + 1];
+        const double2 u = part[(size_t)q * (J + 1) + j], v = part[(size_t)q * (J + 1) + j + 1];
         a.x += u.x;
         a.y += u.y;
         b.x += v.x;
         b.y += v.y;
     }
-    // polynomial in s
-    const double c0 = a.x, c1 = a.y, c2 = 3.0 * (b.x - a.x) - 2.0 * a.y - b.y, c3 = 2.0 * (a.x - b.x) + a.y + b.y;
-    // re-expanded around s = x - 1
-    cub[j] = make_float4((float)(c0 - c1 + c2 - c3), (float)(c1 - 2.0 * c2 + 3.0 * c3), (float)(c2 - 3.0 * c3),
-                         (float)c3);
+    cub[j] = hermite_cubic(a, b);
 }
 
 // General weights (any w(t,c), not a sum of a few products): one table per
 // segment,
 //   Wd_t(D_j) = sum_{c in band} H_c w(t,c) cos 2 pi f_c D_j,   delta Wd_t'(D_j),
-// for every segment t and grid point j <= J at once.  That is a dense
-// contraction over the band's bins, [nt x nbins] . [nbins x (J + 1)], twice
-// (cosine and sine), so it runs on the float64 matrix cores
-// (v_mfma_f64_16x16x4): per workgroup a 64-segment x 64-point tile, the
-// cosine / sine operand of each 32-bin chunk generated into LDS (a float64
-// phase reduced exactly at the chunk's first bin of each 8, then advanced by a
-// float64 rotation), the weight operand H_c w(t,c) (and -2 pi delta f_c times
-// it for the derivative) built in registers from w.  The bins split into
-// blockIdx.z ranges whose float64 partial sums delay_cubic_kernel adds in a
-// fixed order.
+// for every segment t and grid point j <= Jv (the points the seeds' delay
+// bound can reach) at once.  That is a dense contraction over the band's bins,
+// [nt x nbins] . [nbins x (Jv + 1)], twice (cosine and sine), so it runs on the
+// float64 matrix cores (v_mfma_f64_16x16x4): per work item a 64-segment x
+// 64-point tile over one range of the bins, the cosine / sine operand of each
+// 32-bin chunk generated into LDS (a float64 phase reduced exactly at the
+// chunk's first bin of each 8, then advanced by a float64 rotation), the
+// weight operand H_c w(t,c) (and -2 pi delta f_c times it for the derivative)
+// built in registers from w.  Workgroups walk the items persistently; the
+// bins split into as many ranges as fill the chip (their count, like Jv, is
+// worked out on the device), whose float64 partial sums
+// delay_cubic_general_kernel adds in a fixed order.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTgM = 64;  // segments per workgroup tile (16 per wave)
-constexpr int kTgN = 64;  // grid points per workgroup tile (four 16-wide blocks)
-constexpr int kTgK = 32;  // bins per chunk (eight 4-deep matrix-core steps)
+constexpr int kTgM = 64;          // segments per tile (16 per wave)
+constexpr int kTgN = 64;          // grid points per tile (four 16-wide blocks)
+constexpr int kTgK = 32;          // bins per chunk (eight 4-deep matrix-core steps)
+constexpr int kTgSplitsMax = 16;  // bin ranges at most
+constexpr int kTgSplitsBuf = 4;   // partial sums held: kTgSplitsBuf x nt x (J + 1) points
+constexpr int kTgItems = 8192;    // work items aimed at
+
+struct TableSplit {
+    int32_t n;     // bin ranges
+    int32_t bins;  // bins per range (a multiple of kTgK)
+};
+
+// Partial-sum buffer of the table contraction, in tables of J + 1 points per
+// segment: kTgSplitsBuf, fewer for bands of under 16 chunks a range.
+__host__ __device__ __forceinline__ int32_t table_split_cap(int32_t nbins)
+{
+    const int32_t c = ((nbins + kTgK - 1) / kTgK) / 16;
+    return c < 1 ? 1 : (c < kTgSplitsBuf ? c : kTgSplitsBuf);
+}
+
+// Bin ranges for a table of Jv intervals: about kTgItems work items, at least
+// 16 chunks a range (unless there is one range), at most kTgSplitsMax, and no
+// more partial sums than the buffer holds (n (Jv + 1) <= cap (J + 1)).
+__host__ __device__ __forceinline__ TableSplit table_split(int32_t Jv, int32_t J, int32_t nt, int32_t nbins)
+{
+    const int64_t tiles = (int64_t)((Jv + 1 + kTgN - 1) / kTgN) * ((nt + kTgM - 1) / kTgM);
+    const int32_t nchunk = (nbins + kTgK - 1) / kTgK;
+    int64_t n = (kTgItems + tiles - 1) / tiles;
+    n = n < nchunk / 16 ? n : nchunk / 16;
+    const int64_t fit = (int64_t)table_split_cap(nbins) * (J + 1) / (Jv + 1);
+    n = n < fit ? n : fit;
+    n = n < kTgSplitsMax ? n : kTgSplitsMax;
+    n = n > 1 ? n : 1;
+    TableSplit r;
+    r.bins = (int32_t)((nchunk + n - 1) / n) * kTgK;
+    r.n = (nbins + r.bins - 1) / r.bins;
+    return r;
+}
 
 __global__ __launch_bounds__(256) void delay_table_gemm_kernel(const float *__restrict__ w, int64_t ldw,
                                                                const float *__restrict__ H, int32_t nt, int32_t clo,
-                                                               int32_t chi, int32_t split_bins, double f0, double df,
-                                                               int64_t k0, double delta, int32_t J,
+                                                               int32_t chi, double f0, double df, int64_t k0,
+                                                               double delta, int32_t J,
+                                                               const unsigned long long *__restrict__ bound,
                                                                double2 *__restrict__ part)
 {
     __shared__ double bc[kTgK][kTgN], bs[kTgK][kTgN];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int32_t j0 = blockIdx.x * kTgN, t0 = blockIdx.y * kTgM;
-    const int32_t nb = chi - clo;
-    const int32_t cbeg = blockIdx.z * split_bins, cend = min(nb, cbeg + split_bins);
-    // operand generation: grid point j0 + gj, bins 8 gg .. 8 gg + 7 of a chunk
-    const int gj = threadIdx.x & 63, gg = threadIdx.x >> 6;
-    const double D = (double)(j0 + gj) * delta;
-    double er, ei;
-    sincospi(2.0 * df * D, &ei, &er);
-    // weight operand: segment t0 + 16 wv + lane % 16, bin c0 + 4 ks + lane / 16
-    const int32_t trow = t0 + 16 * wv + (lane & 15);
-    const bool rok = trow < nt;
-    const float *wr = w + (int64_t)(rok ? trow : 0) * ldw + clo;
-    const float *hr = H + clo;
     const int kq = lane >> 4;
-    dbl4 av[4], ad[4];
+    const int gj = threadIdx.x & 63, gg = threadIdx.x >> 6;  // generation: point gj, bins 8 gg .. 8 gg + 7
+    const int32_t nb = chi - clo;
+    const int32_t Jv = table_intervals(bound, delta, J);
+    const TableSplit sp = table_split(Jv, J, nt, nb);
+    const int32_t nx = (Jv + 1 + kTgN - 1) / kTgN, ny = (nt + kTgM - 1) / kTgM;
+    const int64_t items = (int64_t)nx * ny * sp.n;
+    const float *hr = H + clo;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int32_t bx = (int32_t)(it % nx);
+        const int64_t rest = it / nx;
+        const int32_t by = (int32_t)(rest % ny), bz = (int32_t)(rest / ny);
+        const int32_t j0 = bx * kTgN, t0 = by * kTgM;
+        const int32_t cbeg = bz * sp.bins, cend = min(nb, cbeg + sp.bins);
+        const double D = (double)(j0 + gj) * delta;
+        double er, ei;
+        sincospi(2.0 * df * D, &ei, &er);
+        // weight operand: segment t0 + 16 wv + lane % 16, bin c0 + 4 ks + lane / 16
+        const int32_t trow = t0 + 16 * wv + (lane & 15);
+        const bool rok = trow < nt;
+        const float *wr = w + (int64_t)(rok ? trow : 0) * ldw + clo;
+        dbl4 av[4], ad[4];
 #pragma unroll
-    for (int n = 0; n < 4; ++n) av[n] = ad[n] = dbl4{0.0, 0.0, 0.0, 0.0};
-    for (int32_t c0 = cbeg; c0 < cend; c0 += kTgK) {
-        // this chunk's weights first, so their loads overlap the generation
-        float wk[kTgK / 4], hk[kTgK / 4];
+        for (int n = 0; n < 4; ++n) av[n] = ad[n] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int32_t c0 = cbeg; c0 < cend; c0 += kTgK) {
+            // this chunk's weights first, so their loads overlap the generation
+            float wk[kTgK / 4], hk[kTgK / 4];
 #pragma unroll
-        for (int ks = 0; ks < kTgK / 4; ++ks) {
-            const int32_t c = c0 + 4 * ks + kq;
-            const bool ok = rok && c < cend;
-            wk[ks] = ok ? wr[c] : 0.0f;
-            hk[ks] = ok ? hr[c] : 0.0f;
-        }
-        __syncthreads();
-        {
-            const int32_t cs = c0 + 8 * gg;
-            const double x = (f0 + (double)(k0 + clo + cs) * df) * D, r = x - rint(x);
-            double zr, zi;
-            sincospi(2.0 * r, &zi, &zr);
+            for (int ks = 0; ks < kTgK / 4; ++ks) {
+                const int32_t c = c0 + 4 * ks + kq;
+                const bool ok = rok && c < cend;
+                wk[ks] = ok ? wr[c] : 0.0f;
+                hk[ks] = ok ? hr[c] : 0.0f;
+            }
+            __syncthreads();  // the previous chunk's (or item's) operands are no longer read
+            {
+                const int32_t cs = c0 + 8 * gg;
+                const double x = (f0 + (double)(k0 + clo + cs) * df) * D, r = x - rint(x);
+                double zr, zi;
+                sincospi(2.0 * r, &zi, &zr);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                bc[8 * gg + i][gj] = zr;
-                bs[8 * gg + i][gj] = zi;
-                const double nr = zr * er - zi * ei, ni = zr * ei + zi * er;
-                zr = nr;
-                zi = ni;
+                for (int i = 0; i < 8; ++i) {
+                    bc[8 * gg + i][gj] = zr;
+                    bs[8 * gg + i][gj] = zi;
+                    const double nr = zr * er - zi * ei, ni = zr * ei + zi * er;
+                    zr = nr;
+                    zi = ni;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < kTgK / 4; ++ks) {
+                const int32_t c = c0 + 4 * ks + kq;
+                const double h = (double)hk[ks] * (double)wk[ks];
+                const double hd = -kTwoPi * delta * (f0 + (double)(k0 + clo + c) * df) * h;
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    const double b1 = bc[4 * ks + kq][16 * n + (lane & 15)];
+                    const double b2 = bs[4 * ks + kq][16 * n + (lane & 15)];
+                    av[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(h, b1, av[n], 0, 0, 0);
+                    ad[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(hd, b2, ad[n], 0, 0, 0);
+                }
             }
         }
-        __syncthreads();
+        // result layout (measured): register r of a lane holds row lane / 16 + 4 r
+        // of the wave's 16, column lane % 16 of each block; partial sums of range
+        // bz at part + (bz nt + t) (Jv + 1) + j
 #pragma unroll
-        for (int ks = 0; ks < kTgK / 4; ++ks) {
-            const int32_t c = c0 + 4 * ks + kq;
-            const double h = (double)hk[ks] * (double)wk[ks];
-            const double hd = -kTwoPi * delta * (f0 + (double)(k0 + clo + c) * df) * h;
+        for (int n = 0; n < 4; ++n)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                const double b1 = bc[4 * ks + kq][16 * n + (lane & 15)];
-                const double b2 = bs[4 * ks + kq][16 * n + (lane & 15)];
-                av[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(h, b1, av[n], 0, 0, 0);
-                ad[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(hd, b2, ad[n], 0, 0, 0);
+            for (int r = 0; r < 4; ++r) {
+                const int32_t t = t0 + 16 * wv + kq + 4 * r, j = j0 + 16 * n + (lane & 15);
+                if (t < nt && j <= Jv)
+                    part[((size_t)bz * nt + t) * (Jv + 1) + j] = make_double2(av[n][r], ad[n][r]);
             }
-        }
     }
-    // result layout (measured): register r of a lane holds row lane / 16 + 4 r
-    // of the wave's 16, column lane % 16 of each block
-#pragma unroll
-    for (int n = 0; n < 4; ++n)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int32_t t = t0 + 16 * wv + kq + 4 * r, j = j0 + 16 * n + (lane & 15);
-            if (t < nt && j <= J) part[((size_t)blockIdx.z * nt + t) * (J + 1) + j] = make_double2(av[n][r], ad[n][r]);
-        }
 }
 
-// Bin ranges of the table contraction: enough workgroups to fill the chip
-// twice over, at least 16 chunks per range, at most 16 ranges.
-static int32_t general_table_splits(int32_t J, int32_t nt, int32_t nbins)
+// Cubic of interval j < Jv of segment blockIdx.y's table, from the bin ranges'
+// partial sums (range order fixed).
+__global__ __launch_bounds__(256) void delay_cubic_general_kernel(const double2 *__restrict__ part, int32_t nt,
+                                                                  int32_t nbins, int32_t J,
+                                                                  const unsigned long long *__restrict__ bound,
+                                                                  double delta, float4 *__restrict__ cub)
 {
-    const int64_t tiles = (int64_t)((J + 1 + kTgN - 1) / kTgN) * ((nt + kTgM - 1) / kTgM);
-    const int32_t nchunk = (nbins + kTgK - 1) / kTgK;
-    int64_t s = (2048 + tiles - 1) / tiles;
-    s = std::min<int64_t>(s, std::max(1, nchunk / 16));
-    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(s, 16));
+    const int32_t j = blockIdx.x * 256 + threadIdx.x;
+    const int32_t Jv = table_intervals(bound, delta, J);
+    if (j >= Jv) return;
+    const TableSplit sp = table_split(Jv, J, nt, nbins);
+    const size_t stride = (size_t)nt * (Jv + 1);
+    part += (size_t)blockIdx.y * (Jv + 1);
+    double2 a = make_double2(0.0, 0.0), b = a;
+    for (int32_t q = 0; q < sp.n; ++q) {
+        const double2 u = part[q * stride + j], v = part[q * stride + j + 1];
+        a.x += u.x;
+        a.y += u.y;
+        b.x += v.x;
+        b.y += v.y;
+    }
+    cub[(size_t)blockIdx.y * J + j] = hermite_cubic(a, b);
 }
 
 // Delays as biased fixed-point table coordinates: U = round(tau / delta 2^fb) + 2^30,
@@ -499,129 +605,156 @@ __global__ __launch_bounds__(512) void fisher_full_lds_kernel(const float *__res
     }
 }
 
-// General weights, LDS form: one pass per group of S = t1 - t0 segments whose
-// tables fit in LDS together (S J <= kLdsTable).  Each tile's sums over the
-// group are added to its running sums, kept between passes in acc
-// (tile-major: thread lt of tile k holds its 4 x 4 entries at
-// acc[(k 256 + lt) 16 ..], four float4, so every pass reads and writes acc
-// fully coalesced); the last pass writes the totals to their matrix entries.
-// Same walk, one-ahead loads and arithmetic per term as fisher_full_lds_kernel,
-// the table of segment t at tab + (t - t0) J.
-__global__ __launch_bounds__(512) void fisher_full_seg_lds_kernel(const float *__restrict__ gamma,
-                                                                   const uint32_t *__restrict__ U, int32_t nt,
-                                                                   int32_t npix, int64_t nside,
-                                                                   const double *__restrict__ flags,
-                                                                   const float4 *__restrict__ cub, int32_t J,
-                                                                   int32_t fb, int32_t t0, int32_t t1,
-                                                                   int64_t ntiles, int32_t first, int32_t last,
-                                                                   float4 *__restrict__ acc, float *__restrict__ G)
+// General weights, streaming form: each workgroup owns kStTiles consecutive
+// tiles of the walk (two waves a tile, one per 32-column half; lane (ty, tx)
+// of a wave the 8 x 4 entries rows 8 ty.., columns 4 tx.. of its half), keeps
+// their sums in registers over every segment and streams the segments'
+// tables through LDS, copied straight from global memory (global_load_lds, 16
+// bytes a lane), a stage of as many segments as fit at a time.  Stages of
+// tables up to kLdsTable / 2 intervals are double-buffered (stage s + 1 lands
+// while stage s is read); longer tables take turns in one buffer.  Only the
+// first Jv intervals of each table are copied: those the seeds' delay bound
+// can reach.  Same term arithmetic as the other forms, so the same bits in the
+// same segment order.
+constexpr int kStTiles = 4;
+constexpr int kStWaves = 2 * kStTiles;  // 512 threads
+
+// Tables of segments s0 .. s0 + ns - 1 (their first Jv intervals; table t at
+// cub + t J) into LDS back to back, 16 bytes a lane straight from global
+// memory; lane l of a wave writes the l-th 16 bytes after the wave's base.
+__device__ __forceinline__ void copy_tables_lds(const float4 *__restrict__ cub, int32_t J, int32_t Jv, int32_t s0,
+                                                int32_t ns, float4 *dst)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t n = ns * Jv;
+    for (int32_t e = threadIdx.x; e < n; e += kStWaves * 64) {
+        const int32_t sg = e / Jv, i = e - sg * Jv;
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const char *>(cub + (size_t)(s0 + sg) * J + i),
+                                         dst + (e - lane), 16, 0, 0);
+    }
+}
+
+__global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__restrict__ gamma,
+                                                                 const uint32_t *__restrict__ U, int32_t nt,
+                                                                 int32_t npix, int64_t nside,
+                                                                 const double *__restrict__ flags,
+                                                                 const float4 *__restrict__ cub, int32_t J,
+                                                                 const unsigned long long *__restrict__ bound,
+                                                                 double delta, int32_t fb, int64_t ntiles,
+                                                                 float *__restrict__ G)
 {
     __shared__ float4 tab[kLdsTable];
-    const int32_t ntab = (t1 - t0) * J;
-    for (int j = threadIdx.x; j < ntab; j += 512) tab[j] = cub[(int64_t)t0 * J + j];
-    __syncthreads();
-    const char *tb = reinterpret_cast<const char *>(tab);
-    const int half = threadIdx.x >> 8, lt = threadIdx.x & 255;
-    const int ty = lt / 16, tx = lt % 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ty = lane >> 3, tx = lane & 7;
     const int64_t nrow = nside > 0 ? npix / 2 : npix;
     const int32_t last_row = (int32_t)nrow - 1;
     const int64_t nT = (nrow + kFt - 1) / kFt;
+    const int64_t k = (int64_t)blockIdx.x * kStTiles + (wv >> 1);
+    const bool active = k < ntiles;
+    int64_t tr = 0, tc = 0;
+    bool ns = false;
+    if (active) fisher_tile(k, nT, nside > 0, tr, tc, ns);
+    const uint32_t qm = ns ? kDelayMirror : 0u, qs = ns ? 0u : 1u;
+    auto ucol = [qm, qs](uint32_t u) { return qs ? u : qm - u; };
+    const int64_t p0 = tr * kFt + ty * 8, q0 = tc * kFt + (wv & 1) * 32 + tx * 4;
+    int32_t pi[8], qi[4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) pi[i] = (int32_t)min<int64_t>(p0 + i, last_row);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) qi[j] = (int32_t)min<int64_t>(q0 + j, last_row);
+    const int32_t Jv = table_intervals(bound, delta, J);
+    const bool dbuf = 2 * Jv <= kLdsTable;
     const bool rejected = seeds_rejected(flags);
-    const int32_t te = rejected ? t0 : t1;
-    for (int64_t k = (int64_t)blockIdx.x * 2 + half; k < ntiles; k += (int64_t)gridDim.x * 2) {
-        int64_t tr, tc;
-        bool ns;
-        fisher_tile(k, nT, nside > 0, tr, tc, ns);
-        const uint32_t qm = ns ? kDelayMirror : 0u, qs = ns ? 0u : 1u;
-        auto ucol = [qm, qs](uint32_t u) { return qs ? u : qm - u; };
-        int32_t pi[4], qi[4];
-        bool pv[4], qv[4];
+    const int32_t ntu = rejected ? 0 : nt;
+    // rows and columns past the matrix (or an idle wave) weigh zero
+    const float pw = active ? 1.0f : 0.0f;
+    float acc[8][4] = {};
+    float gp[8], gq[4];
+    uint32_t up[8], uq[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t p = tr * kFt + ty * 4 + i, q = tc * kFt + tx * 4 + i;
-            pv[i] = p < nrow;
-            qv[i] = q < nrow;
-            pi[i] = (int32_t)(pv[i] ? p : last_row);
-            qi[i] = (int32_t)(qv[i] ? q : last_row);
+    for (int i = 0; i < 8; ++i) {
+        gp[i] = p0 + i < nrow ? pw * gamma[pi[i]] : 0.0f;
+        up[i] = U[pi[i]];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        gq[j] = q0 + j < nrow ? gamma[qi[j]] : 0.0f;
+        uq[j] = ucol(U[qi[j]]);
+    }
+    // segments per stage: as many tables as one buffer holds
+    const int32_t g = (dbuf ? kLdsTable / 2 : kLdsTable) / Jv;
+    if (ntu > 0) copy_tables_lds(cub, J, Jv, 0, min(g, nt), tab);
+    for (int32_t s0 = 0; s0 < ntu; s0 += g) {
+        const int32_t st = s0 / g, s1 = min(s0 + g, nt);
+        float4 *cur = tab;
+        if (dbuf) {
+            cur = tab + (st & 1) * (kLdsTable / 2);
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);  // this stage's tables have landed (this lane's share)
+            __syncthreads();                        // ... every lane's; the previous stage is no longer read
+            if (s1 < nt) copy_tables_lds(cub, J, Jv, s1, min(g, nt - s1), tab + ((st + 1) & 1) * (kLdsTable / 2));
+        } else {
+            if (s0 > 0) {
+                __syncthreads();  // the previous stage is no longer read
+                copy_tables_lds(cub, J, Jv, s0, s1 - s0, tab);
+            }
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            __syncthreads();
         }
-        float4 *ak = acc + ((size_t)k * 256 + lt) * 4;
-        float acs[4][4];
+        for (int32_t t = s0; t < s1; ++t) {
+            // next segment's inputs (the last iteration re-reads segment nt - 1)
+            const int64_t o = (int64_t)min(t + 1, nt - 1) * npix;
+            float gpn[8], gqn[4];
+            uint32_t upn[8], uqn[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float4 v = first ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : ak[i];
-            acs[i][0] = v.x;
-            acs[i][1] = v.y;
-            acs[i][2] = v.z;
-            acs[i][3] = v.w;
-        }
-        float gp[4], gq[4];
-        uint32_t up[4], uq[4];
-        const int64_t o0 = (int64_t)t0 * npix;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            gp[i] = pv[i] ? gamma[o0 + pi[i]] : 0.0f;
-            up[i] = U[o0 + pi[i]];
-            gq[i] = qv[i] ? gamma[o0 + qi[i]] : 0.0f;
-            uq[i] = ucol(U[o0 + qi[i]]);
-        }
-        for (int32_t t = t0; t < te; ++t) {
-            // next segment's inputs (the last iteration re-reads segment t1 - 1)
-            const int64_t o = (int64_t)min(t + 1, t1 - 1) * npix;
-            float gpn[4], gqn[4];
-            uint32_t upn[4], uqn[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < 8; ++i) {
                 gpn[i] = gamma[o + pi[i]];
                 upn[i] = U[o + pi[i]];
-                gqn[i] = gamma[o + qi[i]];
-                uqn[i] = U[o + qi[i]];
             }
-            const char *ts = tb + (size_t)(t - t0) * J * sizeof(float4);
-            float4 c[4][4];
-            float x[4][4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                gqn[j] = gamma[o + qi[j]];
+                uqn[j] = U[o + qi[j]];
+            }
+            const char *tb = reinterpret_cast<const char *>(cur + (size_t)(t - s0) * Jv);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                float4 c[4];
+                float x[4];
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     const uint32_t d = abs_diff(up[i], uq[jj]);
-                    c[i][jj] = *reinterpret_cast<const float4 *>(ts + ((d >> fb) << 4));
-                    x[i][jj] = __uint_as_float(((d << (23 - fb)) & 0x007fffffu) | 0x3f800000u);
+                    c[jj] = *reinterpret_cast<const float4 *>(tb + ((d >> fb) << 4));
+                    x[jj] = __uint_as_float(((d << (23 - fb)) & 0x007fffffu) | 0x3f800000u);
                 }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
-                    const float4 cc = c[i][jj];
-                    const float W = fmaf(fmaf(fmaf(cc.w, x[i][jj], cc.z), x[i][jj], cc.y), x[i][jj], cc.x);
-                    acs[i][jj] = fmaf(gp[i] * gq[jj], W, acs[i][jj]);
+                    const float4 cc = c[jj];
+                    const float W = fmaf(fmaf(fmaf(cc.w, x[jj], cc.z), x[jj], cc.y), x[jj], cc.x);
+                    acc[i][jj] = fmaf(gp[i] * gq[jj], W, acc[i][jj]);
                 }
+            }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                gp[i] = pv[i] ? gpn[i] : 0.0f;
+            for (int i = 0; i < 8; ++i) {
+                gp[i] = p0 + i < nrow ? pw * gpn[i] : 0.0f;
                 up[i] = upn[i];
-                gq[i] = qv[i] ? gqn[i] : 0.0f;
-                uq[i] = ucol(uqn[i]);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                gq[j] = q0 + j < nrow ? gqn[j] : 0.0f;
+                uq[j] = ucol(uqn[j]);
             }
         }
-        if (!last) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ak[i] = make_float4(acs[i][0], acs[i][1], acs[i][2], acs[i][3]);
-            continue;
-        }
-        if (rejected) {  // the matrix is NaN
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) acs[i][jj] = __builtin_nanf("");
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const int64_t p = tr * kFt + ty * 4 + i, q = tc * kFt + tx * 4 + jj;
-                if (pv[i] && q < nrow && (tr != tc || p <= q)) store_value(G, npix, nside, ns, p, q, acs[i][jj], 0);
-            }
     }
+    if (!active) return;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int64_t p = p0 + i, q = q0 + jj;
+            // rejected seeds: the matrix is NaN
+            const float v = rejected ? __builtin_nanf("") : acc[i][jj];
+            if (p < nrow && q < nrow && (tr != tc || p <= q)) store_value(G, npix, nside, ns, p, q, v, 0);
+        }
 }
 
 bool fisher_full_band_ok(double f_max)
@@ -698,8 +831,8 @@ hipError_t launch_fisher_full(const float *a, const float *b, int32_t rank, cons
         const float *ar = a + (int64_t)r * nt, *br = b + (int64_t)r * nf;
         hipLaunchKernelGGL(delay_table_kernel, dim3((unsigned)((J + 1 + 255) / 256), (unsigned)nchunk), dim3(256), 0,
                            s, H, br, clo, chi, f0, df, k0, delta, J, part);
-        hipLaunchKernelGGL(delay_cubic_kernel, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, s, part, nchunk,
-                           (int64_t)J + 1, J, cub);
+        hipLaunchKernelGGL(delay_cubic_kernel, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, s, part, nchunk, J,
+                           cub);
         if (lds) {
             const int64_t grid = std::min<int64_t>(cus, (ntiles + 1) / 2);
             hipLaunchKernelGGL(fisher_full_lds_kernel, dim3((unsigned)grid), dim3(512), 0, s, ar, gamma, U, nt, npix,
@@ -714,9 +847,9 @@ hipError_t launch_fisher_full(const float *a, const float *b, int32_t rank, cons
 
 // ---- general weights: workspace layout and launch ----
 struct GeneralLayout {
-    int32_t J = 0, fb = 0, nsplit = 1, split_bins = 0, seg_per_pass = 0;
+    int32_t J = 0, fb = 0;
     int64_t ntiles = 0;
-    size_t part = 0, cub = 0, U = 0, flags = 0, acc = 0, total = 0;  // byte offsets (total: size)
+    size_t part = 0, cub = 0, U = 0, flags = 0, bound = 0, total = 0;  // byte offsets (total: size)
 };
 
 static GeneralLayout general_layout(double f_max, int32_t nbins, int32_t nt, int32_t npix, int64_t nside)
@@ -724,26 +857,20 @@ static GeneralLayout general_layout(double f_max, int32_t nbins, int32_t nt, int
     GeneralLayout L;
     double delta;
     fisher_table_geometry(f_max, &delta, &L.J, &L.fb);
-    L.nsplit = general_table_splits(L.J, nt, nbins);
-    const int32_t nchunk = (nbins + kTgK - 1) / kTgK;
-    L.split_bins = ((nchunk + L.nsplit - 1) / L.nsplit) * kTgK;
-    L.nsplit = (nbins + L.split_bins - 1) / L.split_bins;
     const int64_t nrow = nside > 0 ? npix / 2 : npix;
     const int64_t nT = (nrow + kFt - 1) / kFt;
     L.ntiles = (nside > 0 ? 2 : 1) * (nT * (nT + 1) / 2);
-    L.seg_per_pass = L.J <= kLdsTable ? kLdsTable / L.J : 0;
     size_t o = 0;
     L.part = o;
-    o += up256((size_t)L.nsplit * nt * (L.J + 1) * sizeof(double2));
+    o += up256((size_t)table_split_cap(nbins) * nt * (L.J + 1) * sizeof(double2));
     L.cub = o;
     o += up256((size_t)nt * L.J * sizeof(float4));
     L.U = o;
     o += up256((size_t)nt * npix * sizeof(uint32_t));
     L.flags = o;
     o += up256(kSymParts * sizeof(double));
-    L.acc = o;
-    // running sums between passes of the LDS form (none if one pass holds every segment)
-    if (L.seg_per_pass > 0 && L.seg_per_pass < nt) o += (size_t)L.ntiles * kFt * kFt * sizeof(float);
+    L.bound = o;
+    o += 256;
     L.total = o;
     return L;
 }
@@ -768,6 +895,7 @@ hipError_t launch_fisher_full_general(const float *w, int64_t ldw, const float *
     double2 *part = reinterpret_cast<double2 *>(base + L.part);
     float4 *cub = reinterpret_cast<float4 *>(base + L.cub);
     uint32_t *U = reinterpret_cast<uint32_t *>(base + L.U);
+    unsigned long long *bound = reinterpret_cast<unsigned long long *>(base + L.bound);
     double *flags = nullptr;
     if (nside > 0) {
         flags = reinterpret_cast<double *>(base + L.flags);
@@ -775,30 +903,26 @@ hipError_t launch_fisher_full_general(const float *w, int64_t ldw, const float *
         if (e != hipSuccess) return e;
     }
     const int64_t n = (int64_t)nt * npix;
+    hipLaunchKernelGGL(delay_bound_init_kernel, dim3(1), dim3(64), 0, s, bound);
+    hipLaunchKernelGGL(delay_bound_kernel, dim3((unsigned)std::min<int64_t>(2048, (n + 255) / 256)), dim3(256), 0,
+                       s, tau, n, bound);
     hipLaunchKernelGGL(fixed_delay_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tau, n,
                        std::ldexp(1.0, fb) / delta, U);
-    hipLaunchKernelGGL(delay_table_gemm_kernel,
-                       dim3((unsigned)((J + 1 + kTgN - 1) / kTgN), (unsigned)((nt + kTgM - 1) / kTgM),
-                            (unsigned)L.nsplit),
-                       dim3(256), 0, s, w, ldw, H, nt, clo, chi, L.split_bins, f0, df, k0, delta, J, part);
-    hipLaunchKernelGGL(delay_cubic_kernel, dim3((unsigned)((J + 255) / 256), (unsigned)nt), dim3(256), 0, s, part,
-                       L.nsplit, (int64_t)nt * (J + 1), J, cub);
-    const bool lds = L.seg_per_pass > 0 && fisher_full_table_in_lds();
-    if (!lds) {
-        hipLaunchKernelGGL(fisher_full_kernel, dim3((unsigned)L.ntiles), dim3(256), 0, s, (const float *)nullptr,
-                           gamma, U, nt, npix, nside, flags, cub, (int64_t)J, fb, (int32_t)0, G);
-        return hipGetLastError();
-    }
     int cus = 256, dev = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-    const int64_t grid = std::min<int64_t>(cus, (L.ntiles + 1) / 2);
-    float4 *acc = reinterpret_cast<float4 *>(base + L.acc);
-    for (int32_t t0 = 0; t0 < nt; t0 += L.seg_per_pass) {
-        const int32_t t1 = std::min(nt, t0 + L.seg_per_pass);
-        hipLaunchKernelGGL(fisher_full_seg_lds_kernel, dim3((unsigned)grid), dim3(512), 0, s, gamma, U, nt, npix,
-                           nside, flags, cub, J, fb, t0, t1, L.ntiles, (int32_t)(t0 == 0), (int32_t)(t1 == nt), acc,
-                           G);
+    // persistent: two workgroups per compute unit (their registers allow two)
+    hipLaunchKernelGGL(delay_table_gemm_kernel, dim3((unsigned)(2 * cus)), dim3(256), 0, s, w, ldw, H, nt, clo, chi, f0,
+                       df, k0, delta, J, (const unsigned long long *)bound, part);
+    hipLaunchKernelGGL(delay_cubic_general_kernel, dim3((unsigned)((J + 255) / 256), (unsigned)nt), dim3(256), 0, s,
+                       part, nt, nbins, J, (const unsigned long long *)bound, delta, cub);
+    if (J <= kLdsTable && fisher_full_table_in_lds()) {
+        const int64_t grid = (L.ntiles + kStTiles - 1) / kStTiles;
+        hipLaunchKernelGGL(fisher_full_stream_kernel, dim3((unsigned)grid), dim3(kStWaves * 64), 0, s, gamma, U, nt,
+                           npix, nside, flags, cub, J, (const unsigned long long *)bound, delta, fb, L.ntiles, G);
+    } else {
+        hipLaunchKernelGGL(fisher_full_kernel, dim3((unsigned)L.ntiles), dim3(256), 0, s, (const float *)nullptr,
+                           gamma, U, nt, npix, nside, flags, cub, (int64_t)J, fb, (int32_t)0, G);
     }
     return hipGetLastError();
 }

@@ -198,14 +198,15 @@ def test_fisher_full_general_validation_on_the_host():
     # workspace too small, or misaligned
     assert F(d, 10, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, 0, d, d, 256, None) == -2
     assert F(d, 10, d, 10, ctypes.byref(fg), 0, 0, 10, d, d, 8, 768, 0, d, ctypes.c_void_p(260), big, None) == -1
-    # sizes: grow with the top frequency (table length) and with the segment
-    # count; the antipodal blocks hold fewer running sums; out of range -> 0
+    # sizes: grow with the top frequency (table length), the segment count and
+    # the band's bins (more bin ranges of partial sums); out of range -> 0
     W = L.sgwb_fisher_full_general_workspace_size
     low = W(ctypes.byref(fg), 0, 0, 10, 8, 768, 0)
     high = W(ctypes.byref(fg), 50000, 0, 10, 8, 768, 0)
     more = W(ctypes.byref(fg), 50000, 0, 10, 9, 768, 0)
     assert 0 < low < high < more
-    assert W(ctypes.byref(fg), 50000, 0, 10, 64, 768, 1) < W(ctypes.byref(fg), 50000, 0, 10, 64, 768, 0)
+    assert W(ctypes.byref(fg), 50000, 0, 10, 9, 768, 0) < W(ctypes.byref(fg), 50000, 0, 4096, 9, 768, 0)
+    assert W(ctypes.byref(fg), 50000, 0, 10, 64, 768, 1) == W(ctypes.byref(fg), 50000, 0, 10, 64, 768, 0)
     bad = sg._FGrid(20.0, 0.0)
     assert W(ctypes.byref(bad), 0, 0, 10, 8, 768, 0) == 0
     assert W(ctypes.byref(fg), 32 * 30000, 0, 10, 8, 768, 0) == 0

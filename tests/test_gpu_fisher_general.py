@@ -16,8 +16,6 @@ the segments (~ sqrt(nt) 6e-8 S); the tables' float64 band sums add nothing
 visible.  G(p,q) depends only on pixels p and q, so where the whole oracle
 matrix is slow it is evaluated on a sampled pixel subset.
 """
-import os
-
 import numpy as np
 import pytest
 
@@ -29,12 +27,14 @@ pytestmark = pytest.mark.gpu
 
 F0 = 20.0
 CASES = [  # baseline, nside, npix used (None: all), nt, k0, nf, band, df, antipodal
-    ("AB", 2, None, 24, 10, 40, (0, 40), 0.25, False),        # 32 Hz: every table in one pass, one ragged tile
-    ("AC", 4, None, 40, 4000, 64, (5, 60), 0.25, False),      # 1.0 kHz: 3 tables a pass, 14 passes (last ragged)
+    ("AB", 2, None, 24, 10, 40, (0, 40), 0.25, False),        # 32 Hz: short tables, one ragged tile
+    ("AC", 4, None, 40, 4000, 64, (5, 60), 0.25, False),      # 1.0 kHz, AC: tables double-buffered
     ("BC", 4, 150, 33, 0, 30, (0, 30), 1.0, False),           # ragged multi-tile pixels (150 = 2 x 64 + 22)
-    ("AB", 8, None, 60, 53000, 64, (0, 64), 1 / 32, False),   # 1.68 kHz: 2 tables a pass, 12 x 12 tiles
+    ("AB", 8, None, 60, 53000, 64, (0, 64), 1 / 32, False),   # 1.68 kHz, 12 x 12 tiles
     ("AB", 4, 100, 30, 79000, 40, (0, 40), 1 / 32, False),    # 2.49 kHz: tables above the LDS, global-memory form
-    ("AC", 4, None, 40, 4000, 64, (5, 60), 0.25, True),       # antipodal blocks, multi-pass
+    ("AC", 4, None, 40, 4000, 64, (5, 60), 0.25, True),       # antipodal blocks, double-buffered tables
+    ("AD", 4, None, 30, 53000, 64, (0, 64), 1 / 32, False),   # 39 ms delays at 1.68 kHz: one table buffer
+    ("AD", 4, None, 30, 53000, 64, (0, 64), 1 / 32, True),    # the same, antipodal
     ("AB", 8, None, 60, 53000, 64, (0, 64), 1 / 32, True),    # antipodal, 1.68 kHz
     ("BC", 2, None, 20, 39000, 50, (3, 47), 0.125, True),     # antipodal, 4.9 kHz global-memory form
     ("AC", 2, None, 7, 63, 2, (1, 2), 0.25, False),           # single bin, tiny day
@@ -96,10 +96,10 @@ def test_fisher_full_general_vs_oracle(sg, oracle_mod, case):
 
 
 def test_fisher_full_general_full_day(sg, oracle_mod):
-    """A whole day (898 segments) at the top of the band (1.67-1.68 kHz, tables of
-    4566 intervals, two per pass: 449 passes over the running sums), nside 16
-    with the antipodal blocks; sampled pixels (with their antipodes) against the
-    oracle."""
+    """A whole day (898 segments) at the top of the band (1.67-1.68 kHz; the
+    baseline's 10 ms delays reach 2.15e3 of the 9.1e3 table intervals, streamed
+    double-buffered), nside 16 with the antipodal blocks; sampled pixels (with
+    their antipodes) against the oracle."""
     nt, nside, k0, nf, df = 898, 16, 52900, 512, 1 / 32
     g, t, w, H = _inputs(sg, "AB", nside, None, nt, k0, nf, df, 42)
     wd, Hd = torch.from_numpy(w).cuda(), torch.from_numpy(H).cuda()
@@ -119,18 +119,20 @@ def test_fisher_full_general_full_day(sg, oracle_mod):
 
 
 def test_fisher_full_general_lds_and_global_forms_agree_bitwise(sg, monkeypatch):
-    """The multi-pass LDS form and the one-launch global-memory form add the same
-    float32 terms in the same segment order: the same bits."""
-    nt, nside, k0, nf, df = 40, 4, 4000, 64, 0.25
-    g, t, w, H = _inputs(sg, "AC", nside, None, nt, k0, nf, df, 43)
-    wd, Hd = torch.from_numpy(w).cuda(), torch.from_numpy(H).cuda()
-    for anti in (False, True):
-        G1 = sg.fisher_full_general(wd, Hd, sg.FGrid(F0, df), k0, 2, nf, g, t, antipodal=anti)
-        monkeypatch.setenv("SGWB_FISHER_TABLE", "global")
-        G2 = sg.fisher_full_general(wd, Hd, sg.FGrid(F0, df), k0, 2, nf, g, t, antipodal=anti)
-        monkeypatch.delenv("SGWB_FISHER_TABLE")
-        torch.cuda.synchronize()
-        assert torch.equal(G1, G2)
+    """The streaming LDS form (double-buffered tables for AC at 1 kHz, one buffer
+    for AD at 1.68 kHz) and the global-memory form add the same float32 terms in
+    the same segment order: the same bits."""
+    for bl, k0, df in (("AC", 4000, 0.25), ("AD", 53000, 1 / 32)):
+        nt, nside, nf = 40, 4, 64
+        g, t, w, H = _inputs(sg, bl, nside, None, nt, k0, nf, df, 43)
+        wd, Hd = torch.from_numpy(w).cuda(), torch.from_numpy(H).cuda()
+        for anti in (False, True):
+            G1 = sg.fisher_full_general(wd, Hd, sg.FGrid(F0, df), k0, 2, nf, g, t, antipodal=anti)
+            monkeypatch.setenv("SGWB_FISHER_TABLE", "global")
+            G2 = sg.fisher_full_general(wd, Hd, sg.FGrid(F0, df), k0, 2, nf, g, t, antipodal=anti)
+            monkeypatch.delenv("SGWB_FISHER_TABLE")
+            torch.cuda.synchronize()
+            assert torch.equal(G1, G2)
 
 
 def test_fisher_full_general_equals_separable_path_for_rank_one(sg):
@@ -213,8 +215,8 @@ def test_fisher_full_general_noise_free_sky_gives_x_equal_g_p(sg):
 
 def test_fisher_full_general_rejects_broken_seeds(sg):
     """Antipodal flag with a delay changed at one pixel of the middle segment:
-    the device check rejects the seeds and the matrix is NaN (multi-pass form:
-    every pass skips its segments and the last writes NaN)."""
+    the device check rejects the seeds and the matrix is NaN (the streaming
+    form skips every segment and writes NaN)."""
     nt, nside, k0, nf, df = 20, 4, 4000, 32, 0.25
     g, t, w, H = _inputs(sg, "AB", nside, None, nt, k0, nf, df, 49)
     t = t.clone()
