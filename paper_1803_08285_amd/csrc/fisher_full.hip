@@ -303,7 +303,8 @@ __global__ __launch_bounds__(256) void delay_table_gemm_kernel(const float *__re
 }
 
 // Cubic of interval j < Jv of segment blockIdx.y's table, from the bin ranges'
-// partial sums (range order fixed).
+// partial sums (range order fixed).  Tables are stored back to back, Jv
+// intervals each (segment t's at cub + t Jv).
 __global__ __launch_bounds__(256) void delay_cubic_general_kernel(const double2 *__restrict__ part, int32_t nt,
                                                                   int32_t nbins, int32_t J,
                                                                   const unsigned long long *__restrict__ bound,
@@ -323,7 +324,7 @@ __global__ __launch_bounds__(256) void delay_cubic_general_kernel(const double2 
         b.x += v.x;
         b.y += v.y;
     }
-    cub[(size_t)blockIdx.y * J + j] = hermite_cubic(a, b);
+    cub[(size_t)blockIdx.y * Jv + j] = hermite_cubic(a, b);
 }
 
 // Delays as biased fixed-point table coordinates: U = round(tau / delta 2^fb) + 2^30,
@@ -411,15 +412,18 @@ __device__ __forceinline__ uint32_t abs_diff(uint32_t x, uint32_t y)
 // G tile (r, c) of the upper triangle; 256 threads, 4 x 4 entries each.  Per
 // (t, p, q): |U_p - U_q| gives the table interval (high bits) and the position
 // in it (low fb bits, placed in the mantissa of x in [1, 2)); three FMAs
-// evaluate the cubic, two more weight and accumulate it.  Segment t reads the
-// table at cub + t seg_stride (0: one table for all, weighted by a[t]; J: one
-// table per segment, a null).
+// evaluate the cubic, two more weight and accumulate it.  With weights a[t],
+// one table for all segments; with a null, one table per segment, Jv
+// intervals each, back to back (Jv from the seeds' delay bound).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void fisher_full_kernel(const float *__restrict__ a, const float *__restrict__ gamma,
                                                           const uint32_t *__restrict__ U, int32_t nt, int32_t npix,
                                                           int64_t nside, const double *__restrict__ flags,
-                                                          const float4 *__restrict__ cub, int64_t seg_stride,
-                                                          int32_t fb, int32_t accumulate, float *__restrict__ G)
+                                                          const float4 *__restrict__ cub, int32_t J,
+                                                          const unsigned long long *__restrict__ bound,
+                                                          double delta, int32_t fb, int32_t accumulate,
+                                                          float *__restrict__ G)
 {
+    const int64_t seg_stride = a ? 0 : table_intervals(bound, delta, J);
     __shared__ float gP[kFtSeg][kFt], gQ[kFtSeg][kFt];
     __shared__ uint32_t uP[kFtSeg][kFt], uQ[kFtSeg][kFt];
     const int64_t nrow = nside > 0 ? npix / 2 : npix;  // rows and columns of the computed blocks
@@ -619,19 +623,22 @@ __global__ __launch_bounds__(512) void fisher_full_lds_kernel(const float *__res
 constexpr int kStTiles = 4;
 constexpr int kStWaves = 2 * kStTiles;  // 512 threads
 
-// Tables of segments s0 .. s0 + ns - 1 (their first Jv intervals; table t at
-// cub + t J) into LDS back to back, 16 bytes a lane straight from global
+// n float4 from src into LDS at dst, 16 bytes a lane straight from global
 // memory; lane l of a wave writes the l-th 16 bytes after the wave's base.
-__device__ __forceinline__ void copy_tables_lds(const float4 *__restrict__ cub, int32_t J, int32_t Jv, int32_t s0,
-                                                int32_t ns, float4 *dst)
+__device__ __forceinline__ void copy_lds(const float4 *__restrict__ src, float4 *dst, int32_t n)
 {
     const int lane = threadIdx.x & 63;
-    const int32_t n = ns * Jv;
-    for (int32_t e = threadIdx.x; e < n; e += kStWaves * 64) {
-        const int32_t sg = e / Jv, i = e - sg * Jv;
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const char *>(cub + (size_t)(s0 + sg) * J + i),
-                                         dst + (e - lane), 16, 0, 0);
-    }
+    const char *base = reinterpret_cast<const char *>(src);
+    for (int32_t e = threadIdx.x; e < n; e += kStWaves * 64)
+        __builtin_amdgcn_global_load_lds(base + (size_t)e * sizeof(float4), dst + (e - lane), 16, 0, 0);
+}
+
+// Buffer resource over one segment's npix 4-byte seeds (raw loads at byte
+// offsets; out-of-range offsets read 0).  0x00020000: the gfx9 descriptor word
+// for plain 32-bit raw access.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t seg_rsrc(const void *p, int32_t npix)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, npix * 4, 0x00020000);
 }
 
 __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__restrict__ gamma,
@@ -647,7 +654,7 @@ __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int ty = lane >> 3, tx = lane & 7;
     const int64_t nrow = nside > 0 ? npix / 2 : npix;
-    const int32_t last_row = (int32_t)nrow - 1;
+    const int64_t last_row = nrow - 1;
     const int64_t nT = (nrow + kFt - 1) / kFt;
     const int64_t k = (int64_t)blockIdx.x * kStTiles + (wv >> 1);
     const bool active = k < ntiles;
@@ -657,33 +664,37 @@ __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__
     const uint32_t qm = ns ? kDelayMirror : 0u, qs = ns ? 0u : 1u;
     auto ucol = [qm, qs](uint32_t u) { return qs ? u : qm - u; };
     const int64_t p0 = tr * kFt + ty * 8, q0 = tc * kFt + (wv & 1) * 32 + tx * 4;
-    int32_t pi[8], qi[4];
+    // byte offsets of the lane's rows and columns within a segment's seeds
+    // (clamped into the matrix: entries past it are computed but never stored,
+    // as are those of an idle wave)
+    uint32_t po[8], qo[4];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) pi[i] = (int32_t)min<int64_t>(p0 + i, last_row);
+    for (int i = 0; i < 8; ++i) po[i] = (uint32_t)min(p0 + i, last_row) * 4u;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) qi[j] = (int32_t)min<int64_t>(q0 + j, last_row);
+    for (int j = 0; j < 4; ++j) qo[j] = (uint32_t)min(q0 + j, last_row) * 4u;
     const int32_t Jv = table_intervals(bound, delta, J);
     const bool dbuf = 2 * Jv <= kLdsTable;
     const bool rejected = seeds_rejected(flags);
     const int32_t ntu = rejected ? 0 : nt;
-    // rows and columns past the matrix (or an idle wave) weigh zero
-    const float pw = active ? 1.0f : 0.0f;
     float acc[8][4] = {};
     float gp[8], gq[4];
     uint32_t up[8], uq[4];
+    {
+        const __amdgpu_buffer_rsrc_t rg = seg_rsrc(gamma, npix), ru = seg_rsrc(U, npix);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        gp[i] = p0 + i < nrow ? pw * gamma[pi[i]] : 0.0f;
-        up[i] = U[pi[i]];
-    }
+        for (int i = 0; i < 8; ++i) {
+            gp[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, po[i], 0, 0));
+            up[i] = __builtin_amdgcn_raw_buffer_load_b32(ru, po[i], 0, 0);
+        }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        gq[j] = q0 + j < nrow ? gamma[qi[j]] : 0.0f;
-        uq[j] = ucol(U[qi[j]]);
+        for (int j = 0; j < 4; ++j) {
+            gq[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, qo[j], 0, 0));
+            uq[j] = ucol(__builtin_amdgcn_raw_buffer_load_b32(ru, qo[j], 0, 0));
+        }
     }
     // segments per stage: as many tables as one buffer holds
     const int32_t g = (dbuf ? kLdsTable / 2 : kLdsTable) / Jv;
-    if (ntu > 0) copy_tables_lds(cub, J, Jv, 0, min(g, nt), tab);
+    if (ntu > 0) copy_lds(cub, tab, min(g, nt) * Jv);
     for (int32_t s0 = 0; s0 < ntu; s0 += g) {
         const int32_t st = s0 / g, s1 = min(s0 + g, nt);
         float4 *cur = tab;
@@ -691,29 +702,31 @@ __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__
             cur = tab + (st & 1) * (kLdsTable / 2);
             __builtin_amdgcn_s_waitcnt(kWaitVm0);  // this stage's tables have landed (this lane's share)
             __syncthreads();                        // ... every lane's; the previous stage is no longer read
-            if (s1 < nt) copy_tables_lds(cub, J, Jv, s1, min(g, nt - s1), tab + ((st + 1) & 1) * (kLdsTable / 2));
+            if (s1 < nt)
+                copy_lds(cub + (size_t)s1 * Jv, tab + ((st + 1) & 1) * (kLdsTable / 2), min(g, nt - s1) * Jv);
         } else {
             if (s0 > 0) {
                 __syncthreads();  // the previous stage is no longer read
-                copy_tables_lds(cub, J, Jv, s0, s1 - s0, tab);
+                copy_lds(cub + (size_t)s0 * Jv, tab, (s1 - s0) * Jv);
             }
             __builtin_amdgcn_s_waitcnt(kWaitVm0);
             __syncthreads();
         }
         for (int32_t t = s0; t < s1; ++t) {
             // next segment's inputs (the last iteration re-reads segment nt - 1)
-            const int64_t o = (int64_t)min(t + 1, nt - 1) * npix;
+            const size_t o = (size_t)min(t + 1, nt - 1) * (size_t)npix;
+            const __amdgpu_buffer_rsrc_t rg = seg_rsrc(gamma + o, npix), ru = seg_rsrc(U + o, npix);
             float gpn[8], gqn[4];
             uint32_t upn[8], uqn[4];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                gpn[i] = gamma[o + pi[i]];
-                upn[i] = U[o + pi[i]];
+                gpn[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, po[i], 0, 0));
+                upn[i] = __builtin_amdgcn_raw_buffer_load_b32(ru, po[i], 0, 0);
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                gqn[j] = gamma[o + qi[j]];
-                uqn[j] = U[o + qi[j]];
+                gqn[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, qo[j], 0, 0));
+                uqn[j] = __builtin_amdgcn_raw_buffer_load_b32(ru, qo[j], 0, 0);
             }
             const char *tb = reinterpret_cast<const char *>(cur + (size_t)(t - s0) * Jv);
 #pragma unroll
@@ -735,12 +748,12 @@ __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                gp[i] = p0 + i < nrow ? pw * gpn[i] : 0.0f;
+                gp[i] = gpn[i];
                 up[i] = upn[i];
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                gq[j] = q0 + j < nrow ? gqn[j] : 0.0f;
+                gq[j] = gqn[j];
                 uq[j] = ucol(uqn[j]);
             }
         }
@@ -839,7 +852,8 @@ hipError_t launch_fisher_full(const float *a, const float *b, int32_t rank, cons
                                nside, flags, cub, J, fb, ntiles, (int32_t)(r > 0), G);
         } else {
             hipLaunchKernelGGL(fisher_full_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, ar, gamma, U, nt, npix,
-                               nside, flags, cub, (int64_t)0, fb, (int32_t)(r > 0), G);
+                               nside, flags, cub, J, (const unsigned long long *)nullptr, delta, fb, (int32_t)(r > 0),
+                               G);
         }
     }
     return hipGetLastError();
@@ -922,7 +936,8 @@ hipError_t launch_fisher_full_general(const float *w, int64_t ldw, const float *
                            npix, nside, flags, cub, J, (const unsigned long long *)bound, delta, fb, L.ntiles, G);
     } else {
         hipLaunchKernelGGL(fisher_full_kernel, dim3((unsigned)L.ntiles), dim3(256), 0, s, (const float *)nullptr,
-                           gamma, U, nt, npix, nside, flags, cub, (int64_t)J, fb, (int32_t)0, G);
+                           gamma, U, nt, npix, nside, flags, cub, J, (const unsigned long long *)bound, delta, fb,
+                           (int32_t)0, G);
     }
     return hipGetLastError();
 }
