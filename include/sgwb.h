@@ -290,9 +290,11 @@ int sgwb_fisher_full(const float *a, const float *b, int32_t rank, const float *
  * fail give G = NaN).
  * Output: G float32 [npix][npix] row-major, symmetric (overwritten).
  * Arithmetic: one table Wd_t per segment on the grid of sgwb_fisher_full, its
- * values and derivatives summed over the band's bins in float64 on the matrix
- * cores (a product of the [nt][nbins] weights with cosines and sines generated
- * in float64), then the same float32 cubic interpolants, fixed-point delays
+ * values and derivatives summed over the band in float64 on the matrix cores:
+ * over the bins (weights times generated cosines and sines) on grids coarser
+ * than 1/8 Hz, else over Jacobi-Anger moments of 16- to 64-bin strips (eight
+ * terms, truncation below 1.6e-9 of sum |H w|); then the same float32 cubic
+ * interpolants, fixed-point delays
  * and float32 accumulation over t; same tolerance.  The tables stop at the
  * largest delay difference the seeds can have, 2 max|tau| (found on the
  * device; |x_A - x_B| / c for seeds of sgwb_build_geometry), not at the
@@ -301,9 +303,9 @@ int sgwb_fisher_full(const float *a, const float *b, int32_t rank, const float *
  * segments; above, the tables are read from global memory.
  * Workspace: at least sgwb_fisher_full_general_workspace_size() bytes (0 for
  * arguments out of range), 256-byte aligned, owned by the caller: the tables
- * and the partial sums of their band sums, sized for the Earth bound (about
- * 0.75 MB per segment for the full 20-1726 Hz band), and the fixed-point
- * delays (4 bytes per seed).
+ * and the partial sums of their band sums, sized for the Earth bound, and the
+ * strip moments (about 0.86 MB per segment for the full 20-1726 Hz band at
+ * 1/32 Hz), and the fixed-point delays (4 bytes per seed).
  * Errors: SGWB_EINVAL (null pointer, nt/nf/npix out of range, ldw < nf, band
  * out of range or reaching above 24 kHz, bad grid, unknown flag bits or the
  * antipodal flag with a non-HEALPix npix, misaligned pointer, more than

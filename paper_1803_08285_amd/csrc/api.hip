@@ -479,8 +479,7 @@ size_t sgwb_fisher_full_general_workspace_size(const sgwb_fgrid *fg, int64_t k0,
 {
     int64_t nside = 0;
     if (!fg || check_fisher_general(fg, k0, clo, chi, chi, nt, npix, flags, &nside)) return 0;
-    return fisher_full_general_workspace_bytes(fg->f0_hz + (double)(k0 + chi - 1) * fg->df_hz, chi - clo, nt, npix,
-                                               nside);
+    return fisher_full_general_workspace_bytes(fg->f0_hz, fg->df_hz, k0, clo, chi, nt, npix, nside);
 }
 
 int sgwb_fisher_full_general(const float *w, int64_t ldw, const float *H, int32_t nf, const sgwb_fgrid *fg,

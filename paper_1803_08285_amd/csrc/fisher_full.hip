@@ -163,103 +163,237 @@ __global__ __launch_bounds__(256) void delay_cubic_kernel(const double2 *__restr
 // segment,
 //   Wd_t(D_j) = sum_{c in band} H_c w(t,c) cos 2 pi f_c D_j,   delta Wd_t'(D_j),
 // for every segment t and grid point j <= Jv (the points the seeds' delay
-// bound can reach) at once.  That is a dense contraction over the band's bins,
-// [nt x nbins] . [nbins x (Jv + 1)], twice (cosine and sine), so it runs on the
-// float64 matrix cores (v_mfma_f64_16x16x4): per work item a 64-segment x
-// 64-point tile over one range of the bins, the cosine / sine operand of each
-// 32-bin chunk generated into LDS (a float64 phase reduced exactly at the
-// chunk's first bin of each 8, then advanced by a float64 rotation), the
-// weight operand H_c w(t,c) (and -2 pi delta f_c times it for the derivative)
-// built in registers from w.  Workgroups walk the items persistently; the
-// bins split into as many ranges as fill the chip (their count, like Jv, is
-// worked out on the device), whose float64 partial sums
-// delay_cubic_general_kernel adds in a fixed order.
+// bound can reach) at once.  That is a dense contraction, run on the float64
+// matrix cores (v_mfma_f64_16x16x4), in one of two bases:
+//  * direct: over the band's bins, [nt x nbins] . [nbins x (Jv + 1)], twice
+//    (cosine and sine), the weight operand H_c w(t,c) (and -2 pi delta f_c
+//    times it for the derivative) built in registers from w;
+//  * expanded: per strip of S bins (S >= 16, aligned to the absolute grid, f_c
+//    = f_s + s_c (S - 1) df / 2 with f_s the strip centre, s_c in [-1, 1]),
+//    the Jacobi-Anger expansion e^{i s eta} = sum_n eps_n i^n J_n(eta) T_n(s),
+//    eta = pi (S - 1) df D, turns the band sum into one over (strip, term):
+//      Wd_t(D) = sum_{s,n} mu_n(t,s) eps_n J_n(eta) Re[i^n e^{2 pi i f_s D}],
+//      delta Wd_t'(D) = -2 pi delta sum_{s,n} nu_n(t,s) eps_n J_n(eta) Im[i^n e^{2 pi i f_s D}],
+//    mu_n = sum_{c in s} H_c w(t,c) T_n(s_c), nu_n the same with H_c w(t,c) f_c
+//    (table_moments_kernel): kTxTerms terms per strip instead of S bins.  S is
+//    the widest power of two up to 64 with eta <= kTxEtaMax at the Earth bound
+//    (S = 64 at 1/32 Hz), so the dropped remainder is below 2 (eta/2)^8 / 8! =
+//    1.6e-9 of sum |H w|.
+// Per work item a 64-segment x 64-point tile over one range of K (bins, or
+// strip terms), the cosine / sine operand of each 32-deep chunk generated into
+// LDS (float64 phases reduced exactly, then advanced by float64 rotations; the
+// Bessel factors once per item), the other operand read per lane.  Workgroups
+// walk the items persistently; K splits into as many ranges as fill the chip
+// (their count, like Jv, is worked out on the device), whose float64 partial
+// sums delay_cubic_general_kernel adds in a fixed order.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTgM = 64;          // segments per tile (16 per wave)
 constexpr int kTgN = 64;          // grid points per tile (four 16-wide blocks)
-constexpr int kTgK = 32;          // bins per chunk (eight 4-deep matrix-core steps)
-constexpr int kTgSplitsMax = 16;  // bin ranges at most
+constexpr int kTgK = 32;          // K per chunk (eight 4-deep matrix-core steps)
+constexpr int kTgSplitsMax = 16;  // K ranges at most
 constexpr int kTgSplitsBuf = 4;   // partial sums held: kTgSplitsBuf x nt x (J + 1) points
 constexpr int kTgItems = 8192;    // work items aimed at
+constexpr int kTxTerms = 8;       // Jacobi-Anger terms per strip (expanded basis)
+constexpr double kTxEtaMax = 0.55;
+static_assert(kTgK % kTxTerms == 0, "a chunk holds whole strips");
 
 struct TableSplit {
-    int32_t n;     // bin ranges
-    int32_t bins;  // bins per range (a multiple of kTgK)
+    int32_t n;     // K ranges
+    int32_t bins;  // K per range (a multiple of kTgK)
 };
 
 // Partial-sum buffer of the table contraction, in tables of J + 1 points per
-// segment: kTgSplitsBuf, fewer for bands of under 16 chunks a range.
-__host__ __device__ __forceinline__ int32_t table_split_cap(int32_t nbins)
+// segment: kTgSplitsBuf, fewer for K of under 16 chunks a range.
+__host__ __device__ __forceinline__ int32_t table_split_cap(int32_t nk)
 {
-    const int32_t c = ((nbins + kTgK - 1) / kTgK) / 16;
+    const int32_t c = ((nk + kTgK - 1) / kTgK) / 16;
     return c < 1 ? 1 : (c < kTgSplitsBuf ? c : kTgSplitsBuf);
 }
 
-// Bin ranges for a table of Jv intervals: about kTgItems work items, at least
+// K ranges for a table of Jv intervals: about kTgItems work items, at least
 // 16 chunks a range (unless there is one range), at most kTgSplitsMax, and no
 // more partial sums than the buffer holds (n (Jv + 1) <= cap (J + 1)).
-__host__ __device__ __forceinline__ TableSplit table_split(int32_t Jv, int32_t J, int32_t nt, int32_t nbins)
+__host__ __device__ __forceinline__ TableSplit table_split(int32_t Jv, int32_t J, int32_t nt, int32_t nk)
 {
     const int64_t tiles = (int64_t)((Jv + 1 + kTgN - 1) / kTgN) * ((nt + kTgM - 1) / kTgM);
-    const int32_t nchunk = (nbins + kTgK - 1) / kTgK;
+    const int32_t nchunk = (nk + kTgK - 1) / kTgK;
     int64_t n = (kTgItems + tiles - 1) / tiles;
     n = n < nchunk / 16 ? n : nchunk / 16;
-    const int64_t fit = (int64_t)table_split_cap(nbins) * (J + 1) / (Jv + 1);
+    const int64_t fit = (int64_t)table_split_cap(nk) * (J + 1) / (Jv + 1);
     n = n < fit ? n : fit;
     n = n < kTgSplitsMax ? n : kTgSplitsMax;
     n = n > 1 ? n : 1;
     TableSplit r;
     r.bins = (int32_t)((nchunk + n - 1) / n) * kTgK;
-    r.n = (nbins + r.bins - 1) / r.bins;
+    r.n = (nk + r.bins - 1) / r.bins;
     return r;
 }
 
+// Strips of the expanded basis: S bins each (0: use the direct basis), the
+// first strip's index (absolute bins first S ..) and the count touching the band.
+struct StripGrid {
+    int32_t S = 0;
+    int64_t first = 0;
+    int32_t n = 0;
+};
+
+static StripGrid strip_grid(double df, int64_t k0, int32_t clo, int32_t chi)
+{
+    StripGrid g;
+    int32_t S = 64;
+    while (S >= 16 && kTwoPi * 0.5 * (S - 1) * df * 2.0 * kMaxDelay > kTxEtaMax) S >>= 1;
+    if (S < 16) return g;  // eight terms per strip would not save work
+    g.S = S;
+    const int64_t a = k0 + clo, b = k0 + chi - 1;
+    g.first = a / S;
+    g.n = (int32_t)(b / S - g.first + 1);
+    return g;
+}
+
+// Strip moments: mu_n(t,s) = sum over the strip's band bins of H_c w(t,c)
+// T_n(s_c), nu_n(t,s) the same with H_c w(t,c) f_c; [nt][nstrips kTxTerms]
+// float64, T_n by the three-term recurrence.  One thread per (segment, strip).
+__global__ __launch_bounds__(64) void table_moments_kernel(const float *__restrict__ w, int64_t ldw,
+                                                           const float *__restrict__ H, int32_t clo, int32_t chi,
+                                                           double f0, double df, int64_t k0, int32_t S, int64_t first,
+                                                           int32_t nstrips, double *__restrict__ mu,
+                                                           double *__restrict__ nu)
+{
+    const int32_t sg = blockIdx.x * 64 + threadIdx.x;
+    if (sg >= nstrips) return;
+    const int32_t t = blockIdx.y;
+    const int64_t kb = (first + sg) * S;  // absolute first bin of the strip
+    const double half = 0.5 * (S - 1);
+    const float *wr = w + (int64_t)t * ldw;
+    double m[kTxTerms], v[kTxTerms];
+#pragma unroll
+    for (int n = 0; n < kTxTerms; ++n) m[n] = v[n] = 0.0;
+    for (int32_t i = 0; i < S; ++i) {
+        const int64_t c = kb + i - k0;  // column
+        if (c < clo || c >= chi) continue;
+        const double h = (double)H[c] * (double)wr[c];
+        const double hf = h * (f0 + (double)(kb + i) * df);
+        const double s = ((double)i - half) / half;
+        double tp = 1.0, tc = s;  // T_0, T_1
+        m[0] += h;
+        v[0] += hf;
+        m[1] += h * s;
+        v[1] += hf * s;
+#pragma unroll
+        for (int n = 2; n < kTxTerms; ++n) {
+            const double tn = 2.0 * s * tc - tp;
+            tp = tc;
+            tc = tn;
+            m[n] += h * tn;
+            v[n] += hf * tn;
+        }
+    }
+    const int64_t nk = (int64_t)nstrips * kTxTerms;
+    double *mr = mu + (int64_t)t * nk + (int64_t)sg * kTxTerms, *vr = nu + (int64_t)t * nk + (int64_t)sg * kTxTerms;
+#pragma unroll
+    for (int n = 0; n < kTxTerms; ++n) {
+        mr[n] = m[n];
+        vr[n] = v[n];
+    }
+}
+
+// eps_n J_n(eta) for n < kTxTerms (power series; eta <= kTxEtaMax, 12 terms
+// leave less than 1e-17).
+__device__ __forceinline__ void bessel_eps(double eta, double (&J)[kTxTerms])
+{
+    const double x = 0.5 * eta, x2 = -x * x;
+    double lead = 1.0;  // x^n / n!
+#pragma unroll
+    for (int n = 0; n < kTxTerms; ++n) {
+        double term = lead, sum = lead;
+#pragma unroll
+        for (int k = 1; k <= 12; ++k) {
+            term *= x2 / (double)(k * (n + k));
+            sum += term;
+        }
+        J[n] = n == 0 ? sum : 2.0 * sum;
+        lead *= x / (double)(n + 1);
+    }
+}
+
+// EXP = false: A = w, H (direct basis over the bins; nk = nbins); EXP = true:
+// A = mu, nu (strip moments, nk = nstrips kTxTerms).
+template <bool EXP>
 __global__ __launch_bounds__(256) void delay_table_gemm_kernel(const float *__restrict__ w, int64_t ldw,
-                                                               const float *__restrict__ H, int32_t nt, int32_t clo,
-                                                               int32_t chi, double f0, double df, int64_t k0,
-                                                               double delta, int32_t J,
-                                                               const unsigned long long *__restrict__ bound,
+                                                               const float *__restrict__ H,
+                                                               const double *__restrict__ mu,
+                                                               const double *__restrict__ nu, int32_t nt,
+                                                               int32_t clo, int32_t nk, double f0, double df,
+                                                               int64_t k0, int32_t S, int64_t first, double delta,
+                                                               int32_t J, const unsigned long long *__restrict__ bound,
                                                                double2 *__restrict__ part)
 {
     __shared__ double bc[kTgK][kTgN], bs[kTgK][kTgN];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int kq = lane >> 4;
-    const int gj = threadIdx.x & 63, gg = threadIdx.x >> 6;  // generation: point gj, bins 8 gg .. 8 gg + 7
-    const int32_t nb = chi - clo;
+    const int gj = threadIdx.x & 63, gg = threadIdx.x >> 6;  // generation: point gj, K rows 8 gg .. 8 gg + 7
     const int32_t Jv = table_intervals(bound, delta, J);
-    const TableSplit sp = table_split(Jv, J, nt, nb);
+    const TableSplit sp = table_split(Jv, J, nt, nk);
     const int32_t nx = (Jv + 1 + kTgN - 1) / kTgN, ny = (nt + kTgM - 1) / kTgM;
     const int64_t items = (int64_t)nx * ny * sp.n;
     const float *hr = H + clo;
+    const double half = 0.5 * (S - 1);
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
         const int32_t bx = (int32_t)(it % nx);
         const int64_t rest = it / nx;
         const int32_t by = (int32_t)(rest % ny), bz = (int32_t)(rest / ny);
         const int32_t j0 = bx * kTgN, t0 = by * kTgM;
-        const int32_t cbeg = bz * sp.bins, cend = min(nb, cbeg + sp.bins);
+        const int32_t cbeg = bz * sp.bins, cend = min(nk, cbeg + sp.bins);
         const double D = (double)(j0 + gj) * delta;
-        double er, ei;
-        sincospi(2.0 * df * D, &ei, &er);
-        // weight operand: segment t0 + 16 wv + lane % 16, bin c0 + 4 ks + lane / 16
+        double er, ei, Jn[kTxTerms];
+        if (EXP) {
+            bessel_eps(kTwoPi * half * df * D, Jn);
+        } else {
+            sincospi(2.0 * df * D, &ei, &er);
+        }
+        // operand from memory: segment t0 + 16 wv + lane % 16, K index c0 + 4 ks + lane / 16
         const int32_t trow = t0 + 16 * wv + (lane & 15);
         const bool rok = trow < nt;
         const float *wr = w + (int64_t)(rok ? trow : 0) * ldw + clo;
+        const double *mr = EXP ? mu + (int64_t)(rok ? trow : 0) * nk : nullptr;
+        const double *vr = EXP ? nu + (int64_t)(rok ? trow : 0) * nk : nullptr;
         dbl4 av[4], ad[4];
 #pragma unroll
         for (int n = 0; n < 4; ++n) av[n] = ad[n] = dbl4{0.0, 0.0, 0.0, 0.0};
         for (int32_t c0 = cbeg; c0 < cend; c0 += kTgK) {
-            // this chunk's weights first, so their loads overlap the generation
-            float wk[kTgK / 4], hk[kTgK / 4];
+            // this chunk's operand values first, so their loads overlap the generation
+            double ak[kTgK / 4], dk[kTgK / 4];
 #pragma unroll
             for (int ks = 0; ks < kTgK / 4; ++ks) {
                 const int32_t c = c0 + 4 * ks + kq;
                 const bool ok = rok && c < cend;
-                wk[ks] = ok ? wr[c] : 0.0f;
-                hk[ks] = ok ? hr[c] : 0.0f;
+                if (EXP) {
+                    ak[ks] = ok ? mr[c] : 0.0;
+                    dk[ks] = ok ? vr[c] : 0.0;
+                } else {
+                    const double h = ok ? (double)hr[c] * (double)wr[c] : 0.0;
+                    ak[ks] = h;
+                    dk[ks] = -kTwoPi * delta * (f0 + (double)(k0 + clo + c) * df) * h;
+                }
             }
             __syncthreads();  // the previous chunk's (or item's) operands are no longer read
-            {
+            if (EXP) {
+                // strip c0 / kTxTerms + gg, its kTxTerms terms
+                const int64_t sgi = first + c0 / kTxTerms + gg;
+                const double x = (f0 + ((double)(sgi * S) + half) * df) * D, r = x - rint(x);
+                double zr, zi;
+                sincospi(2.0 * r, &zi, &zr);
+                const double sd = -kTwoPi * delta;
+#pragma unroll
+                for (int n = 0; n < kTxTerms; ++n) {
+                    // i^n e^{i theta}: real and imaginary parts
+                    const double re = (n & 3) == 0 ? zr : (n & 3) == 1 ? -zi : (n & 3) == 2 ? -zr : zi;
+                    const double im = (n & 3) == 0 ? zi : (n & 3) == 1 ? zr : (n & 3) == 2 ? -zi : -zr;
+                    bc[8 * gg + n][gj] = Jn[n] * re;
+                    bs[8 * gg + n][gj] = sd * Jn[n] * im;
+                }
+            } else {
                 const int32_t cs = c0 + 8 * gg;
                 const double x = (f0 + (double)(k0 + clo + cs) * df) * D, r = x - rint(x);
                 double zr, zi;
@@ -276,15 +410,12 @@ __global__ __launch_bounds__(256) void delay_table_gemm_kernel(const float *__re
             __syncthreads();
 #pragma unroll
             for (int ks = 0; ks < kTgK / 4; ++ks) {
-                const int32_t c = c0 + 4 * ks + kq;
-                const double h = (double)hk[ks] * (double)wk[ks];
-                const double hd = -kTwoPi * delta * (f0 + (double)(k0 + clo + c) * df) * h;
 #pragma unroll
                 for (int n = 0; n < 4; ++n) {
                     const double b1 = bc[4 * ks + kq][16 * n + (lane & 15)];
                     const double b2 = bs[4 * ks + kq][16 * n + (lane & 15)];
-                    av[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(h, b1, av[n], 0, 0, 0);
-                    ad[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(hd, b2, ad[n], 0, 0, 0);
+                    av[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(ak[ks], b1, av[n], 0, 0, 0);
+                    ad[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(dk[ks], b2, ad[n], 0, 0, 0);
                 }
             }
         }
@@ -306,14 +437,14 @@ __global__ __launch_bounds__(256) void delay_table_gemm_kernel(const float *__re
 // partial sums (range order fixed).  Tables are stored back to back, Jv
 // intervals each (segment t's at cub + t Jv).
 __global__ __launch_bounds__(256) void delay_cubic_general_kernel(const double2 *__restrict__ part, int32_t nt,
-                                                                  int32_t nbins, int32_t J,
+                                                                  int32_t nk, int32_t J,
                                                                   const unsigned long long *__restrict__ bound,
                                                                   double delta, float4 *__restrict__ cub)
 {
     const int32_t j = blockIdx.x * 256 + threadIdx.x;
     const int32_t Jv = table_intervals(bound, delta, J);
     if (j >= Jv) return;
-    const TableSplit sp = table_split(Jv, J, nt, nbins);
+    const TableSplit sp = table_split(Jv, J, nt, nk);
     const size_t stride = (size_t)nt * (Jv + 1);
     part += (size_t)blockIdx.y * (Jv + 1);
     double2 a = make_double2(0.0, 0.0), b = a;
@@ -862,21 +993,26 @@ hipError_t launch_fisher_full(const float *a, const float *b, int32_t rank, cons
 // ---- general weights: workspace layout and launch ----
 struct GeneralLayout {
     int32_t J = 0, fb = 0;
+    StripGrid sg;     // expanded basis (sg.S > 0) or direct
+    int32_t nk = 0;   // K of the table contraction
     int64_t ntiles = 0;
-    size_t part = 0, cub = 0, U = 0, flags = 0, bound = 0, total = 0;  // byte offsets (total: size)
+    size_t part = 0, cub = 0, U = 0, flags = 0, bound = 0, mu = 0, nu = 0, total = 0;  // byte offsets (total: size)
 };
 
-static GeneralLayout general_layout(double f_max, int32_t nbins, int32_t nt, int32_t npix, int64_t nside)
+static GeneralLayout general_layout(double f0, double df, int64_t k0, int32_t clo, int32_t chi, int32_t nt,
+                                    int32_t npix, int64_t nside)
 {
     GeneralLayout L;
     double delta;
-    fisher_table_geometry(f_max, &delta, &L.J, &L.fb);
+    fisher_table_geometry(f0 + (double)(k0 + chi - 1) * df, &delta, &L.J, &L.fb);
+    L.sg = strip_grid(df, k0, clo, chi);
+    L.nk = L.sg.S > 0 ? L.sg.n * kTxTerms : chi - clo;
     const int64_t nrow = nside > 0 ? npix / 2 : npix;
     const int64_t nT = (nrow + kFt - 1) / kFt;
     L.ntiles = (nside > 0 ? 2 : 1) * (nT * (nT + 1) / 2);
     size_t o = 0;
     L.part = o;
-    o += up256((size_t)table_split_cap(nbins) * nt * (L.J + 1) * sizeof(double2));
+    o += up256((size_t)table_split_cap(L.nk) * nt * (L.J + 1) * sizeof(double2));
     L.cub = o;
     o += up256((size_t)nt * L.J * sizeof(float4));
     L.U = o;
@@ -885,26 +1021,31 @@ static GeneralLayout general_layout(double f_max, int32_t nbins, int32_t nt, int
     o += up256(kSymParts * sizeof(double));
     L.bound = o;
     o += 256;
+    if (L.sg.S > 0) {
+        L.mu = o;
+        o += up256((size_t)nt * L.nk * sizeof(double));
+        L.nu = o;
+        o += up256((size_t)nt * L.nk * sizeof(double));
+    }
     L.total = o;
     return L;
 }
 
-size_t fisher_full_general_workspace_bytes(double f_max, int32_t nbins, int32_t nt, int32_t npix, int64_t nside)
+size_t fisher_full_general_workspace_bytes(double f0, double df, int64_t k0, int32_t clo, int32_t chi, int32_t nt,
+                                           int32_t npix, int64_t nside)
 {
-    return general_layout(f_max, nbins, nt, npix, nside).total;
+    return general_layout(f0, df, k0, clo, chi, nt, npix, nside).total;
 }
 
 hipError_t launch_fisher_full_general(const float *w, int64_t ldw, const float *H, int32_t clo, int32_t chi,
                                       double f0, double df, int64_t k0, const float *gamma, const double *tau,
                                       int32_t nt, int32_t npix, int64_t nside, float *G, void *work, hipStream_t s)
 {
-    const double f_max = f0 + (double)(k0 + chi - 1) * df;
-    const int32_t nbins = chi - clo;
-    const GeneralLayout L = general_layout(f_max, nbins, nt, npix, nside);
+    const GeneralLayout L = general_layout(f0, df, k0, clo, chi, nt, npix, nside);
     if (L.fb < kFracBitsMin || L.ntiles > 0x7fffffff) return hipErrorInvalidValue;
     double delta;
     int32_t J, fb;
-    fisher_table_geometry(f_max, &delta, &J, &fb);
+    fisher_table_geometry(f0 + (double)(k0 + chi - 1) * df, &delta, &J, &fb);
     char *base = reinterpret_cast<char *>(work);
     double2 *part = reinterpret_cast<double2 *>(base + L.part);
     float4 *cub = reinterpret_cast<float4 *>(base + L.cub);
@@ -926,10 +1067,20 @@ hipError_t launch_fisher_full_general(const float *w, int64_t ldw, const float *
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
     // persistent: two workgroups per compute unit (their registers allow two)
-    hipLaunchKernelGGL(delay_table_gemm_kernel, dim3((unsigned)(2 * cus)), dim3(256), 0, s, w, ldw, H, nt, clo, chi, f0,
-                       df, k0, delta, J, (const unsigned long long *)bound, part);
+    if (L.sg.S > 0) {
+        double *mu = reinterpret_cast<double *>(base + L.mu), *nu = reinterpret_cast<double *>(base + L.nu);
+        hipLaunchKernelGGL(table_moments_kernel, dim3((unsigned)((L.sg.n + 63) / 64), (unsigned)nt), dim3(64), 0, s, w,
+                           ldw, H, clo, chi, f0, df, k0, L.sg.S, L.sg.first, L.sg.n, mu, nu);
+        hipLaunchKernelGGL(delay_table_gemm_kernel<true>, dim3((unsigned)(2 * cus)), dim3(256), 0, s, w, ldw, H,
+                           (const double *)mu, (const double *)nu, nt, clo, L.nk, f0, df, k0, L.sg.S, L.sg.first,
+                           delta, J, (const unsigned long long *)bound, part);
+    } else {
+        hipLaunchKernelGGL(delay_table_gemm_kernel<false>, dim3((unsigned)(2 * cus)), dim3(256), 0, s, w, ldw, H,
+                           (const double *)nullptr, (const double *)nullptr, nt, clo, L.nk, f0, df, k0, (int32_t)0,
+                           (int64_t)0, delta, J, (const unsigned long long *)bound, part);
+    }
     hipLaunchKernelGGL(delay_cubic_general_kernel, dim3((unsigned)((J + 255) / 256), (unsigned)nt), dim3(256), 0, s,
-                       part, nt, nbins, J, (const unsigned long long *)bound, delta, cub);
+                       part, nt, L.nk, J, (const unsigned long long *)bound, delta, cub);
     if (J <= kLdsTable && fisher_full_table_in_lds()) {
         const int64_t grid = (L.ntiles + kStTiles - 1) / kStTiles;
         hipLaunchKernelGGL(fisher_full_stream_kernel, dim3((unsigned)grid), dim3(kStWaves * 64), 0, s, gamma, U, nt,

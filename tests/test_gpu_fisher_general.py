@@ -7,6 +7,10 @@ segment (synth.nonstationary_weights: per-segment level and tilt, the scatter
 of a 16-average spectral estimate, lines switching on and off), of full rank,
 so no sum of a few products a(t) b(c) reproduces them.
 
+The tables' band sums run over the bins (coarse grids, 1/4 Hz and 1 Hz here)
+or over Jacobi-Anger moments of 64- or 16-bin strips (1/32 Hz, 1/8 Hz); both
+bases are covered.
+
 Tolerance of G: max |G_gpu - G_oracle| / S <= 1e-5 with
 S(p,q) = sum_t (sum_c |H w(t,c)|) |gamma_p(t) gamma_q(t)|, the bound of each
 term of the band and segment sums.  Budget as for the separable matrix: cubic
@@ -38,6 +42,7 @@ CASES = [  # baseline, nside, npix used (None: all), nt, k0, nf, band, df, antip
     ("AB", 8, None, 60, 53000, 64, (0, 64), 1 / 32, True),    # antipodal, 1.68 kHz
     ("BC", 2, None, 20, 39000, 50, (3, 47), 0.125, True),     # antipodal, 4.9 kHz global-memory form
     ("AC", 2, None, 7, 63, 2, (1, 2), 0.25, False),           # single bin, tiny day
+    ("AB", 4, None, 30, 53010, 300, (7, 290), 1 / 32, True),  # band from mid-strip to mid-strip, 5 strips
 ]
 
 
@@ -135,11 +140,14 @@ def test_fisher_full_general_lds_and_global_forms_agree_bitwise(sg, monkeypatch)
             assert torch.equal(G1, G2)
 
 
-def test_fisher_full_general_equals_separable_path_for_rank_one(sg):
-    """w = a(t) b(c): the general path (a folded into each segment's table) and
-    sgwb_fisher_full (one table, a applied per term) agree to float32 rounding
-    (1e-6 of S)."""
-    nt, nside, k0, nf, df = 40, 4, 4000, 64, 0.25
+@pytest.mark.parametrize("k0,df", [(4000, 0.25), (53000, 1 / 32), (39000, 0.125)],
+                         ids=["direct-bins", "expanded-S64", "expanded-S16"])
+def test_fisher_full_general_equals_separable_path_for_rank_one(sg, k0, df):
+    """w = a(t) b(c): the general path (a folded into each segment's table; its
+    band sum over the bins at 1/4 Hz, over 64- or 16-bin strip moments at 1/32
+    and 1/8 Hz) and sgwb_fisher_full (one table, a applied per term) agree to
+    float32 rounding (1e-6 of S)."""
+    nt, nside, nf = 40, 4, 64
     g, t, _, H = _inputs(sg, "AB", nside, None, nt, k0, nf, df, 44)
     f = freqs(F0, df, k0, nf)
     a = synth.segment_scale(nt, 45).astype(np.float32)
