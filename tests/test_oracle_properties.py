@@ -16,7 +16,12 @@ mistake the fixed pins happen not to exercise still fails one of them.
   * folding (Sec. II.B): one day without overlapping windows (W = 0) gives
     v = s, u = w = 0, x = s C; folding two halves of the days and adding gives
     the fold of all days, for v always and for u, w, x when no neighbour pair
-    with data crosses the split.
+    with data crosses the split;
+  * full Fisher matrix for general weights (Eq. eq_fisher, Sec. V): symmetric,
+    positive semi-definite for w >= 0, linear in w, segment-order invariant,
+    diagonal = band-summed per-bin diagonal.  Planted in a copy of the oracle,
+    tau_p + tau_q for tau_p - tau_q, a dropped H and gamma_p^2 for
+    gamma_p gamma_q each fail it.
 """
 import numpy as np
 import pytest
@@ -167,3 +172,37 @@ def test_fold_properties(oracle_mod, seed, ndays, nt, nf, W):
     t = oracle_mod.fold(C, s, pr, W)
     for ai, bi, ti in zip(a, b, t):
         np.testing.assert_allclose(ai + bi, ti, rtol=1e-12, atol=1e-12)
+
+
+@SETTINGS
+@given(seed=st.integers(0, 2**31), nt=st.integers(1, 7), nf=st.integers(1, 10), npix=st.integers(1, 9), g=grid,
+       a=st.floats(0.0, 3.0), b=st.floats(0.0, 3.0), data=st.data())
+def test_full_fisher_properties(oracle_mod, seed, nt, nf, npix, g, a, b, data):
+    """Full Fisher matrix for general weights (Eq. eq_fisher with the band's H,
+    Sec. V), any w(t,c) >= 0: symmetric; positive semi-definite (a sum over
+    segments and bins of H w k k^T with k = gamma cos / sin of the phases);
+    linear in w; unchanged by reordering the segments; its diagonal is the
+    band sum of the per-bin Fisher diagonal (Eq. eq_fisher at p = p')."""
+    f0, df, k0 = g
+    rng = np.random.default_rng(seed)
+    w1 = rng.uniform(0.0, 2.0, (nt, nf))
+    w2 = rng.uniform(0.0, 2.0, (nt, nf))
+    H = rng.uniform(0.1, 2.0, nf)
+    gamma = rng.uniform(-1.0, 1.0, (nt, npix))
+    tau = rng.uniform(-0.04, 0.04, (nt, npix))
+    klo = data.draw(st.integers(0, nf - 1))
+    khi = data.draw(st.integers(klo + 1, nf))
+    G1 = oracle_mod.fisher_full(w1, H, f0, df, k0, klo, khi, gamma, tau)
+    G2 = oracle_mod.fisher_full(w2, H, f0, df, k0, klo, khi, gamma, tau)
+    scale = np.abs(H[klo:khi]).sum() * (np.abs(w1).sum(axis=1) @ (gamma ** 2).sum(axis=1)) + 1e-300
+    np.testing.assert_allclose(G1, G1.T, rtol=0, atol=1e-13 * scale)
+    assert np.linalg.eigvalsh(0.5 * (G1 + G1.T)).min() >= -1e-12 * scale
+    G12 = oracle_mod.fisher_full(a * w1 + b * w2, H, f0, df, k0, klo, khi, gamma, tau)
+    np.testing.assert_allclose(G12, a * G1 + b * G2, rtol=0, atol=1e-12 * (1 + a + b) * scale)
+    perm = rng.permutation(nt)
+    Gp = oracle_mod.fisher_full(w1[perm], H, f0, df, k0, klo, khi, gamma[perm], tau[perm])
+    np.testing.assert_allclose(Gp, G1, rtol=0, atol=1e-12 * scale)
+    C = np.zeros((nt, nf), dtype=np.complex128)
+    _, Gk = oracle_mod.maps(C, w1, f0, df, k0, gamma, tau)
+    _, Gbb = oracle_mod.band(np.zeros_like(Gk), Gk, H, klo, khi)
+    np.testing.assert_allclose(np.diag(G1), Gbb, rtol=1e-12, atol=1e-300)
