@@ -253,26 +253,43 @@ static StripGrid strip_grid(double df, int64_t k0, int32_t clo, int32_t chi)
 
 // Strip moments: mu_n(t,s) = sum over the strip's band bins of H_c w(t,c)
 // T_n(s_c), nu_n(t,s) the same with H_c w(t,c) f_c; [nt][nstrips kTxTerms]
-// float64, T_n by the three-term recurrence.  One thread per (segment, strip).
-__global__ __launch_bounds__(64) void table_moments_kernel(const float *__restrict__ w, int64_t ldw,
-                                                           const float *__restrict__ H, int32_t clo, int32_t chi,
-                                                           double f0, double df, int64_t k0, int32_t S, int64_t first,
-                                                           int32_t nstrips, double *__restrict__ mu,
-                                                           double *__restrict__ nu)
+// float64, T_n by the three-term recurrence.  A 256-thread workgroup takes 64
+// strips of one segment: their H w (float64, zero outside the band) come into
+// LDS with coalesced loads (rows padded by one word against bank conflicts);
+// four threads share a strip, a quarter of its bins each, and their partial
+// moments are added in a fixed order.
+constexpr int kTxStrips = 64;  // strips per workgroup
+constexpr int kTxSplit = 4;    // threads per strip
+
+__global__ __launch_bounds__(256) void table_moments_kernel(const float *__restrict__ w, int64_t ldw,
+                                                            const float *__restrict__ H, int32_t clo, int32_t chi,
+                                                            double f0, double df, int64_t k0, int32_t S,
+                                                            int64_t first, int32_t nstrips, double *__restrict__ mu,
+                                                            double *__restrict__ nu)
 {
-    const int32_t sg = blockIdx.x * 64 + threadIdx.x;
-    if (sg >= nstrips) return;
+    __shared__ double hw[kTxStrips][64 + 1];
+    __shared__ double red[kTxSplit - 1][kTxStrips][2 * kTxTerms];
+    const int32_t s0 = blockIdx.x * kTxStrips;
     const int32_t t = blockIdx.y;
-    const int64_t kb = (first + sg) * S;  // absolute first bin of the strip
-    const double half = 0.5 * (S - 1);
     const float *wr = w + (int64_t)t * ldw;
+    const int64_t kb0 = (first + s0) * S;  // absolute first bin of the workgroup's first strip
+    const int32_t nsg = min(kTxStrips, nstrips - s0);
+    for (int32_t e = threadIdx.x; e < nsg * S; e += 256) {
+        const int64_t c = kb0 + e - k0;  // column
+        hw[e / S][e % S] = c >= clo && c < chi ? (double)H[c] * (double)wr[c] : 0.0;
+    }
+    __syncthreads();
+    const int ls = threadIdx.x % kTxStrips, part = threadIdx.x / kTxStrips;  // strip, quarter
+    const int32_t sg = s0 + ls;
+    const bool ok = sg < nstrips;
+    const int64_t kb = kb0 + (int64_t)ls * S;
+    const double half = 0.5 * (S - 1);
+    const int32_t q = S / kTxSplit, i0 = part * q;
     double m[kTxTerms], v[kTxTerms];
 #pragma unroll
     for (int n = 0; n < kTxTerms; ++n) m[n] = v[n] = 0.0;
-    for (int32_t i = 0; i < S; ++i) {
-        const int64_t c = kb + i - k0;  // column
-        if (c < clo || c >= chi) continue;
-        const double h = (double)H[c] * (double)wr[c];
+    for (int32_t i = i0; ok && i < i0 + q; ++i) {
+        const double h = hw[ls][i];
         const double hf = h * (f0 + (double)(kb + i) * df);
         const double s = ((double)i - half) / half;
         double tp = 1.0, tc = s;  // T_0, T_1
@@ -289,6 +306,22 @@ __global__ __launch_bounds__(64) void table_moments_kernel(const float *__restri
             v[n] += hf * tn;
         }
     }
+    if (part > 0) {
+#pragma unroll
+        for (int n = 0; n < kTxTerms; ++n) {
+            red[part - 1][ls][n] = m[n];
+            red[part - 1][ls][kTxTerms + n] = v[n];
+        }
+    }
+    __syncthreads();
+    if (part > 0 || !ok) return;
+#pragma unroll
+    for (int r = 0; r < kTxSplit - 1; ++r)
+#pragma unroll
+        for (int n = 0; n < kTxTerms; ++n) {
+            m[n] += red[r][ls][n];
+            v[n] += red[r][ls][kTxTerms + n];
+        }
     const int64_t nk = (int64_t)nstrips * kTxTerms;
     double *mr = mu + (int64_t)t * nk + (int64_t)sg * kTxTerms, *vr = nu + (int64_t)t * nk + (int64_t)sg * kTxTerms;
 #pragma unroll
@@ -1069,7 +1102,8 @@ hipError_t launch_fisher_full_general(const float *w, int64_t ldw, const float *
     // persistent: two workgroups per compute unit (their registers allow two)
     if (L.sg.S > 0) {
         double *mu = reinterpret_cast<double *>(base + L.mu), *nu = reinterpret_cast<double *>(base + L.nu);
-        hipLaunchKernelGGL(table_moments_kernel, dim3((unsigned)((L.sg.n + 63) / 64), (unsigned)nt), dim3(64), 0, s, w,
+        hipLaunchKernelGGL(table_moments_kernel, dim3((unsigned)((L.sg.n + kTxStrips - 1) / kTxStrips), (unsigned)nt),
+                           dim3(kTxStrips * kTxSplit), 0, s, w,
                            ldw, H, clo, chi, f0, df, k0, L.sg.S, L.sg.first, L.sg.n, mu, nu);
         hipLaunchKernelGGL(delay_table_gemm_kernel<true>, dim3((unsigned)(2 * cus)), dim3(256), 0, s, w, ldw, H,
                            (const double *)mu, (const double *)nu, nt, clo, L.nk, f0, df, k0, L.sg.S, L.sg.first,
