@@ -233,3 +233,39 @@ def test_fisher_full_general_rejects_broken_seeds(sg):
     G = sg.fisher_full_general(wd, Hd, sg.FGrid(F0, df), k0, 0, nf, g, t, antipodal=True)
     torch.cuda.synchronize()
     assert bool(torch.isnan(G).all())
+
+
+@pytest.mark.parametrize("weights", ["separable", "general"])
+def test_fisher_full_nside64_sampled(sg, oracle_mod, weights):
+    """nside 64 (49 152 pixels: G has 2.4e9 entries, past 2^31, so the entry
+    offsets must be 64-bit), a whole 898-segment day, 256 bins at the top of the
+    band, antipodal blocks: sampled rows and columns (with their antipodes)
+    against the oracle, for the separable and the general entry point."""
+    nt, nside, k0, nf, df = 898, 64, 54336, 256, 1 / 32
+    g, t, w, H = _inputs(sg, "AB", nside, None, nt, k0, nf, df, 50)
+    Hd = torch.from_numpy(H).cuda()
+    if weights == "general":
+        G = sg.fisher_full_general(torch.from_numpy(w).cuda(), Hd, sg.FGrid(F0, df), k0, 0, nf, g, t, antipodal=True)
+    else:
+        f = freqs(F0, df, k0, nf)
+        a = synth.segment_scale(nt, 51).astype(np.float32)
+        b = (synth.spectrum_H(f) / synth.noise_psd(f) ** 2).astype(np.float32)
+        w = np.outer(a, b).astype(np.float32)
+        G = sg.fisher_full(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), Hd, sg.FGrid(F0, df), k0, 0, nf,
+                           g, t, antipodal=True)
+    _, am = sg.healpix_centres(nside)
+    torch.cuda.synchronize()
+    am = am.cpu().numpy().astype(np.int64)
+    npix = 12 * nside * nside
+    base = np.concatenate([np.random.default_rng(8).choice(npix, 10, replace=False), [0, npix // 2 - 1, npix - 1]])
+    sel = np.unique(np.concatenate([base, am[base]]))
+    idx = torch.from_numpy(sel).cuda()
+    Gs = G.index_select(0, idx).index_select(1, idx).double().cpu().numpy()
+    gh, th = g.cpu().numpy().astype(np.float64), t.cpu().numpy()
+    Go = _oracle(oracle_mod, w, H, df, k0, 0, nf, gh, th, sel)
+    S = _scale(w, H, 0, nf, gh[:, sel])
+    assert np.max(np.abs(Gs - Go) / S) <= 1e-5
+    # the far corner of the matrix (row and column past 2^31 entries) is the mirror of its transpose
+    assert torch.equal(G[npix - 1, :64], G[:64, npix - 1])
+    del G
+    torch.cuda.empty_cache()
