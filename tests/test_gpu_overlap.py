@@ -108,3 +108,35 @@ def test_overlap_fisher_deterministic_and_single_segment(sg):
     _, Gp = sg.make_maps(C, vd[:1], sg.FGrid(F0, 1 / 32), 0, g[:1].contiguous(), t[:1].contiguous(), want_x=False)
     torch.cuda.synchronize()
     assert torch.equal(G1, Gp)
+
+
+def test_overlap_fisher_full_band_nside32_sampled(sg, oracle_mod):
+    """The configuration the overlap leg of the benchmark times: the full band
+    (54 592 bins of 1/32 Hz from 20 Hz), a whole 898-segment day, nside 32,
+    antipodal seeds; 3000 sampled (bin, pixel) outputs against the oracle, the
+    whole value at the beam bound and the neighbour terms alone at the
+    dirty-map bound."""
+    nt, nside, k0, nf, df = 898, 32, 0, 54592, 1 / 32
+    g, t, v, u, w = _inputs(sg, "AB", nside, nt, k0, nf, df, 12)
+    vd, ud, wd = (torch.from_numpy(a).cuda() for a in (v, u, w))
+    G = sg.fisher_overlap(vd, ud, wd, sg.FGrid(F0, df), k0, g, t, antipodal=True)
+    z = torch.zeros_like(vd)
+    G0 = sg.fisher_overlap(vd, z, z, sg.FGrid(F0, df), k0, g, t, antipodal=True)
+    npix = 12 * nside * nside
+    rng = np.random.default_rng(13)
+    rows = np.concatenate([rng.integers(0, nf, 2992), [0, 63, 64, 127, 128, nf - 65, nf - 64, nf - 1]])
+    cols = rng.integers(0, npix, rows.size)
+    ri, ci = torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()
+    Gg = G[ri, ci].double().cpu().numpy()
+    Gg0 = G0[ri, ci].double().cpu().numpy()
+    del G, G0
+    torch.cuda.empty_cache()
+    gh, th = g.cpu().numpy(), t.cpu().numpy()
+    Go, _, S = oracle_mod.fisher_overlap_at(v, u, w, F0, df, k0, gh, th, rows, cols)
+    zh = np.zeros_like(v)
+    Go0, _, _ = oracle_mod.fisher_overlap_at(v, zh, zh, F0, df, k0, gh, th, rows, cols)
+    assert np.max(np.abs(Gg - Go) / S) <= 1e-4
+    S_nb = S - np.abs(Go0)
+    err_nb = np.abs((Gg - Gg0) - (Go - Go0)) / S_nb
+    round_once = 2.0 ** -23 * np.abs(Gg) / S_nb
+    assert np.max(err_nb - round_once) <= 1e-5
