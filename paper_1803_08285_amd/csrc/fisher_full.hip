@@ -805,14 +805,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t seg_rsrc(const void *p, int32_
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, npix * 4, 0x00020000);
 }
 
-__global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__restrict__ gamma,
+// ONE = true: one table for every segment (weights a of rank-one terms),
+// copied once, the segment's weight a[t] on the row seeds; accumulate adds to
+// G (the later ranks).  ONE = false: per-segment tables streamed as above.
+template <bool ONE>
+__global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__restrict__ a,
+                                                                 const float *__restrict__ gamma,
                                                                  const uint32_t *__restrict__ U, int32_t nt,
                                                                  int32_t npix, int64_t nside,
                                                                  const double *__restrict__ flags,
                                                                  const float4 *__restrict__ cub, int32_t J,
                                                                  const unsigned long long *__restrict__ bound,
                                                                  double delta, int32_t fb, int64_t ntiles,
-                                                                 float *__restrict__ G)
+                                                                 int32_t accumulate, float *__restrict__ G)
 {
     __shared__ float4 tab[kLdsTable];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -837,7 +842,7 @@ __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__
 #pragma unroll
     for (int j = 0; j < 4; ++j) qo[j] = (uint32_t)min(q0 + j, last_row) * 4u;
     const int32_t Jv = table_intervals(bound, delta, J);
-    const bool dbuf = 2 * Jv <= kLdsTable;
+    const bool dbuf = !ONE && 2 * Jv <= kLdsTable;
     const bool rejected = seeds_rejected(flags);
     const int32_t ntu = rejected ? 0 : nt;
     float acc[8][4] = {};
@@ -845,9 +850,10 @@ __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__
     uint32_t up[8], uq[4];
     {
         const __amdgpu_buffer_rsrc_t rg = seg_rsrc(gamma, npix), ru = seg_rsrc(U, npix);
+        const float a0 = ONE ? a[0] : 1.0f;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            gp[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, po[i], 0, 0));
+            gp[i] = a0 * __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, po[i], 0, 0));
             up[i] = __builtin_amdgcn_raw_buffer_load_b32(ru, po[i], 0, 0);
         }
 #pragma unroll
@@ -856,9 +862,9 @@ __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__
             uq[j] = ucol(__builtin_amdgcn_raw_buffer_load_b32(ru, qo[j], 0, 0));
         }
     }
-    // segments per stage: as many tables as one buffer holds
-    const int32_t g = (dbuf ? kLdsTable / 2 : kLdsTable) / Jv;
-    if (ntu > 0) copy_lds(cub, tab, min(g, nt) * Jv);
+    // segments per stage: as many tables as one buffer holds (all of them with one table)
+    const int32_t g = ONE ? nt : (dbuf ? kLdsTable / 2 : kLdsTable) / Jv;
+    if (ntu > 0) copy_lds(cub, tab, (ONE ? 1 : min(g, nt)) * Jv);
     for (int32_t s0 = 0; s0 < ntu; s0 += g) {
         const int32_t st = s0 / g, s1 = min(s0 + g, nt);
         float4 *cur = tab;
@@ -878,8 +884,10 @@ __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__
         }
         for (int32_t t = s0; t < s1; ++t) {
             // next segment's inputs (the last iteration re-reads segment nt - 1)
-            const size_t o = (size_t)min(t + 1, nt - 1) * (size_t)npix;
+            const int32_t tn = min(t + 1, nt - 1);
+            const size_t o = (size_t)tn * (size_t)npix;
             const __amdgpu_buffer_rsrc_t rg = seg_rsrc(gamma + o, npix), ru = seg_rsrc(U + o, npix);
+            const float an = ONE ? a[tn] : 1.0f;
             float gpn[8], gqn[4];
             uint32_t upn[8], uqn[4];
 #pragma unroll
@@ -892,7 +900,7 @@ __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__
                 gqn[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, qo[j], 0, 0));
                 uqn[j] = __builtin_amdgcn_raw_buffer_load_b32(ru, qo[j], 0, 0);
             }
-            const char *tb = reinterpret_cast<const char *>(cur + (size_t)(t - s0) * Jv);
+            const char *tb = reinterpret_cast<const char *>(ONE ? cur : cur + (size_t)(t - s0) * Jv);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 float4 c[4];
@@ -912,7 +920,7 @@ __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                gp[i] = gpn[i];
+                gp[i] = ONE ? an * gpn[i] : gpn[i];
                 up[i] = upn[i];
             }
 #pragma unroll
@@ -930,7 +938,7 @@ __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__
             const int64_t p = p0 + i, q = q0 + jj;
             // rejected seeds: the matrix is NaN
             const float v = rejected ? __builtin_nanf("") : acc[i][jj];
-            if (p < nrow && q < nrow && (tr != tc || p <= q)) store_value(G, npix, nside, ns, p, q, v, 0);
+            if (p < nrow && q < nrow && (tr != tc || p <= q)) store_value(G, npix, nside, ns, p, q, v, accumulate);
         }
 }
 
@@ -948,6 +956,15 @@ static bool fisher_full_table_in_lds()
 {
     const char *e = std::getenv("SGWB_FISHER_TABLE");
     return !(e && std::strcmp(e, "global") == 0);
+}
+
+// Separable weights go through the streaming kernel (one table, 8 x 4
+// entries a lane: 25 % faster); SGWB_FISHER_ONE_TABLE=persistent selects the
+// persistent LDS kernel (4 x 4 a thread).  Both give the same bits.
+static bool fisher_full_one_table_stream()
+{
+    const char *e = std::getenv("SGWB_FISHER_ONE_TABLE");
+    return !(e && std::strcmp(e, "persistent") == 0);
 }
 
 static size_t up256(size_t n) { return (n + 255) & ~(size_t)255; }
@@ -1010,7 +1027,11 @@ hipError_t launch_fisher_full(const float *a, const float *b, int32_t rank, cons
                            s, H, br, clo, chi, f0, df, k0, delta, J, part);
         hipLaunchKernelGGL(delay_cubic_kernel, dim3((unsigned)((J + 255) / 256)), dim3(256), 0, s, part, nchunk, J,
                            cub);
-        if (lds) {
+        if (lds && fisher_full_one_table_stream()) {
+            hipLaunchKernelGGL(fisher_full_stream_kernel<true>, dim3((unsigned)((ntiles + kStTiles - 1) / kStTiles)),
+                               dim3(kStWaves * 64), 0, s, ar, gamma, U, nt, npix, nside, flags, cub, J,
+                               (const unsigned long long *)nullptr, delta, fb, ntiles, (int32_t)(r > 0), G);
+        } else if (lds) {
             const int64_t grid = std::min<int64_t>(cus, (ntiles + 1) / 2);
             hipLaunchKernelGGL(fisher_full_lds_kernel, dim3((unsigned)grid), dim3(512), 0, s, ar, gamma, U, nt, npix,
                                nside, flags, cub, J, fb, ntiles, (int32_t)(r > 0), G);
@@ -1117,8 +1138,9 @@ hipError_t launch_fisher_full_general(const float *w, int64_t ldw, const float *
                        part, nt, L.nk, J, (const unsigned long long *)bound, delta, cub);
     if (J <= kLdsTable && fisher_full_table_in_lds()) {
         const int64_t grid = (L.ntiles + kStTiles - 1) / kStTiles;
-        hipLaunchKernelGGL(fisher_full_stream_kernel, dim3((unsigned)grid), dim3(kStWaves * 64), 0, s, gamma, U, nt,
-                           npix, nside, flags, cub, J, (const unsigned long long *)bound, delta, fb, L.ntiles, G);
+        hipLaunchKernelGGL(fisher_full_stream_kernel<false>, dim3((unsigned)grid), dim3(kStWaves * 64), 0, s,
+                           (const float *)nullptr, gamma, U, nt, npix, nside, flags, cub, J,
+                           (const unsigned long long *)bound, delta, fb, L.ntiles, (int32_t)0, G);
     } else {
         hipLaunchKernelGGL(fisher_full_kernel, dim3((unsigned)L.ntiles), dim3(256), 0, s, (const float *)nullptr,
                            gamma, U, nt, npix, nside, flags, cub, J, (const unsigned long long *)bound, delta, fb,

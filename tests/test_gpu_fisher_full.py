@@ -258,3 +258,27 @@ def test_fisher_full_antipodal_rejects_broken_seeds(sg):
     G = sg.fisher_full(ad, bd, Hd, sg.FGrid(F0, df), k0, 0, nf, g, t, antipodal=True)
     torch.cuda.synchronize()
     assert bool(torch.isnan(G).all())
+
+
+@pytest.mark.parametrize("case", [("AB", 4, 40, 100, 64, 0.25, 1, False), ("AC", 8, 60, 53000, 64, 1 / 32, 1, True),
+                                  ("AB", 4, 40, 100, 64, 0.25, 3, True), ("BC", 4, 33, 0, 30, 1.0, 2, False)],
+                         ids=["AB4", "AC8-anti", "AB4-rank3-anti", "BC4-rank2"])
+def test_fisher_full_stream_and_persistent_forms_agree_bitwise(sg, monkeypatch, case):
+    """The streaming kernel (the default: one table in LDS, 8 x 4 entries a
+    lane) and the persistent LDS kernel (SGWB_FISHER_ONE_TABLE=persistent, 4 x 4
+    a thread) add the same float32 terms in the same order: the same bits, also
+    over several ranks (the later ranks add to G)."""
+    bl, nside, nt, k0, nf, df, rank, anti = case
+    g, t, _, _, H = _inputs(sg, bl, nside, None, nt, k0, nf, df, 34)
+    rng = np.random.default_rng(35)
+    f = freqs(F0, df, k0, nf)
+    a = rng.uniform(0.2, 1.0, (rank, nt)).astype(np.float32)
+    b = np.stack([(synth.spectrum_H(f) / synth.noise_psd(f) ** 2) * rng.uniform(0.5, 1.5, nf)
+                  for _ in range(rank)]).astype(np.float32)
+    ad, bd, Hd = (torch.from_numpy(x).cuda() for x in (a, b, H))
+    G1 = sg.fisher_full(ad, bd, Hd, sg.FGrid(F0, df), k0, 0, nf, g, t, antipodal=anti)
+    monkeypatch.setenv("SGWB_FISHER_ONE_TABLE", "persistent")
+    G2 = sg.fisher_full(ad, bd, Hd, sg.FGrid(F0, df), k0, 0, nf, g, t, antipodal=anti)
+    monkeypatch.delenv("SGWB_FISHER_ONE_TABLE")
+    torch.cuda.synchronize()
+    assert torch.equal(G1, G2)
