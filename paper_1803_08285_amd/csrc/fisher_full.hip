@@ -797,6 +797,23 @@ __device__ __forceinline__ void copy_lds(const float4 *__restrict__ src, float4 
         __builtin_amdgcn_global_load_lds(base + (size_t)e * sizeof(float4), dst + (e - lane), 16, 0, 0);
 }
 
+// kLdsTable / 2 float4 into LDS at dst (a half-size buffer), the first n of
+// them from src: a fixed number of copy instructions per lane (lanes past n
+// copy src[n - 1] into the buffer's unused tail), so the compiler can count
+// them and wait for earlier loads without waiting for the copy.
+__device__ __forceinline__ void copy_lds_half(const float4 *__restrict__ src, float4 *dst, int32_t n)
+{
+    const int lane = threadIdx.x & 63;
+    const char *base = reinterpret_cast<const char *>(src);
+#pragma unroll
+    for (int r = 0; r < kLdsTable / 2 / (kStWaves * 64); ++r) {
+        const int32_t e = r * kStWaves * 64 + (int32_t)threadIdx.x;
+        __builtin_amdgcn_global_load_lds(base + (size_t)min(e, n - 1) * sizeof(float4), dst + (e - lane), 16, 0,
+                                         0);
+    }
+}
+static_assert((kLdsTable / 2) % (kStWaves * 64) == 0, "whole copy rounds");
+
 // Buffer resource over one segment's npix 4-byte seeds (raw loads at byte
 // offsets; out-of-range offsets read 0).  0x00020000: the gfx9 descriptor word
 // for plain 32-bit raw access.
@@ -808,6 +825,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t seg_rsrc(const void *p, int32_
 // ONE = true: one table for every segment (weights a of rank-one terms),
 // copied once, the segment's weight a[t] on the row seeds; accumulate adds to
 // G (the later ranks).  ONE = false: per-segment tables streamed as above.
+// The two stage buffers are distinct LDS arrays, and the stage loop is
+// unrolled by two so that each step reads one and copies into the other by
+// name: the compiler then orders the reads only after copies into the same
+// array (with one array it waits for every copy before every read).  Tables
+// longer than one buffer (single-buffered) span both arrays.
 template <bool ONE>
 __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__restrict__ a,
                                                                  const float *__restrict__ gamma,
@@ -819,7 +841,7 @@ __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__
                                                                  double delta, int32_t fb, int64_t ntiles,
                                                                  int32_t accumulate, float *__restrict__ G)
 {
-    __shared__ float4 tab[kLdsTable];
+    constexpr int32_t kHalf = kLdsTable / 2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int ty = lane >> 3, tx = lane & 7;
     const int64_t nrow = nside > 0 ? npix / 2 : npix;
@@ -842,7 +864,6 @@ __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__
 #pragma unroll
     for (int j = 0; j < 4; ++j) qo[j] = (uint32_t)min(q0 + j, last_row) * 4u;
     const int32_t Jv = table_intervals(bound, delta, J);
-    const bool dbuf = !ONE && 2 * Jv <= kLdsTable;
     const bool rejected = seeds_rejected(flags);
     const int32_t ntu = rejected ? 0 : nt;
     float acc[8][4] = {};
@@ -862,73 +883,105 @@ __global__ __launch_bounds__(512) void fisher_full_stream_kernel(const float *__
             uq[j] = ucol(__builtin_amdgcn_raw_buffer_load_b32(ru, qo[j], 0, 0));
         }
     }
-    // segments per stage: as many tables as one buffer holds (all of them with one table)
-    const int32_t g = ONE ? nt : (dbuf ? kLdsTable / 2 : kLdsTable) / Jv;
-    if (ntu > 0) copy_lds(cub, tab, (ONE ? 1 : min(g, nt)) * Jv);
-    for (int32_t s0 = 0; s0 < ntu; s0 += g) {
-        const int32_t st = s0 / g, s1 = min(s0 + g, nt);
-        float4 *cur = tab;
-        if (dbuf) {
-            cur = tab + (st & 1) * (kLdsTable / 2);
-            __builtin_amdgcn_s_waitcnt(kWaitVm0);  // this stage's tables have landed (this lane's share)
-            __syncthreads();                        // ... every lane's; the previous stage is no longer read
-            if (s1 < nt)
-                copy_lds(cub + (size_t)s1 * Jv, tab + ((st + 1) & 1) * (kLdsTable / 2), min(g, nt - s1) * Jv);
-        } else {
-            if (s0 > 0) {
-                __syncthreads();  // the previous stage is no longer read
-                copy_lds(cub + (size_t)s0 * Jv, tab, (s1 - s0) * Jv);
+    // One segment t: the next segment's seeds are loaded, then hook() runs (it
+    // may start a copy: issued after those loads, it is not waited for with
+    // them), then the terms, with entry(i) the table interval i (byte offset
+    // i * 16 given as off).
+    auto segment = [&](int32_t t, auto hook, auto entry) {
+        const int32_t tn = min(t + 1, nt - 1);
+        const size_t o = (size_t)tn * (size_t)npix;
+        const __amdgpu_buffer_rsrc_t rg = seg_rsrc(gamma + o, npix), ru = seg_rsrc(U + o, npix);
+        const float an = ONE ? a[tn] : 1.0f;
+        float gpn[8], gqn[4];
+        uint32_t upn[8], uqn[4];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            gpn[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, po[i], 0, 0));
+            upn[i] = __builtin_amdgcn_raw_buffer_load_b32(ru, po[i], 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            gqn[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, qo[j], 0, 0));
+            uqn[j] = __builtin_amdgcn_raw_buffer_load_b32(ru, qo[j], 0, 0);
+        }
+        hook();
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            float4 c[4];
+            float x[4];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const uint32_t d = abs_diff(up[i], uq[jj]);
+                c[jj] = entry(d >> fb);
+                x[jj] = __uint_as_float(((d << (23 - fb)) & 0x007fffffu) | 0x3f800000u);
             }
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const float4 cc = c[jj];
+                const float W = fmaf(fmaf(fmaf(cc.w, x[jj], cc.z), x[jj], cc.y), x[jj], cc.x);
+                acc[i][jj] = fmaf(gp[i] * gq[jj], W, acc[i][jj]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            gp[i] = ONE ? an * gpn[i] : gpn[i];
+            up[i] = upn[i];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            gq[j] = gqn[j];
+            uq[j] = ucol(uqn[j]);
+        }
+    };
+    auto none = [] {};
+    if constexpr (ONE) {
+        __shared__ float4 tab[kLdsTable];
+        if (ntu > 0) {
+            copy_lds(cub, tab, Jv);
             __builtin_amdgcn_s_waitcnt(kWaitVm0);
             __syncthreads();
         }
-        for (int32_t t = s0; t < s1; ++t) {
-            // next segment's inputs (the last iteration re-reads segment nt - 1)
-            const int32_t tn = min(t + 1, nt - 1);
-            const size_t o = (size_t)tn * (size_t)npix;
-            const __amdgpu_buffer_rsrc_t rg = seg_rsrc(gamma + o, npix), ru = seg_rsrc(U + o, npix);
-            const float an = ONE ? a[tn] : 1.0f;
-            float gpn[8], gqn[4];
-            uint32_t upn[8], uqn[4];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                gpn[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, po[i], 0, 0));
-                upn[i] = __builtin_amdgcn_raw_buffer_load_b32(ru, po[i], 0, 0);
+        for (int32_t t = 0; t < ntu; ++t) segment(t, none, [](uint32_t i) { return tab[i]; });
+    } else {
+    __shared__ float4 tab0[kHalf], tab1[kHalf];
+    // a table longer than one array: intervals [0, kHalf) in tab0, the rest in tab1
+    auto split_entry = [](uint32_t i) { return i < (uint32_t)kHalf ? tab0[i] : tab1[i - kHalf]; };
+    auto copy_split = [&](const float4 *src) {
+        copy_lds(src, tab0, min(Jv, kHalf));
+        if (Jv > kHalf) copy_lds(src + kHalf, tab1, Jv - kHalf);
+    };
+    if (2 * Jv <= kLdsTable) {
+        // double-buffered stages of g tables each, tab0 and tab1 by turns
+        const int32_t g = kHalf / Jv;
+        auto stage = [&](int32_t s0, const float4 *cur, float4 *nxt) {
+            const int32_t s1 = min(s0 + g, nt);
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);  // this stage's tables have landed (this lane's share)
+            __syncthreads();                        // ... every lane's; the previous stage is no longer read
+            // the stage's first segment copies the next stage in, always (the
+            // last stage copies table 0 into the idle buffer), so that the
+            // count of copy instructions after its loads is known
+            const int32_t cs = s1 < nt ? s1 : 0, cn = s1 < nt ? min(g, nt - s1) * Jv : Jv;
+            segment(s0, [&] { copy_lds_half(cub + (size_t)cs * Jv, nxt, cn); }, [cur](uint32_t i) { return cur[i]; });
+            for (int32_t t = s0 + 1; t < s1; ++t) {
+                const float4 *tt = cur + (size_t)(t - s0) * Jv;
+                segment(t, none, [tt](uint32_t i) { return tt[i]; });
             }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                gqn[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, qo[j], 0, 0));
-                uqn[j] = __builtin_amdgcn_raw_buffer_load_b32(ru, qo[j], 0, 0);
-            }
-            const char *tb = reinterpret_cast<const char *>(ONE ? cur : cur + (size_t)(t - s0) * Jv);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                float4 c[4];
-                float x[4];
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const uint32_t d = abs_diff(up[i], uq[jj]);
-                    c[jj] = *reinterpret_cast<const float4 *>(tb + ((d >> fb) << 4));
-                    x[jj] = __uint_as_float(((d << (23 - fb)) & 0x007fffffu) | 0x3f800000u);
-                }
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const float4 cc = c[jj];
-                    const float W = fmaf(fmaf(fmaf(cc.w, x[jj], cc.z), x[jj], cc.y), x[jj], cc.x);
-                    acc[i][jj] = fmaf(gp[i] * gq[jj], W, acc[i][jj]);
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                gp[i] = ONE ? an * gpn[i] : gpn[i];
-                up[i] = upn[i];
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                gq[j] = gqn[j];
-                uq[j] = ucol(uqn[j]);
-            }
+        };
+        if (ntu > 0) copy_lds(cub, tab0, min(g, nt) * Jv);
+        for (int32_t s0 = 0; s0 < ntu; s0 += 2 * g) {
+            stage(s0, tab0, tab1);
+            if (s0 + g < ntu) stage(s0 + g, tab1, tab0);
         }
+    } else {
+        // one table at a time, spanning both arrays
+        for (int32_t t = 0; t < ntu; ++t) {
+            if (t > 0) __syncthreads();  // the previous table is no longer read
+            copy_split(cub + (size_t)t * Jv);
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            __syncthreads();
+            segment(t, none, split_entry);
+        }
+    }
     }
     if (!active) return;
 #pragma unroll
