@@ -235,8 +235,8 @@ int sgwb_fisher_overlap(const float *v, const float *u, const float *w, int64_t 
  *   w(t,c) = sum_{r < rank} a_r(t) b_r(c)
  * (rank 1: a per-segment noise factor times a per-bin spectral factor, which is
  * how w = H / P^2 factors when the noise spectrum keeps its shape across
- * segments; any w is a sum of min(nt, nf) such terms, e.g. from its singular
- * value decomposition):
+ * segments; weights of any other form, or of rank 2 and up, are better served
+ * by sgwb_fisher_full_general below):
  *   G(p,q) = sum_{c in [clo,chi)} H(c) sum_t w(t,c) gamma(t,p) gamma(t,q)
  *              cos 2 pi f_{k0+c} (tau(t,p) - tau(t,q))
  *          = sum_r sum_t a_r(t) gamma(t,p) gamma(t,q) Wd_r(tau(t,p) - tau(t,q)),
