@@ -523,6 +523,7 @@ def serving_sweep(args, torch, sg, rates, duration):
         # server
         t0 = time.perf_counter()
         tickets = {}
+        lag = {}  # ticket -> submission time minus arrival time, s (the loop submits up to a poll late)
         i = 0
         done = {}
         next_log = 10.0
@@ -532,6 +533,7 @@ def serving_sweep(args, torch, sg, rates, duration):
                 tk = srv.submit(*qs[i][1:])
                 if tk < 0:
                     break
+                lag[tk] = (time.perf_counter() - t0) - qs[i][0]
                 tickets[tk] = i
                 i += 1
             for tk in list(tickets):
@@ -545,7 +547,8 @@ def serving_sweep(args, torch, sg, rates, duration):
                 next_log += 10.0
             time.sleep(0.0002)
         assert all(r["status"] == 0 for r in done.values()), "a served query failed"
-        lat = np.array([r["t_done"] - r["t_submit"] for r in done.values()]) * 1e3
+        # from arrival, as the plain path's: the server's own submit-to-done time plus the submission lag
+        lat = np.array([r["t_done"] - r["t_submit"] + lag[tk] for tk, r in done.items()]) * 1e3
         span = max(r["t_done"] for r in done.values()) - min(r["t_submit"] for r in done.values())
         st = srv.stats()
         log(f"rate {rate}/s server: {len(qs)} queries, p50 {np.percentile(lat, 50):.1f} ms, "
