@@ -471,10 +471,10 @@ int sgwb_plan_describe(const sgwb_plan *plan, char *buf, size_t len);
  * hbm_budget_bytes (0: 60 % of the free memory) reserved at creation; queries
  * that arrive while others run are admitted as slots and memory free up, and
  * their kernels overlap on the device.  Admission is cost-aware: a query of at
- * least 1e10 map terms (segments x bins x pixels; SGWB_SERVER_HEAVY_TERMS in
+ * least 3e10 map terms (segments x bins x pixels; SGWB_SERVER_HEAVY_TERMS in
  * the environment overrides the threshold) fills the GPU alone, so at most
- * one such heavy query runs at a time and heavy queries start in arrival
- * order; lighter queries start in arrival order among themselves, run in the
+ * one such heavy query runs at a time (SGWB_SERVER_MAX_HEAVY, 1 to 64,
+ * overrides) and heavy queries start in arrival order; lighter queries start in arrival order among themselves, run in the
  * other slots beside it and may pass a heavy query that waits for its turn; a
  * query waiting for memory holds back every query behind it.  A query larger
  * than the whole arena fails with SGWB_ENOMEM; nothing is ever allocated

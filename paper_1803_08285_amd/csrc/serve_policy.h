@@ -8,8 +8,8 @@
 //
 // Admission is cost-aware.  A query's cost is its number of map terms
 // (segments x bins x pixels).  Heavy queries (cost >= the heavy threshold) fill
-// the whole GPU on their own, so at most one runs at a time and they start in
-// arrival order; light queries run beside it in the other slots, in arrival
+// the whole GPU on their own, so at most max_heavy (default one) run at a time
+// and they start in arrival order; light queries run beside it in the other slots, in arrival
 // order among themselves, and pass a heavy query that is waiting for the heavy
 // slot.  A heavy query therefore waits only for the heavy queries before it
 // (never behind a queue of light ones) and shares the GPU only with light
@@ -109,9 +109,11 @@ class Arena {
     std::map<size_t, size_t> sizes_;  // offset -> length of live blocks
 };
 
-// Default heavy threshold: 1e10 terms, about a quarter of a millisecond of the
-// whole GPU; queries above it have enough tiles to occupy every compute unit.
-constexpr double kHeavyTermsDefault = 1e10;
+// Default heavy threshold: 3e10 terms, about 0.8 ms of the whole GPU; queries
+// above it have enough tiles to occupy every compute unit for long enough that
+// letting them overlap only stretches both, while those below it finish
+// quickly enough to run beside a heavy one.
+constexpr double kHeavyTermsDefault = 3e10;
 
 struct PendingView {
     double cost;  // map terms
@@ -120,21 +122,23 @@ struct PendingView {
 
 struct RunningView {
     int free_slots;
-    bool heavy_running;
+    int heavy_running;  // heavy queries running now
 };
 
 enum : int { kAdmitNone = -1 };
 
 // Index (into pending, arrival order) of the query to start now, or kAdmitNone.
-// fits(i) says whether pending[i]'s footprint fits in the arena now.
+// fits(i) says whether pending[i]'s footprint fits in the arena now; at most
+// max_heavy heavy queries run at a time.
 template <class Fits>
-int pick_admission(const std::vector<PendingView> &pending, const RunningView &run, double heavy_terms, Fits fits)
+int pick_admission(const std::vector<PendingView> &pending, const RunningView &run, double heavy_terms, Fits fits,
+                   int max_heavy = 1)
 {
     if (run.free_slots <= 0) return kAdmitNone;
     bool heavy_seen = false;
     for (size_t i = 0; i < pending.size(); ++i) {
         const bool heavy = pending[i].cost >= heavy_terms;
-        if (heavy && (heavy_seen || run.heavy_running)) {
+        if (heavy && (heavy_seen || run.heavy_running >= max_heavy)) {
             heavy_seen = true;  // waits for the heavy slot; light queries may pass it
             continue;
         }

@@ -93,6 +93,7 @@ struct sgwb_server {
     std::atomic<bool> stop{false};
     Clock::time_point t0;
     double heavy_terms = serve::kHeavyTermsDefault;
+    int max_heavy = 1;  // heavy queries at a time
     // statistics
     uint64_t n_done = 0, n_failed = 0;
     double terms_done = 0.0;
@@ -242,14 +243,15 @@ void worker_loop(sgwb_server *s)
         // admit pending queries (serve_policy.h: cost-aware, see the header)
         for (;;) {
             int free_slot = -1, nfree = 0;
-            bool any_running = false, heavy_running = false;
+            bool any_running = false;
+            int heavy_running = 0;
             for (size_t k = 0; k < s->slots.size(); ++k) {
                 if (!s->slots[k].ticket) {
                     if (free_slot < 0) free_slot = (int)k;
                     ++nfree;
                 } else {
                     any_running = true;
-                    heavy_running = heavy_running || s->slots[k].heavy;
+                    heavy_running += s->slots[k].heavy ? 1 : 0;
                 }
             }
             if (free_slot < 0 || s->pending.empty()) break;
@@ -283,7 +285,8 @@ void worker_loop(sgwb_server *s)
                                                       return !any_running ||
                                                              (s->arena.size() - s->arena.used() >= n &&
                                                               s->arena.fits(n));
-                                                  });
+                                                  },
+                                                  s->max_heavy);
             if (idx == serve::kAdmitNone) break;
             const uint64_t ticket = s->pending[(size_t)idx];
             s->pending.erase(s->pending.begin() + idx);
@@ -366,6 +369,10 @@ int sgwb_server_create(const sgwb_server_cfg *cfg, sgwb_server **out)
     if (const char *e = getenv("SGWB_SERVER_HEAVY_TERMS")) {
         const double v = atof(e);
         if (v > 0.0) s->heavy_terms = v;
+    }
+    if (const char *e = getenv("SGWB_SERVER_MAX_HEAVY")) {
+        const int v = atoi(e);
+        if (v >= 1 && v <= 64) s->max_heavy = v;
     }
     int dev = 0;
     (void)hipGetDevice(&dev);

@@ -138,7 +138,7 @@ struct FakeQuery {
     char *mem = nullptr;
 };
 
-static void test_admission(unsigned seed, int slots)
+static void test_admission(unsigned seed, int slots, int max_heavy)
 {
     std::mt19937_64 rng(seed);
     std::uniform_real_distribution<double> U(0.0, 1.0);
@@ -179,19 +179,20 @@ static void test_admission(unsigned seed, int slots)
         while (next < qs.size() && qs[next].arrive <= now) pending.push_back(qs[next++].id);
         // admit
         for (;;) {
-            bool heavy_running = false;
-            for (int id : running) heavy_running = heavy_running || qs[id].cost >= heavy;
+            int heavy_running = 0;
+            for (int id : running) heavy_running += qs[id].cost >= heavy ? 1 : 0;
+            const bool heavy_full = heavy_running >= max_heavy;
             std::vector<sgwb::serve::PendingView> views;
             for (int id : pending) views.push_back({qs[id].cost, qs[id].need});
             const int idx = sgwb::serve::pick_admission(
                 views, sgwb::serve::RunningView{slots - (int)running.size(), heavy_running}, heavy,
-                [&](size_t i) { return arena.fits(views[i].need); });
+                [&](size_t i) { return arena.fits(views[i].need); }, max_heavy);
             if (idx == sgwb::serve::kAdmitNone) {
                 // nothing admissible: a free slot, memory and no heavy in the way
                 // would have admitted the head
                 if ((int)running.size() < slots && !pending.empty()) {
                     FakeQuery &h = qs[pending.front()];
-                    CHECK(!arena.fits(h.need) || (h.cost >= heavy && heavy_running));
+                    CHECK(!arena.fits(h.need) || (h.cost >= heavy && heavy_full));
                 }
                 break;
             }
@@ -200,7 +201,7 @@ static void test_admission(unsigned seed, int slots)
             FakeQuery &q = qs[id];
             // order: heavy after heavy, light after light
             if (q.cost >= heavy) {
-                CHECK(!heavy_running);
+                CHECK(!heavy_full);
                 CHECK(id > last_heavy_started);
                 last_heavy_started = id;
             } else {
@@ -208,7 +209,14 @@ static void test_admission(unsigned seed, int slots)
                 last_light_started = id;
             }
             // everything before it in the queue is a heavy one waiting for the heavy slot
-            for (int j = 0; j < idx; ++j) CHECK(qs[pending[(size_t)j]].cost >= heavy && heavy_running);
+            // (or, once the first waiting heavy one is passed over, any later heavy one)
+            bool heavy_blocked = false;
+            for (int j = 0; j < idx; ++j) {
+                const FakeQuery &w = qs[pending[(size_t)j]];
+                CHECK(w.cost >= heavy);
+                CHECK(heavy_full || heavy_blocked);
+                heavy_blocked = true;
+            }
             q.mem = arena.alloc(q.need);
             CHECK(q.mem != nullptr);
             q.start = now;
@@ -238,7 +246,8 @@ int main()
 {
     for (unsigned s = 1; s <= 6; ++s) test_arena(s);
     for (unsigned s = 1; s <= 6; ++s)
-        for (int slots : {1, 2, 4, 8}) test_admission(s, slots);
+        for (int slots : {1, 2, 4, 8})
+            for (int max_heavy : {1, 2}) test_admission(s, slots, max_heavy);
     if (failures) {
         fprintf(stderr, "%d checks failed\n", failures);
         return 1;
