@@ -480,7 +480,8 @@ def serving_sweep(args, torch, sg, rates, duration):
     workload; other rates for a sweep) against three resident baselines, through
     the continuous-batching server and through the plain per-query path (one
     query at a time, synchronous), same queries, same accuracy (the same
-    kernels: each served result is bitwise the direct call's)."""
+    kernels: each served result is bitwise the direct call's).  Both compute a
+    query's broadband maps alone (no narrowband map is written)."""
     dev = torch.device("cuda:0")
     datasets = []
     for i, bl in enumerate(("AB", "AC", "BC")):
@@ -509,7 +510,9 @@ def serving_sweep(args, torch, sg, rates, duration):
         if (ds, nside) not in geoms:
             geoms[(ds, nside)] = sg.build_geometry(d.sites, nside, d.tgrid, device=dev)
         g, t = geoms[(ds, nside)]
-        sg.make_maps_band(d.C[:, lo:hi], d.w[:, lo:hi], d.fgrid, d.k0 + lo, g, t, d.H[lo:hi].contiguous(), 0, hi - lo)
+        # the broadband maps alone, as the server computes them
+        sg.make_maps_band(d.C[:, lo:hi], d.w[:, lo:hi], d.fgrid, d.k0 + lo, g, t, d.H[lo:hi].contiguous(), 0, hi - lo,
+                          narrowband=False)
         torch.cuda.synchronize()
 
     for ds in range(3):  # warm the plain path's seeds too

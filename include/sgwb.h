@@ -372,12 +372,20 @@ int sgwb_reduce_band_f64(const double *X, const double *Gam, const double *H, in
  *     the band sum moved into the weights, float64 throughout, rounded once (the
  *     exact band-summed diagonal; sgwb_reduce_band of the split-bf16 Gam meets it
  *     within that map's 1e-4).
- * X and Xbb, Gam and Gbb come in pairs (either pair may be NULL, not both);
- * H[nf] is needed with Gbb.
+ * X needs Xbb and Gam needs Gbb; either pair may be NULL, not both.  The
+ * broadband maps may also come alone, without their narrowband map (X or Gam
+ * NULL):
+ *   Gbb alone runs only the weight-side sum above (no beam GEMM);
+ *   Xbb alone runs the matrix-core dirty map without writing any narrowband
+ *     row (only the strip sums), so it needs that form: SGWB_MAPS_ANTIPODAL,
+ *     df <= 0.0344 Hz and no vector-unit request, else SGWB_EINVAL.
+ * Either way the broadband maps are bitwise those of the call with the
+ * narrowband maps.  H[nf] is needed with Gbb.
  * Workspace: at least sgwb_make_maps_band_workspace_size() bytes, 256-byte
  * aligned, owned by the caller.
- * Errors: as sgwb_make_maps; SGWB_EINVAL also for unpaired outputs, a band
- * outside [0, nf] or a null H.                                               */
+ * Errors: as sgwb_make_maps; SGWB_EINVAL also for a narrowband map without
+ * its broadband map, no output at all, Xbb alone where the matrix-core form
+ * does not apply, a band outside [0, nf] or a null H.                        */
 size_t sgwb_make_maps_band_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint32_t flags);
 int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf,
                         const sgwb_fgrid *fg /*host*/, int64_t k0, const float *gamma, const double *tau,
@@ -457,8 +465,9 @@ int sgwb_plan_describe(const sgwb_plan *plan, char *buf, size_t len);
 
 /* ---- query server with continuous batching ------------------------------
  * Serves broadband maps (Sec. V) of a baseline, resolution and contiguous
- * band, from narrowband maps of that band (Eq. eq_dirtymap split per bin,
- * Eq. eq_fisher diagonal): folding makes the day's data small enough to stay
+ * band (Eq. eq_dirtymap split per bin and summed over the band, Eq. eq_fisher
+ * diagonal summed the same way; sgwb_make_maps_band with the broadband maps
+ * alone, so no narrowband map is kept): folding makes the day's data small enough to stay
  * resident (Sec. I), so every query reuses it and the cached seeds.
  * Datasets: the folded CSD C [nt][ldc] (interleaved complex float32), weights
  * w [nt][ldc] and shape H [nf] of one baseline, covering absolute bins
@@ -466,8 +475,8 @@ int sgwb_plan_describe(const sgwb_plan *plan, char *buf, size_t len);
  * unchanged until sgwb_server_destroy.  The seeds of each (dataset, nside)
  * are built on first use and kept.
  * A worker thread admits queries while one of `slots` HIP streams is free and
- * the query's footprint (two band x npix float32 maps, the beam and band
- * workspaces, the result, and new seeds) fits in an HBM arena of
+ * the query's footprint (the make_maps_band workspace, the two result
+ * maps, and new seeds) fits in an HBM arena of
  * hbm_budget_bytes (0: 60 % of the free memory) reserved at creation; queries
  * that arrive while others run are admitted as slots and memory free up, and
  * their kernels overlap on the device.  Admission is cost-aware: a query of at

@@ -325,12 +325,14 @@ def band_maps_workspace_bytes(nt: int, nf: int, npix: int, antipodal: bool = Tru
 def make_maps_band(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamma: torch.Tensor,
                    tau: torch.Tensor, H: torch.Tensor | None, k_lo: int, k_hi: int, antipodal: bool = True,
                    want_x: bool = True, want_gamma: bool = True, out=None, workspace: torch.Tensor | None = None,
-                   x_kernel: str = "auto", noalloc: bool = False):
+                   x_kernel: str = "auto", noalloc: bool = False, narrowband: bool = True):
     """make_maps and reduce_band over columns [k_lo, k_hi) in one call (float32):
     returns X, Gam [nf][npix] and Xbb, Gbb [npix] (None where not asked for).
-    noalloc=True calls sgwb_make_maps_band_noalloc (the library's fixed scratch
-    array instead of a workspace; pass preallocated outputs in ``out`` for a
-    call that allocates nothing at all)."""
+    narrowband=False computes the broadband maps alone (X and Gam None: no
+    narrowband row is written and no beam GEMM runs; the broadband bits are
+    those of the full call).  noalloc=True calls sgwb_make_maps_band_noalloc
+    (the library's fixed scratch array instead of a workspace; pass
+    preallocated outputs in ``out`` for a call that allocates nothing at all)."""
     if C.dim() != 2 or w.dim() != 2:
         raise SgwbError("C and w must be 2-D")
     nt, nf = w.shape
@@ -350,8 +352,8 @@ def make_maps_band(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamm
         _require_contig(H, "H")
     dev = C.device
     if out is None:
-        X = torch.empty((nf, npix), dtype=torch.float32, device=dev) if want_x else None
-        G = torch.empty((nf, npix), dtype=torch.float32, device=dev) if want_gamma else None
+        X = torch.empty((nf, npix), dtype=torch.float32, device=dev) if want_x and narrowband else None
+        G = torch.empty((nf, npix), dtype=torch.float32, device=dev) if want_gamma and narrowband else None
         Xbb = torch.empty(npix, dtype=torch.float32, device=dev) if want_x else None
         Gbb = torch.empty(npix, dtype=torch.float32, device=dev) if want_gamma else None
     else:

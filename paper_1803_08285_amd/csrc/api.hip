@@ -559,9 +559,9 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
                         void *workspace, size_t workspace_bytes, hipStream_t stream)
 {
     note_xform(SGWB_XFORM_NONE);
-    if (!X != !Xbb || !Gam != !Gbb)
-        return set_error(SGWB_EINVAL, "make_maps_band: X and Xbb, Gam and Gbb come in pairs");
-    if (!X && !Gam) return set_error(SGWB_EINVAL, "make_maps_band: nothing to compute");
+    if ((X && !Xbb) || (Gam && !Gbb))
+        return set_error(SGWB_EINVAL, "make_maps_band: X needs Xbb and Gam needs Gbb");
+    if (!Xbb && !Gbb) return set_error(SGWB_EINVAL, "make_maps_band: nothing to compute");
     if (Gbb && !H) return set_error(SGWB_EINVAL, "make_maps_band: null H");
     if (!(0 <= k_lo && k_lo <= k_hi && k_hi <= nf))
         return set_error(SGWB_EINVAL, "make_maps_band: band [%d, %d) not inside [0, %d]", k_lo, k_hi, nf);
@@ -581,11 +581,15 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
     double *vband = reinterpret_cast<double *>(ws + base + up256(rows_x * npix * sizeof(double)));
     const int32_t ncol = a.nside > 0 ? npix / 2 : npix;
     const size_t beam_bytes = up256(beam_workspace_bytes(nt, nf, ncol));
-    if (X) {
+    if (Xbb) {
         const bool use_xm =
             want_xm(a, flags, workspace, workspace_bytes, beam_bytes + xm_workspace_bytes(k0, nt, nf, npix),
                     "make_maps_band", &rc);
         if (rc) return rc;
+        if (!X && !use_xm)
+            return set_error(SGWB_EINVAL,
+                             "make_maps_band: Xbb without X needs the matrix-core dirty map (antipodal seeds, "
+                             "df <= 0.0344 Hz, no vector-unit request)");
         if (use_xm) {
             // the dirty map writes per-strip partial sums; one small kernel adds them
             MapArgs ab = a;
@@ -608,10 +612,12 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
         }
         if (rc) return rc;
     }
-    if (Gam) {
-        rc = check_hip(launch_beam_bf16x3(a, w, gamma, Gam, workspace, default_beam_shape(), stream),
-                       "beam kernel launch");
-        if (rc) return rc;
+    if (Gbb) {
+        if (Gam) {
+            rc = check_hip(launch_beam_bf16x3(a, w, gamma, Gam, workspace, default_beam_shape(), stream),
+                           "beam kernel launch");
+            if (rc) return rc;
+        }
         // Gbb from its definition, the band sum moved into the weights (no pass over Gam)
         rc = check_hip(launch_band_gamma(w, ldc, nt, H, k_lo, k_hi, gamma, npix, vband, Gbb, stream),
                        "band weights launch");

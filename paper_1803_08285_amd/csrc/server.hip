@@ -3,8 +3,10 @@
 // The folded CSD of every baseline stays resident (caller-owned device memory);
 // the seeds of each (baseline, nside) are built on first use and cached.  A
 // query names a baseline, a resolution and a contiguous band of bins; its
-// answer is the broadband pair Xbb, Gbb of that band (Sec. V), computed from
-// the narrowband maps of the band (Eqs. eq_dirtymap, eq_fisher split per bin).
+// answer is the broadband pair Xbb, Gbb of that band (Sec. V): the band sums
+// of the narrowband maps (Eqs. eq_dirtymap, eq_fisher split per bin), computed
+// without writing those maps (the dirty map's tiles add up their strips' rows,
+// and Gbb is the band-summed weights against gamma^2, so no beam GEMM runs).
 //
 // A worker thread owns the device side:
 //   * admission (serve_policy.h): cost-aware -- at most one heavy query (one
@@ -15,9 +17,9 @@
 //     made at creation, so serving never calls the device allocator);
 //   * each admitted query's kernels are queued on its slot's stream, so work of
 //     queries that arrive while others run overlaps on the device;
-//   * completion is detected with an event per slot; the narrowband buffers go
-//     back to the arena at once, the broadband pair when the caller releases
-//     the ticket.
+//   * completion is detected with an event per slot; the workspace goes back
+//     to the arena at once, the broadband pair when the caller releases the
+//     ticket.
 // Results do not depend on the mix: every kernel has a fixed summation order.
 #include <math.h>
 #include <stdlib.h>
@@ -61,8 +63,8 @@ struct Query {
     int status = SGWB_OK;
     int slot = -1;
     Clock::time_point t_submit, t_start, t_done;
-    char *X = nullptr, *G = nullptr, *ws = nullptr;  // narrowband buffers (arena)
-    float *Xbb = nullptr, *Gbb = nullptr;                             // result (arena)
+    char *ws = nullptr;                    // workspace (arena)
+    float *Xbb = nullptr, *Gbb = nullptr;  // result (arena)
     size_t ws_bytes = 0;
     int32_t npix = 0;
     double cost = 0.0;  // map terms: segments x bins x pixels
@@ -112,10 +114,9 @@ size_t query_footprint(const sgwb_server *s, const sgwb_query &q, size_t *ws_byt
     const sgwb_dataset &d = s->data[q.dataset];
     const int64_t npix = 12LL * q.nside * q.nside;
     const int32_t nf = q.k_hi - q.k_lo;
-    const size_t maps = (size_t)nf * npix * sizeof(float);
     *ws_bytes = sgwb_make_maps_band_workspace_size(d.tg.nt, nf, (int32_t)npix, SGWB_MAPS_ANTIPODAL);
     auto up = [](size_t n) { return (n + 255) / 256 * 256; };
-    return 2 * up(maps) + up(*ws_bytes) + 2 * up(npix * sizeof(float));
+    return up(*ws_bytes) + 2 * up(npix * sizeof(float));
 }
 
 size_t geom_bytes(const sgwb_dataset &d, int nside)
@@ -183,20 +184,18 @@ int launch_query(sgwb_server *s, Query &q, int k)
         return check_hip(hipGetLastError(), "server: wait for seeds");
     const int32_t nf = q.q.k_hi - q.q.k_lo;
     const int32_t npix = g->npix;
-    const size_t maps = (size_t)nf * npix * sizeof(float);
-    q.X = s->arena.alloc(maps);
-    q.G = s->arena.alloc(maps);
     q.ws = s->arena.alloc(q.ws_bytes);
     q.Xbb = reinterpret_cast<float *>(s->arena.alloc(npix * sizeof(float)));
     q.Gbb = reinterpret_cast<float *>(s->arena.alloc(npix * sizeof(float)));
-    if (!q.X || !q.G || !q.ws || !q.Xbb || !q.Gbb)
+    if (!q.ws || !q.Xbb || !q.Gbb)
         return set_error(SGWB_ENOMEM, "server: arena exhausted");
     q.npix = npix;
     const float *C = d.C + 2 * (int64_t)q.q.k_lo;
     const float *w = d.w + q.q.k_lo;
+    // the broadband maps alone: no narrowband row is written and no beam GEMM runs
     rc = sgwb_make_maps_band(C, w, d.ldc, d.tg.nt, nf, &d.fg, d.k0 + q.q.k_lo, g->gamma, g->tau, npix,
-                             SGWB_MAPS_ANTIPODAL, d.H + q.q.k_lo, 0, nf, reinterpret_cast<float *>(q.X),
-                             reinterpret_cast<float *>(q.G), q.Xbb, q.Gbb, q.ws, q.ws_bytes, sl.stream);
+                             SGWB_MAPS_ANTIPODAL, d.H + q.q.k_lo, 0, nf, nullptr, nullptr, q.Xbb, q.Gbb, q.ws,
+                             q.ws_bytes, sl.stream);
     if (rc) return rc;
     if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return check_hip(hipGetLastError(), "server: record");
     sl.ticket = q.ticket;
@@ -206,12 +205,10 @@ int launch_query(sgwb_server *s, Query &q, int k)
     return SGWB_OK;
 }
 
-void release_narrowband(sgwb_server *s, Query &q)
+void release_workspace(sgwb_server *s, Query &q)
 {
-    s->arena.release(q.X);
-    s->arena.release(q.G);
     s->arena.release(q.ws);
-    q.X = q.G = q.ws = nullptr;
+    q.ws = nullptr;
 }
 
 void worker_loop(sgwb_server *s)
@@ -234,7 +231,7 @@ void worker_loop(sgwb_server *s)
                 s->n_done++;
                 s->terms_done += (double)s->data[q.q.dataset].tg.nt * (q.q.k_hi - q.q.k_lo) * q.npix;
             }
-            release_narrowband(s, q);
+            release_workspace(s, q);
             sl.ticket = 0;
             sl.heavy = false;
             progressed = true;
@@ -296,7 +293,7 @@ void worker_loop(sgwb_server *s)
                 // kernels of this query may already be queued on the slot's
                 // stream (seeds, maps): let them finish before the blocks go back
                 (void)hipStreamSynchronize(s->slots[free_slot].stream);
-                release_narrowband(s, q);
+                release_workspace(s, q);
                 s->arena.release(reinterpret_cast<char *>(q.Xbb));
                 s->arena.release(reinterpret_cast<char *>(q.Gbb));
                 q.Xbb = q.Gbb = nullptr;

@@ -224,7 +224,15 @@ def test_make_maps_band_validation_on_the_host():
     # X without Xbb
     rc = L.sgwb_make_maps_band(d, d, 8, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1, d, 0, 8, d, None, None, None, d,
                                big, None)
-    assert rc == -1 and b"pairs" in L.sgwb_last_error()
+    assert rc == -1 and b"X needs Xbb" in L.sgwb_last_error()
+    # Xbb alone needs the matrix-core dirty map: refused with a vector-unit request, or at df = 1/4 Hz
+    rc = L.sgwb_make_maps_band(d, d, 8, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1 | 2, d, 0, 8, None, None, d, d, d,
+                               big, None)
+    assert rc == -1 and b"matrix-core" in L.sgwb_last_error()
+    coarse = sg._FGrid(20.0, 0.25)
+    rc = L.sgwb_make_maps_band(d, d, 8, 10, 8, ctypes.byref(coarse), 0, d, d, 768, 1, d, 0, 8, None, None, d, None,
+                               d, big, None)
+    assert rc == -1 and b"matrix-core" in L.sgwb_last_error()
     # nothing asked for
     rc = L.sgwb_make_maps_band(d, d, 8, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1, d, 0, 8, None, None, None, None,
                                d, big, None)

@@ -81,6 +81,44 @@ def test_fused_band_maps_single_outputs_and_determinism(sg):
     assert torch.equal(X, X3) and torch.equal(G, G3) and torch.equal(Xbb, Xbb3) and torch.equal(Gbb, Gbb3)
 
 
+@pytest.mark.parametrize("case", [c for c in CASES if c[7] and c[6] <= 1 / 32 and c[8] == "auto"],
+                         ids=lambda c: f"{c[0]}-{c[1]}-{c[3]}-{c[5]}")
+def test_broadband_alone_bitwise_and_vs_oracle(sg, oracle_mod, case):
+    """The broadband maps alone (no narrowband map written, no beam GEMM) are
+    bitwise those of the call with the narrowband maps, and Xbb meets the FP64
+    oracle's band-summed dirty map within 1e-5 of its band-summed scale."""
+    bl, nside, nt, k0, nf, (klo, khi), df, anti, xk = case
+    g, t, C, w, H = _setup(sg, bl, nside, nt, k0, nf, df, 70 + nside)
+    fg = sg.FGrid(F0, df)
+    X, G, Xbb, Gbb = sg.make_maps_band(C, w, fg, k0, g, t, H, klo, khi)
+    X0, G0, Xbb0, Gbb0 = sg.make_maps_band(C, w, fg, k0, g, t, H, klo, khi, narrowband=False)
+    _, _, Xbb1, _ = sg.make_maps_band(C, w, fg, k0, g, t, None, klo, khi, want_gamma=False, narrowband=False)
+    _, _, _, Gbb2 = sg.make_maps_band(C, w, fg, k0, g, t, H, klo, khi, want_x=False, narrowband=False)
+    torch.cuda.synchronize()
+    assert X0 is None and G0 is None
+    assert torch.equal(Xbb, Xbb0) and torch.equal(Gbb, Gbb0)
+    assert torch.equal(Xbb, Xbb1) and torch.equal(Gbb, Gbb2)
+    Xo, _, S = oracle_mod.maps(C.cpu().numpy(), w.cpu().numpy(), F0, df, k0, g.cpu().numpy(), t.cpu().numpy(),
+                               with_scale=True)
+    Sb = S[klo:khi].sum(axis=0)
+    err = np.abs(Xbb0.cpu().numpy().astype(np.float64) - Xo[klo:khi].sum(axis=0))
+    assert np.all(err <= 1e-5 * Sb + 1e-300)
+
+
+def test_broadband_alone_needs_the_matrix_core_form(sg):
+    g, t, C, w, H = _setup(sg, "AB", 4, 20, 0, 64, 1 / 32, 3)
+    fg = sg.FGrid(F0, 1 / 32)
+    with pytest.raises(sg.SgwbError, match="matrix-core"):
+        sg.make_maps_band(C, w, fg, 0, g, t, H, 0, 64, x_kernel="valu", narrowband=False)
+    with pytest.raises(sg.SgwbError, match="matrix-core"):
+        sg.make_maps_band(C, w, fg, 0, g, t, H, 0, 64, antipodal=False, narrowband=False)
+    # the beam's broadband map alone needs no particular form
+    _, _, _, Gbb = sg.make_maps_band(C, w, fg, 0, g, t, H, 0, 64, antipodal=False, want_x=False, narrowband=False)
+    _, _, _, Gref = sg.make_maps_band(C, w, fg, 0, g, t, H, 0, 64, antipodal=False, want_x=False)
+    torch.cuda.synchronize()
+    assert torch.equal(Gbb, Gref)
+
+
 def test_fused_band_maps_rejects_bad_arguments(sg):
     g, t, C, w, H = _setup(sg, "AB", 4, 20, 0, 64, 1 / 32, 3)
     fg = sg.FGrid(F0, 1 / 32)

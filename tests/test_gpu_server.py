@@ -129,8 +129,9 @@ def test_server_rejects_bad_queries_before_device_work(sg, datasets):
 
 
 def test_server_fails_oversized_query_and_keeps_serving(sg, datasets):
-    # arena of 8 MiB: an nside-16 full-band query needs far more (two 1500 x 3072 maps)
-    srv = sg.Server(datasets, slots=2, hbm_budget_bytes=8 << 20)
+    # arena of 4 MiB: an nside-16 full-band query needs more (its workspace alone is 5.7 MiB)
+    assert sg.band_maps_workspace_bytes(NT, NF, 3072, True) > 4 << 20
+    srv = sg.Server(datasets, slots=2, hbm_budget_bytes=4 << 20)
     big = srv.submit(0, 16, 0, NF)
     small = srv.submit(1, 1, 0, 20)
     res = _wait(srv, [big, small])
