@@ -558,6 +558,34 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
                         const float *H, int32_t k_lo, int32_t k_hi, float *X, float *Gam, float *Xbb, float *Gbb,
                         void *workspace, size_t workspace_bytes, hipStream_t stream)
 {
+    return sgwb::make_maps_band_seeded(C, w, ldc, nt, nf, fg, k0, gamma, tau, npix, flags, H, k_lo, k_hi, X, Gam, Xbb,
+                                       Gbb, workspace, workspace_bytes, nullptr, stream);
+}
+
+}  // extern "C"
+
+namespace sgwb {
+
+int seed_products(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
+                  int64_t k0, const float *gamma, const double *tau, int32_t npix, void *seeds, hipStream_t stream,
+                  bool *made)
+{
+    *made = false;
+    MapArgs a;
+    int rc = check_maps_args<float>(C, w, ldc, nt, nf, fg, k0, gamma, tau, npix, SGWB_MAPS_ANTIPODAL, &a);
+    if (rc) return rc;
+    if (!xm_eligible(a) || x_kernel_choice() == kXKernelValu) return SGWB_OK;  // no matrix-core form to prepare for
+    if (!seeds || (uintptr_t)seeds % 256) return set_error(SGWB_EINVAL, "seed products: buffer null or misaligned");
+    rc = check_hip(launch_xm_seed_products(a, gamma, tau, seeds, stream), "seed products launch");
+    if (!rc) *made = true;
+    return rc;
+}
+
+int make_maps_band_seeded(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
+                          int64_t k0, const float *gamma, const double *tau, int32_t npix, uint32_t flags,
+                          const float *H, int32_t k_lo, int32_t k_hi, float *X, float *Gam, float *Xbb, float *Gbb,
+                          void *workspace, size_t workspace_bytes, const void *seeds, hipStream_t stream)
+{
     note_xform(SGWB_XFORM_NONE);
     if ((X && !Xbb) || (Gam && !Gbb))
         return set_error(SGWB_EINVAL, "make_maps_band: X needs Xbb and Gam needs Gbb");
@@ -597,7 +625,7 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
             ab.band_lo = k_lo;
             ab.band_hi = k_hi;
             const double *rec = nullptr;
-            rc = check_hip(launch_dirty_map_mfma(ab, C, w, gamma, tau, X, ws + beam_bytes, stream, &rec),
+            rc = check_hip(launch_dirty_map_mfma(ab, C, w, gamma, tau, X, ws + beam_bytes, stream, &rec, seeds),
                            "dirty-map (matrix cores) launch");
             if (rc) return rc;
             note_xform(kXFormDevice, rec, stream);
@@ -625,6 +653,10 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
     }
     return SGWB_OK;
 }
+
+}  // namespace sgwb
+
+extern "C" {
 
 size_t sgwb_reduce_band_workspace_size(int32_t npix, int32_t k_lo, int32_t k_hi)
 {

@@ -50,6 +50,8 @@ using serve::Arena;
 struct Geom {
     float *gamma = nullptr;
     double *tau = nullptr;
+    char *seeds = nullptr;  // seed-side products of the matrix-core dirty map
+    bool seeded = false;    // seeds holds them (a matrix-core form applies)
     hipEvent_t ready = nullptr;
     int32_t npix = 0;
 };
@@ -123,10 +125,12 @@ size_t geom_bytes(const sgwb_dataset &d, int nside)
 {
     const size_t npix = 12ull * nside * nside;
     auto up = [](size_t n) { return (n + 255) / 256 * 256; };
-    return up(npix * d.tg.nt * sizeof(float)) + up(npix * d.tg.nt * sizeof(double));
+    return up(npix * d.tg.nt * sizeof(float)) + up(npix * d.tg.nt * sizeof(double)) +
+           up(xm_seed_bytes(d.tg.nt, (int32_t)npix));
 }
 
-// Build (or find) the seeds of (dataset, nside); queued on stream st.
+// Build (or find) the seeds of (dataset, nside) and the dirty map's seed-side
+// products (its form record and Bessel amplitudes), once; queued on stream st.
 int ensure_geometry(sgwb_server *s, int ds, int nside, hipStream_t st, Geom **out)
 {
     auto key = std::make_pair(ds, nside);
@@ -140,12 +144,17 @@ int ensure_geometry(sgwb_server *s, int ds, int nside, hipStream_t st, Geom **ou
     g.npix = 12 * nside * nside;
     g.gamma = reinterpret_cast<float *>(s->arena.alloc((size_t)g.npix * d.tg.nt * sizeof(float)));
     g.tau = reinterpret_cast<double *>(s->arena.alloc((size_t)g.npix * d.tg.nt * sizeof(double)));
-    if (!g.gamma || !g.tau) {
+    g.seeds = s->arena.alloc(xm_seed_bytes(d.tg.nt, g.npix));
+    if (!g.gamma || !g.tau || !g.seeds) {
         s->arena.release(reinterpret_cast<char *>(g.gamma));
         s->arena.release(reinterpret_cast<char *>(g.tau));
+        s->arena.release(g.seeds);
         return set_error(SGWB_ENOMEM, "server: no room for the seeds of dataset %d at nside %d", ds, nside);
     }
     int rc = sgwb_build_geometry(&d.bl, nside, &d.tg, g.gamma, g.tau, st);
+    if (!rc)
+        rc = seed_products(d.C, d.w, d.ldc, d.tg.nt, d.nf, &d.fg, d.k0, g.gamma, g.tau, g.npix, g.seeds, st,
+                           &g.seeded);
     if (!rc && (hipEventCreateWithFlags(&g.ready, hipEventDisableTiming) != hipSuccess ||
                 hipEventRecord(g.ready, st) != hipSuccess))
         rc = check_hip(hipGetLastError(), "server: geometry event");
@@ -156,6 +165,7 @@ int ensure_geometry(sgwb_server *s, int ds, int nside, hipStream_t st, Geom **ou
         if (g.ready) (void)hipEventDestroy(g.ready);
         s->arena.release(reinterpret_cast<char *>(g.gamma));
         s->arena.release(reinterpret_cast<char *>(g.tau));
+        s->arena.release(g.seeds);
         return rc;
     }
     auto ins = s->geoms.emplace(key, g);
@@ -192,10 +202,11 @@ int launch_query(sgwb_server *s, Query &q, int k)
     q.npix = npix;
     const float *C = d.C + 2 * (int64_t)q.q.k_lo;
     const float *w = d.w + q.q.k_lo;
-    // the broadband maps alone: no narrowband row is written and no beam GEMM runs
-    rc = sgwb_make_maps_band(C, w, d.ldc, d.tg.nt, nf, &d.fg, d.k0 + q.q.k_lo, g->gamma, g->tau, npix,
-                             SGWB_MAPS_ANTIPODAL, d.H + q.q.k_lo, 0, nf, nullptr, nullptr, q.Xbb, q.Gbb, q.ws,
-                             q.ws_bytes, sl.stream);
+    // the broadband maps alone: no narrowband row is written and no beam GEMM
+    // runs; the dirty map's seed-side products come from the geometry cache
+    rc = make_maps_band_seeded(C, w, d.ldc, d.tg.nt, nf, &d.fg, d.k0 + q.q.k_lo, g->gamma, g->tau, npix,
+                               SGWB_MAPS_ANTIPODAL, d.H + q.q.k_lo, 0, nf, nullptr, nullptr, q.Xbb, q.Gbb, q.ws,
+                               q.ws_bytes, g->seeded ? g->seeds : nullptr, sl.stream);
     if (rc) return rc;
     if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return check_hip(hipGetLastError(), "server: record");
     sl.ticket = q.ticket;

@@ -202,7 +202,25 @@ size_t xm_workspace_bytes(int64_t k0, int32_t nt, int32_t nf, int32_t npix);
 // form_rec (optional out): device address of the call's form record
 hipError_t launch_dirty_map_mfma(const MapArgs &a, const float *C, const float *w, const float *gamma,
                                  const double *tau, float *X, void *work, hipStream_t s,
-                                 const double **form_rec = nullptr);
+                                 const double **form_rec = nullptr, const void *seeds = nullptr);
+// The seed-side products of the matrix-core dirty map (form record and Bessel
+// amplitudes) depend on gamma, tau and df alone: a caller that keeps seeds
+// resident computes them once into a buffer of xm_seed_bytes() and passes it
+// as `seeds` above, which then skips their preparation.
+size_t xm_seed_bytes(int32_t nt, int32_t npix);
+hipError_t launch_xm_seed_products(const MapArgs &a, const float *gamma, const double *tau, void *seeds,
+                                   hipStream_t s);
+// sgwb_make_maps_band with the seed-side products of the matrix-core dirty map
+// taken from `seeds` (nullptr: prepared in the workspace, as the C-ABI call
+// does); seed_products fills such a buffer for resident seeds (*made false
+// where no matrix-core form applies, and the buffer is then not used).
+int make_maps_band_seeded(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
+                          int64_t k0, const float *gamma, const double *tau, int32_t npix, uint32_t flags,
+                          const float *H, int32_t k_lo, int32_t k_hi, float *X, float *Gam, float *Xbb, float *Gbb,
+                          void *workspace, size_t workspace_bytes, const void *seeds, hipStream_t stream);
+int seed_products(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
+                  int64_t k0, const float *gamma, const double *tau, int32_t npix, void *seeds, hipStream_t stream,
+                  bool *made);
 struct XmArgs {
     MapArgs a;
     int64_t strip_first, nstrips, nchunks;
