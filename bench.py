@@ -404,6 +404,67 @@ def bench_fisher_full(args, torch, sg):
           flush=True)
 
 
+PEAK_HBM_TBPS = 8.0  # MI355X HBM3E
+
+
+def bench_network(args, torch, sg):
+    """Network sum over the three baselines AB, AC, BC (the sum over I of
+    Eq. eq:narrowband) of their narrowband dirty maps, then the isotropic and a
+    directed contraction (Sec. V) of the summed map, for --workload.  The maps
+    are the library's own dirty maps of each baseline's synthetic data."""
+    dev = torch.device("cuda:0")
+    maps = []
+    for i, bl in enumerate(("AB", "AC", "BC")):
+        wl = synth.workload(args.workload, baseline=bl)
+        wl.noise_seed += i  # each baseline its own noise
+        tg, fgd = wl.tgrid, wl.fgrid
+        npix = 12 * wl.nside ** 2
+        inp = make_inputs(sg, torch, wl, dev)
+        X, _ = sg.make_maps(inp["C"], inp["w"], sg.FGrid(fgd.f0, fgd.df), fgd.k0, inp["gamma"], inp["tau"],
+                            want_gamma=False)
+        maps.append(X)
+        del inp
+        torch.cuda.empty_cache()
+        log(f"dirty map of {bl} ready")
+    nf = maps[0].shape[0]
+    out = torch.empty_like(maps[0])
+    # a directed search's pixel set: the pixels within 5 degrees of a direction
+    c, _ = sg.healpix_centres(wl.nside, device=dev)
+    d = torch.tensor([0.3, -0.5, 0.81], dtype=torch.float64, device=dev)
+    pix = torch.nonzero((c @ (d / d.norm())) >= np.cos(np.radians(5.0))).flatten().to(torch.int32)
+    iso = torch.empty(nf, dtype=torch.float32, device=dev)
+    dire = torch.empty(nf, dtype=torch.float32, device=dev)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    t_sum = timed(lambda: sg.network_sum(maps, out=out), args.steps)
+    t_iso = timed(lambda: sg.contract_pixels(out, None, out=iso), args.steps)
+    t_dir = timed(lambda: sg.contract_pixels(out, pix, out=dire), args.steps)
+    n = out.numel()
+    sum_bytes = (len(maps) + 1) * n * 4
+    gbps = sum_bytes / (t_sum * 1e-3) / 1e9
+    log(f"network sum of {len(maps)} maps ({n} values each): {t_sum:.3f} ms, {gbps:.0f} GB/s; isotropic contraction "
+        f"{t_iso:.3f} ms; directed contraction over {pix.numel()} pixels {t_dir:.3f} ms")
+    print(json.dumps({"metric": "network sum GB/s (HBM bytes read + written)", "value": gbps, "unit": "GB/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": t_sum, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f32 maps, f64 sums", "data": "synthetic",
+                      "config": {"workload": wl.name + "_network_sum", "baselines": 3, "nf": nf,
+                                 "npix": int(out.shape[1]), "parallelism": "single GPU"},
+                      "roofline": {"bound": "hbm", "achieved": gbps, "peak": PEAK_HBM_TBPS * 1e3, "unit": "GB/s",
+                                   "frac": gbps / (PEAK_HBM_TBPS * 1e3), "traffic": None},
+                      "isotropic_contraction": {"ms": t_iso, "GBps": n * 4 / (t_iso * 1e-3) / 1e9},
+                      "directed_contraction": {"ms": t_dir, "pixels": int(pix.numel())}}), flush=True)
+
+
 def bench_folded(args, torch, sg):
     """Folded pipeline over --days synthetic sidereal days of the full band: fold
     (v, u, w, x), dirty map of x, overlap-corrected Fisher diagonal, band sums."""
@@ -618,6 +679,8 @@ def main():
     ap.add_argument("--days", type=int, default=10)
     ap.add_argument("--fisher-overlap", action="store_true",
                     help="overlap-corrected Fisher diagonal over the full band of --workload")
+    ap.add_argument("--network", action="store_true",
+                    help="network sum of three baselines' narrowband maps and the contractions, for --workload")
     ap.add_argument("--fisher-full", action="store_true",
                     help="full Fisher matrix of the whole band and the CG clean map for --workload")
     ap.add_argument("--cg-iters", type=int, default=50)
@@ -657,6 +720,9 @@ def main():
         return
     if args.fisher_full:
         bench_fisher_full(args, torch, sg)
+        return
+    if args.network:
+        bench_network(args, torch, sg)
         return
     wl = synth.workload(args.workload)
     tg, fgd = wl.tgrid, wl.fgrid

@@ -88,16 +88,16 @@ def workload(cfg: int, baseline: str = "AB") -> Workload:
     """The named workloads: 1 tiny, 2 full band nside 32, 3 full band nside 64,
     4 the batched jobs (use ``batched_jobs``)."""
     if cfg == 1:
-        return Workload("tiny", "AB", 8, TGRID_TINY, FGrid(20.0, 0.25, 1024), 1, [100], [0.1])
+        return Workload("tiny", baseline, 8, TGRID_TINY, FGrid(20.0, 0.25, 1024), 1, [100], [0.1])
     if cfg == 2:
         pix, amp = _sources(2, 12 * 32 * 32)
-        return Workload("full_band_nside32", "AB", 32, TGRID_FULL, FGrid(20.0, 1 / 32, 54592), 2, pix, amp)
+        return Workload("full_band_nside32", baseline, 32, TGRID_FULL, FGrid(20.0, 1 / 32, 54592), 2, pix, amp)
     if cfg == 3:
         # Same data as workload 2: the source directions are the nside-32 pixel
         # centres; at nside 64 the caller injects them at the nearest nside-64
         # centre.
         pix, amp = _sources(2, 12 * 32 * 32)
-        return Workload("full_band_nside64", "AB", 64, TGRID_FULL, FGrid(20.0, 1 / 32, 54592), 2, pix, amp)
+        return Workload("full_band_nside64", baseline, 64, TGRID_FULL, FGrid(20.0, 1 / 32, 54592), 2, pix, amp)
     raise ValueError(cfg)
 
 

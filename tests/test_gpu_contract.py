@@ -29,6 +29,20 @@ def test_network_sum_vs_oracle(sg, oracle_mod):
     assert np.all(np.abs(out - ref) <= 2.0 ** -23 * scale)
 
 
+@pytest.mark.parametrize("shape,offset", [((5, 7), 0), ((33, 3072), 1), ((4, 4096), 0)])
+def test_network_sum_scalar_and_vector_paths(sg, oracle_mod, shape, offset):
+    """Sizes not a multiple of 4 and maps not 16-byte aligned take the scalar
+    kernel, the rest the 16-byte one; both give the oracle's float64 sums."""
+    rng = np.random.default_rng(shape[1] + offset)
+    n = shape[0] * shape[1]
+    maps = [rng.standard_normal(n + offset).astype(np.float32) for _ in range(4)]
+    dev = [torch.from_numpy(m).cuda()[offset:] for m in maps]
+    out = sg.network_sum(dev).cpu().numpy()
+    ref = oracle_mod.network_sum([m[offset:] for m in maps])
+    scale = oracle_mod.network_sum([np.abs(m[offset:]) for m in maps])
+    assert np.all(np.abs(out - ref) <= 2.0 ** -23 * scale)
+
+
 @pytest.mark.parametrize("npix,sel", [(768, [100]), (12288, [5, 77, 4000, 12287]), (3072, None), (49152, None)])
 def test_contractions_vs_oracle(sg, oracle_mod, npix, sel):
     rng = np.random.default_rng(npix)
