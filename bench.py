@@ -609,7 +609,10 @@ def serving_sweep(args, torch, sg, rates, duration):
             if now >= next_log:
                 log(f"rate {rate}/s server: {now:.0f} s, {len(done)}/{len(qs)} queries done")
                 next_log += 10.0
-            time.sleep(0.0002)
+            # sleep until the next arrival, at most 0.1 ms (results are polled meanwhile)
+            wait = (qs[i][0] - (time.perf_counter() - t0)) if i < len(qs) else 1e-4
+            if wait > 0:
+                time.sleep(min(wait, 1e-4))
         assert all(r["status"] == 0 for r in done.values()), "a served query failed"
         # from arrival, as the plain path's: the server's own submit-to-done time plus the submission lag
         lat = np.array([r["t_done"] - r["t_submit"] + lag[tk] for tk, r in done.items()]) * 1e3
