@@ -73,6 +73,66 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def sample_power(torch, step, seconds=4.0):
+    """Package power and shader clocks while the step runs back to back for
+    `seconds` (untimed, after the timed region): amd-smi is sampled from a
+    thread; the cap comes from rocm-smi.  None where the tools are missing or
+    print nothing usable."""
+    import re
+    import shutil
+    import subprocess
+    import threading
+
+    smi = shutil.which("amd-smi")
+    if not smi:
+        return None
+    samples, stop = [], threading.Event()
+
+    def sampler():
+        while not stop.is_set():
+            try:
+                r = subprocess.run([smi, "metric", "--power", "--clock", "-g", "0", "--csv"], capture_output=True,
+                                   text=True, timeout=10)
+                lines = [l for l in r.stdout.splitlines() if l.strip()]
+                head = next((l.split(",") for l in lines if l.startswith("gpu,")), None)
+                row = next((l.split(",") for l in reversed(lines) if l[:1].isdigit()), None)
+                if head and row and len(row) == len(head):
+                    clk = [float(row[i]) for i, h in enumerate(head) if re.fullmatch(r"gfx_\d+_clk", h)]
+                    samples.append((float(row[head.index("socket_power")]), sum(clk) / len(clk) if clk else None))
+            except (OSError, ValueError, subprocess.SubprocessError):
+                pass
+            time.sleep(0.05)
+
+    th = threading.Thread(target=sampler, daemon=True)
+    th.start()
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        step()
+        torch.cuda.synchronize()
+        n += 1
+    stop.set()
+    th.join(timeout=15)
+    if len(samples) < 3:
+        return None
+    # the first samples may predate the load
+    pw = [x[0] for x in samples[1:]]
+    ck = [x[1] for x in samples[1:] if x[1] is not None]
+    cap = None
+    rs = shutil.which("rocm-smi")
+    if rs:
+        try:
+            r = subprocess.run([rs, "--showmaxpower"], capture_output=True, text=True, timeout=20)
+            m = re.search(r"Max Graphics Package Power \(W\):\s*([0-9.]+)", r.stdout)
+            cap = float(m.group(1)) if m else None
+        except (OSError, subprocess.SubprocessError):
+            cap = None
+    return {"socket_power_w_median": float(np.median(pw)), "socket_power_w_max": float(np.max(pw)),
+            "power_cap_w": cap, "shader_clock_mhz_median": float(np.median(ck)) if ck else None,
+            "samples": len(pw), "steps_run": n, "seconds": seconds,
+            "how": "amd-smi metric --power --clock while the step ran back to back, untimed"}
+
+
 def make_inputs(sg, torch, wl, dev):
     tg, fgd = wl.tgrid, wl.fgrid
     gamma, tau = sg.build_geometry(synth.baseline_sites(wl.baseline), wl.nside,
@@ -672,6 +732,7 @@ def main():
     ap.add_argument("--workload", type=int, default=3, help="3: full band nside 64 (default); 2: full band nside 32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-errors", action="store_true", help="skip the per-result errors against the oracle")
+    ap.add_argument("--no-power", action="store_true", help="skip the untimed package-power sample")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="serving leg of the default run: Poisson queries at 200/s for this long (0: none)")
     ap.add_argument("--batched", action="store_true", help="batched plan of three uneven baseline jobs")
@@ -794,6 +855,12 @@ def main():
                     "traffic": None, "flops_per_term": X_FLOPS_PER_TERM, "x_form": x_form,
                     "launch_ms": float(t_x.mean())}
 
+    power = None
+    if not args.no_power:
+        log("package power while the step runs back to back (untimed)")
+        power = sample_power(torch, step)
+        log(f"power: {power}")
+
     if args.copy_calib_mib:
         nbytes = args.copy_calib_mib << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
@@ -849,6 +916,7 @@ def main():
         "step_latency_ms": {"p50": float(np.percentile(t_step, 50)), "p99": float(np.percentile(t_step, 99))},
         "errors_vs_oracle": errors,
         "cpu_baseline": cpu,
+        "power": power,
     }
     if batched:
         out["batched"] = batched
