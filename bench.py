@@ -157,13 +157,20 @@ def make_inputs(sg, torch, wl, dev):
 
 
 def cpu_model() -> str:
+    """The first processor's model name, with its family / model / stepping
+    numbers (virtual machines often report only a generic name)."""
+    fields = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if not line.strip():
+                break
+            k, _, v = line.partition(":")
+            fields[k.strip()] = v.strip()
     except OSError:
         pass
-    return "unknown"
+    name = fields.get("model name", "unknown")
+    ids = [f"{k} {fields[k]}" for k in ("cpu family", "model", "stepping") if k in fields]
+    return f"{name} ({', '.join(ids)})" if ids else name
 
 
 def cpu_baseline(inp, wl, target_s=CPU_BASELINE_TARGET_S):
