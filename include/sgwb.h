@@ -473,7 +473,9 @@ int sgwb_plan_describe(const sgwb_plan *plan, char *buf, size_t len);
  * w [nt][ldc] and shape H [nf] of one baseline, covering absolute bins
  * [k0, k0 + nf) of grid fg; device memory owned by the caller, kept alive and
  * unchanged until sgwb_server_destroy.  The seeds of each (dataset, nside)
- * are built on first use and kept.
+ * are built on first use and kept, together with the dirty map's seed-side
+ * products (its form record and Bessel amplitudes, which depend on the seeds
+ * and df alone, so every band of the dataset shares them).
  * A worker thread admits queries while one of `slots` HIP streams is free and
  * the query's footprint (the make_maps_band workspace, the two result
  * maps, and new seeds) fits in an HBM arena of
@@ -483,8 +485,9 @@ int sgwb_plan_describe(const sgwb_plan *plan, char *buf, size_t len);
  * least 3e10 map terms (segments x bins x pixels; SGWB_SERVER_HEAVY_TERMS in
  * the environment overrides the threshold) fills the GPU alone, so at most
  * one such heavy query runs at a time (SGWB_SERVER_MAX_HEAVY, 1 to 64,
- * overrides) and heavy queries start in arrival order; lighter queries start in arrival order among themselves, run in the
- * other slots beside it and may pass a heavy query that waits for its turn; a
+ * overrides) and heavy queries start in arrival order; lighter queries start
+ * in arrival order among themselves, run in the other slots beside it and
+ * may pass a heavy query that waits for its turn; a
  * query waiting for memory holds back every query behind it.  A query larger
  * than the whole arena fails with SGWB_ENOMEM; nothing is ever allocated
  * after creation.  Results are bitwise the same alone and in any mix.
