@@ -632,15 +632,16 @@ def serving_sweep(args, torch, sg, rates, duration):
     for t in warm:
         srv.release(t)
     geoms = {}
+    bounds = [sg.baseline_delay_bound(d.sites) for d in datasets]
 
     def plain_query(ds, nside, lo, hi):
         d = datasets[ds]
         if (ds, nside) not in geoms:
             geoms[(ds, nside)] = sg.build_geometry(d.sites, nside, d.tgrid, device=dev)
         g, t = geoms[(ds, nside)]
-        # the broadband maps alone, as the server computes them
-        sg.make_maps_band(d.C[:, lo:hi], d.w[:, lo:hi], d.fgrid, d.k0 + lo, g, t, d.H[lo:hi].contiguous(), 0, hi - lo,
-                          narrowband=False)
+        # the broadband maps alone, as the server computes them (the same route for the same query)
+        sg.broadband_maps(d.C[:, lo:hi], d.w[:, lo:hi], d.fgrid, d.k0 + lo, g, t, d.H[lo:hi].contiguous(), 0, hi - lo,
+                          tau_bound=bounds[ds])
         torch.cuda.synchronize()
 
     for ds in range(3):  # warm the plain path's seeds too

@@ -145,6 +145,8 @@ int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int3
  *   SGWB_XFORM_MFMA4   matrix cores, four terms (|eta| <= 0.07);
  *   SGWB_XFORM_MFMA5   five terms, m = 2 unsplit (|eta| <= 0.17);
  *   SGWB_XFORM_MFMA5S  five terms, m = 2 split hi + lo (|eta| <= 0.29),
+ *   SGWB_XFORM_TABLE   no narrowband map: sgwb_broadband_maps summed the band
+ *                      first through per-segment delay tables,
  * with eta = 2 pi 31.5 df max|tau| of the call's seeds.  The matrix-core
  * choice is made on the device; for it this call synchronises the stream of
  * that call and reads the choice back from its workspace (16 bytes), so it
@@ -156,6 +158,7 @@ int sgwb_make_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int3
 #define SGWB_XFORM_MFMA4 2
 #define SGWB_XFORM_MFMA5 3
 #define SGWB_XFORM_MFMA5S 4
+#define SGWB_XFORM_TABLE 5
 int sgwb_last_x_form(int32_t *form /*host*/);
 
 /* ---- network sum: the sum over baselines I of Eq. eq:narrowband ------------
@@ -391,6 +394,53 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
                         const sgwb_fgrid *fg /*host*/, int64_t k0, const float *gamma, const double *tau,
                         int32_t npix, uint32_t flags, const float *H, int32_t k_lo, int32_t k_hi, float *X,
                         float *Gam, float *Xbb, float *Gbb, void *workspace, size_t workspace_bytes,
+                        hipStream_t stream);
+
+/* ---- broadband maps alone, the band's bins summed first: Sec. V ------------
+ * Xbb and Gbb over columns [k_lo, k_hi) as sgwb_make_maps_band defines them,
+ * with no narrowband map.  The call takes one of two routes:
+ *  - strips: sgwb_make_maps_band with X = Gam = NULL (the matrix-core dirty map
+ *    of all nf columns writes only its strip sums; needs SGWB_MAPS_ANTIPODAL,
+ *    df <= 0.0344 Hz, seeds within 2R/c; bitwise that call's result);
+ *  - table: Eq. eq_dirtymap summed over the band with the sums over bins and
+ *    segments exchanged,
+ *      Xbb(p) = sum_t gamma(t,p) Re[e^{2 pi i f_c tau} Y_t(tau)], tau = tau(t,p),
+ *      Y_t(tau) = sum_{k_lo <= k < k_hi} w(t,k) C(t,k) e^{2 pi i (f_k - f_c) tau},
+ *    f_c the band's centre.  Y_t is tabulated per segment on the delay grid
+ *    tau_j = (j - m - 1) h (float64 sums, stored as float32), h =
+ *    0.03 / (2 pi F), F = (k_hi - k_lo - 1) df / 2, m = ceil(tau_bound / h),
+ *    and read by 4-point Lagrange interpolation (error below 1.9e-8 of
+ *    sum_k |w C| per segment); the carrier phase is reduced in float64.  The
+ *    error against the definition stays below 1e-6 of
+ *    S_bb(p) = sum_t sum_k |gamma w C|.  Any df, any seeds within tau_bound.
+ *  Gbb (either route): the band sum moved into the weights, as in
+ *    sgwb_make_maps_band.
+ * The route is chosen on the host from the arguments alone: SGWB_BB_TABLE or
+ * SGWB_BB_STRIPS in flags forces one; otherwise SGWB_BB_ROUTE=table|strips in
+ * the environment, where that route applies; otherwise the table route runs
+ * where the strips route does not apply or a cost estimate (the tables' nt nb G
+ * products and nt npix interpolations against the strips' preparation and
+ * nt nf npix map terms, rates measured on an MI355X) favours it.  sgwb_last_x_form reports the
+ * route (SGWB_XFORM_TABLE, or the matrix-core form).
+ * tau_bound_s: a bound on |tau(t,p)| that the seeds meet, e.g.
+ * sgwb_baseline_delay_bound() of their baseline; 0 takes 2R/c (any baseline
+ * on the Earth).  In the table route a seed beyond it (or not a number) makes
+ * Xbb NaN at its pixel.
+ * Workspace: sgwb_broadband_maps_workspace_size() bytes for the same
+ * arguments (the route's own need), 256-byte aligned, owned by the caller.
+ * Errors: as sgwb_make_maps_band for the strips route; SGWB_EINVAL also for
+ * no output, a forced route that does not apply, both routes forced, a bad
+ * tau_bound_s, or a band whose table would exceed 2^21 + 3 nodes.            */
+#define SGWB_BB_TABLE 4u
+#define SGWB_BB_STRIPS 8u
+double sgwb_baseline_delay_bound(const sgwb_baseline *bl /*host*/);
+size_t sgwb_broadband_maps_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint32_t flags,
+                                          const sgwb_fgrid *fg /*host*/, int32_t k_lo, int32_t k_hi,
+                                          double tau_bound_s);
+int sgwb_broadband_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf,
+                        const sgwb_fgrid *fg /*host*/, int64_t k0, const float *gamma, const double *tau,
+                        int32_t npix, uint32_t flags, double tau_bound_s, const float *H, int32_t k_lo,
+                        int32_t k_hi, float *Xbb, float *Gbb, void *workspace, size_t workspace_bytes,
                         hipStream_t stream);
 
 /* ---- make_maps_band without allocation ---------------------------------

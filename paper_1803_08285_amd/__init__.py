@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libsgwb.so")
 
 SGWB_MAPS_ANTIPODAL = 1
 SGWB_MAPS_VALU_X = 2
+SGWB_BB_TABLE = 4
+SGWB_BB_STRIPS = 8
 SGWB_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
@@ -106,6 +108,12 @@ _SIGNATURES = {
     "sgwb_make_maps_band_workspace_size": ([_I32, _I32, _I32, ctypes.c_uint32], ctypes.c_size_t),
     "sgwb_make_maps_band": ([_VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
                              ctypes.c_uint32, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP],
+                            ctypes.c_int),
+    "sgwb_baseline_delay_bound": ([ctypes.POINTER(_Baseline)], ctypes.c_double),
+    "sgwb_broadband_maps_workspace_size": ([_I32, _I32, _I32, ctypes.c_uint32, ctypes.POINTER(_FGrid), _I32, _I32,
+                                            ctypes.c_double], ctypes.c_size_t),
+    "sgwb_broadband_maps": ([_VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
+                             ctypes.c_uint32, ctypes.c_double, _VP, _I32, _I32, _VP, _VP, _VP, ctypes.c_size_t, _VP],
                             ctypes.c_int),
     "sgwb_make_maps_band_noalloc": ([_VP, _VP, _I64, _I32, _I32, ctypes.POINTER(_FGrid), _I64, _VP, _VP, _I32,
                                      ctypes.c_uint32, _VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
@@ -236,13 +244,14 @@ def build_geometry(sites, nside: int, tgrid: TGrid, dtype=torch.float32, device=
     return gamma, tau
 
 
-X_FORMS = {0: "none", 1: "valu", 2: "mfma4", 3: "mfma5", 4: "mfma5_split"}
+X_FORMS = {0: "none", 1: "valu", 2: "mfma4", 3: "mfma5", 4: "mfma5_split", 5: "table"}
 
 
 def last_x_form() -> str:
     """Form of the dirty map that the last make_maps / make_maps_band /
     fisher_overlap call of this thread took: "none", "valu", "mfma4", "mfma5" or
-    "mfma5_split" (synchronises that call's stream for the matrix-core forms;
+    "mfma5_split", or "table" after a broadband_maps call that took the delay-table
+    route (synchronises that call's stream for the matrix-core forms;
     raises if its seeds failed the antipodal check)."""
     f = _I32(0)
     _check(lib().sgwb_last_x_form(ctypes.byref(f)), "last_x_form")
@@ -386,6 +395,78 @@ def make_maps_band(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamm
                                            _ptr(Xbb), _ptr(Gbb), _ptr(workspace), wsz, _stream())
     _check(rc, "make_maps_band_noalloc" if noalloc else "make_maps_band")
     return X, G, Xbb, Gbb
+
+
+def baseline_delay_bound(sites) -> float:
+    """|x_a - x_b| / c (s) of a baseline's two sites: the bound its seeds' delays meet."""
+    bl = _baseline(sites)
+    return float(lib().sgwb_baseline_delay_bound(ctypes.byref(bl)))
+
+
+_BB_ROUTES = {"auto": 0, "table": SGWB_BB_TABLE, "strips": SGWB_BB_STRIPS}
+
+
+def broadband_maps_workspace_bytes(nt: int, nf: int, npix: int, fgrid: FGrid, k_lo: int, k_hi: int,
+                                   tau_bound: float = 0.0, antipodal: bool = True, route: str = "auto") -> int:
+    if route not in _BB_ROUTES:
+        raise SgwbError("route must be 'auto', 'table' or 'strips'")
+    fg = _FGrid(float(fgrid.f0), float(fgrid.df))
+    flags = (SGWB_MAPS_ANTIPODAL if antipodal else 0) | _BB_ROUTES[route]
+    return int(lib().sgwb_broadband_maps_workspace_size(nt, nf, npix, flags, ctypes.byref(fg), int(k_lo), int(k_hi),
+                                                        float(tau_bound)))
+
+
+def broadband_maps(C: torch.Tensor, w: torch.Tensor, fgrid: FGrid, k0: int, gamma: torch.Tensor,
+                   tau: torch.Tensor, H: torch.Tensor | None, k_lo: int, k_hi: int, tau_bound: float = 0.0,
+                   antipodal: bool = True, want_x: bool = True, want_gamma: bool = True, out=None,
+                   workspace: torch.Tensor | None = None, route: str = "auto"):
+    """Broadband maps Xbb, Gbb [npix] over columns [k_lo, k_hi), no narrowband
+    map (float32): the library takes the strips route (the matrix-core dirty
+    map's strip sums) or sums the band first through per-segment delay tables,
+    as ``route`` forces or its cost estimate picks.  tau_bound: a bound on the
+    seeds' |tau| (s), e.g. baseline_delay_bound(sites); 0 takes 2R/c."""
+    if C.dim() != 2 or w.dim() != 2:
+        raise SgwbError("C and w must be 2-D")
+    nt, nf = w.shape
+    npix = gamma.shape[1]
+    _require(C, "C", torch.complex64, (nt, nf))
+    _require(w, "w", torch.float32, (nt, nf))
+    if C.stride(0) != w.stride(0):
+        raise SgwbError("C and w must share their row stride")
+    _require(gamma, "gamma", torch.float32, (nt, npix))
+    _require(tau, "tau", torch.float64, (nt, npix))
+    _require_contig(gamma, "gamma")
+    _require_contig(tau, "tau")
+    if want_gamma:
+        if H is None:
+            raise SgwbError("H is needed for Gbb")
+        _require(H, "H", torch.float32, (nf,))
+        _require_contig(H, "H")
+    if route not in _BB_ROUTES:
+        raise SgwbError("route must be 'auto', 'table' or 'strips'")
+    dev = C.device
+    if out is None:
+        Xbb = torch.empty(npix, dtype=torch.float32, device=dev) if want_x else None
+        Gbb = torch.empty(npix, dtype=torch.float32, device=dev) if want_gamma else None
+    else:
+        Xbb, Gbb = out
+    for name, t in (("Xbb", Xbb), ("Gbb", Gbb)):
+        if t is not None:
+            _require(t, name, torch.float32, (npix,))
+            _require_contig(t, name)
+    flags = (SGWB_MAPS_ANTIPODAL if antipodal else 0) | _BB_ROUTES[route]
+    fg = _FGrid(float(fgrid.f0), float(fgrid.df))
+    with torch.cuda.device(dev):
+        if workspace is None:
+            need = broadband_maps_workspace_bytes(nt, nf, npix, fgrid, k_lo, k_hi, tau_bound, antipodal, route)
+            workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        wsz = workspace.numel() * workspace.element_size()
+        rc = lib().sgwb_broadband_maps(_ptr(torch.view_as_real(C)), _ptr(w), int(w.stride(0)), nt, nf,
+                                       ctypes.byref(fg), int(k0), _ptr(gamma), _ptr(tau), npix, flags,
+                                       float(tau_bound), _ptr(H) if H is not None else None, int(k_lo), int(k_hi),
+                                       _ptr(Xbb), _ptr(Gbb), _ptr(workspace), wsz, _stream())
+    _check(rc, "broadband_maps")
+    return Xbb, Gbb
 
 
 def network_sum(maps, out=None):

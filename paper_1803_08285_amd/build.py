@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsgwb.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "geometry.hip", "dirty_map.hip", "dirty_map_mfma.hip", "beam.hip", "band.hip", "fisher.hip", "fold.hip", "contract.hip", "fisher_full.hip", "plan.hip", "tune.hip", "server.hip", "noalloc.hip"]
+SOURCES = ["api.hip", "geometry.hip", "dirty_map.hip", "dirty_map_mfma.hip", "beam.hip", "band.hip", "broadband.hip", "fisher.hip", "fold.hip", "contract.hip", "fisher_full.hip", "plan.hip", "tune.hip", "server.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 

@@ -654,9 +654,155 @@ int make_maps_band_seeded(const float *C, const float *w, int64_t ldc, int32_t n
     return SGWB_OK;
 }
 
+// Broadband maps alone: the route (strips or delay tables) from the host
+// arguments, and the table grid when that route is taken.
+struct BbRoute {
+    bool table = false;
+    BbGrid grid;
+};
+
+static int bb_route(int32_t nt, int32_t nf, int32_t npix, uint32_t flags, const sgwb_fgrid *fg, int32_t k_lo,
+                    int32_t k_hi, double tau_bound, BbRoute *r)
+{
+    if ((flags & SGWB_BB_TABLE) && (flags & SGWB_BB_STRIPS))
+        return set_error(SGWB_EINVAL, "broadband_maps: both routes forced");
+    if (!(tau_bound >= 0.0) || !isfinite(tau_bound))
+        return set_error(SGWB_EINVAL, "broadband_maps: tau_bound %g is not a finite bound >= 0", tau_bound);
+    if (!(0 <= k_lo && k_lo < k_hi && k_hi <= nf))
+        return set_error(SGWB_EINVAL, "broadband_maps: band [%d, %d) not a non-empty part of [0, %d)", k_lo, k_hi, nf);
+    const double earth = 2.0 * kEarthRadius / kLightSpeed;
+    const double bound = tau_bound > 0.0 ? tau_bound : earth;
+    const int32_t nb = k_hi - k_lo;
+    const bool have_grid = bb_grid(nb, fg->df_hz, bound, &r->grid);
+    MapArgs a;  // what the matrix-core eligibility reads (k0 = 63: the most strips a call can span)
+    a.k0 = 63;
+    a.nt = nt;
+    a.nf = nf;
+    a.npix = npix;
+    a.df = fg->df_hz;
+    a.nside = (flags & SGWB_MAPS_ANTIPODAL) ? nside_of_npix(npix) : 0;
+    // the strips route: the matrix-core dirty map over the call's columns
+    const bool strips_ok = a.nside > 0 && !(flags & SGWB_MAPS_VALU_X) && x_kernel_choice() != kXKernelValu &&
+                           xm_eligible(a) && bound <= earth;
+    if (flags & SGWB_BB_STRIPS) {
+        if (!strips_ok)
+            return set_error(SGWB_EINVAL, "broadband_maps: the strips route needs the matrix-core dirty map "
+                                          "(antipodal seeds, df <= 0.0344 Hz, seeds within 2R/c)");
+        r->table = false;
+        return SGWB_OK;
+    }
+    if (!have_grid && ((flags & SGWB_BB_TABLE) || !strips_ok))
+        return set_error(SGWB_EINVAL, "broadband_maps: a delay table for %d bins of %g Hz up to %g s would "
+                                      "exceed 2^21 + 3 nodes", nb, fg->df_hz, bound);
+    if ((flags & SGWB_BB_TABLE) || !strips_ok) {
+        r->table = true;
+        return SGWB_OK;
+    }
+    // SGWB_BB_ROUTE=table|strips in the environment sets the route of calls
+    // that force none (read at every call; a route that does not apply is ignored)
+    if (const char *e = getenv("SGWB_BB_ROUTE")) {
+        if (strcmp(e, "strips") == 0) {
+            r->table = false;
+            return SGWB_OK;
+        }
+        if (strcmp(e, "table") == 0 && have_grid) {
+            r->table = true;
+            return SGWB_OK;
+        }
+    }
+    // Cost estimate (s), from timings of both routes on one MI355X (full day,
+    // nside 8..128, bands of 16..4096 bins): the strips route takes ~0.19 ms
+    // of preparation, ~1.2e11 (segment, pixel) seed items/s and ~4.2e13 map
+    // terms/s over its whole 64-bin strips; the table route ~0.03 ms of
+    // launches, ~1.1e13 float64 products/s for the tables (4 per segment, bin
+    // and node), ~1.6e11 phase factors/s and ~3.3e11 items/s in the map pass.
+    const double strip_cols = (double)(((int64_t)nf + 63) / 64 * 64);
+    const double strips = 1.9e-4 + (double)nt * npix / 1.2e11 + (double)nt * strip_cols * npix / 4.2e13;
+    const double table = 3e-5 + (double)nt * nb * r->grid.G * 4.0 / 1.1e13 + (double)nb * r->grid.G / 1.6e11 +
+                         (double)nt * npix / 3.3e11;
+    r->table = have_grid && table < strips;
+    return SGWB_OK;
+}
+
+int broadband_maps_seeded(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
+                          int64_t k0, const float *gamma, const double *tau, int32_t npix, uint32_t flags,
+                          double tau_bound, const float *H, int32_t k_lo, int32_t k_hi, float *Xbb, float *Gbb,
+                          void *workspace, size_t workspace_bytes, const void *seeds, hipStream_t stream)
+{
+    note_xform(SGWB_XFORM_NONE);
+    if (!Xbb && !Gbb) return set_error(SGWB_EINVAL, "broadband_maps: nothing to compute");
+    if (Gbb && !H) return set_error(SGWB_EINVAL, "broadband_maps: null H");
+    if (!fg) return set_error(SGWB_EINVAL, "broadband_maps: null grid");
+    if (flags & ~(SGWB_MAPS_ANTIPODAL | SGWB_MAPS_VALU_X | SGWB_BB_TABLE | SGWB_BB_STRIPS))
+        return set_error(SGWB_EINVAL, "broadband_maps: unknown flag bits");
+    const uint32_t mflags = flags & (SGWB_MAPS_ANTIPODAL | SGWB_MAPS_VALU_X);
+    MapArgs a;
+    int rc = check_maps_args<float>(C, w, ldc, nt, nf, fg, k0, gamma, tau, npix, mflags, &a);
+    if (rc) return rc;
+    BbRoute r;
+    rc = bb_route(nt, nf, npix, flags, fg, k_lo, k_hi, tau_bound, &r);
+    if (rc) return rc;
+    if (!r.table)
+        return make_maps_band_seeded(C, w, ldc, nt, nf, fg, k0, gamma, tau, npix, mflags, H, k_lo, k_hi, nullptr,
+                                     nullptr, Xbb, Gbb, workspace, workspace_bytes, seeds, stream);
+    if (!workspace || (uintptr_t)workspace % 256)
+        return set_error(SGWB_EINVAL, "broadband_maps: workspace null or not 256-byte aligned");
+    const int32_t nb = k_hi - k_lo;
+    const size_t need = bb_workspace_bytes(nt, npix, nb, r.grid);
+    if (workspace_bytes < need)
+        return set_error(SGWB_ENOMEM, "broadband_maps: workspace of %zu bytes needed, %zu given", need,
+                         workspace_bytes);
+    if (Xbb) {
+        rc = check_hip(launch_broadband_table(C, w, ldc, nt, k_lo, k_hi, fg->f0_hz, fg->df_hz, k0, gamma, tau, npix,
+                                              r.grid, Xbb, workspace, stream),
+                       "broadband table launch");
+        if (rc) return rc;
+        note_xform(SGWB_XFORM_TABLE);
+    }
+    if (Gbb) {
+        rc = check_hip(launch_band_gamma(w, ldc, nt, H, k_lo, k_hi, gamma, npix,
+                                         bb_gamma_scratch(workspace, nt, npix, nb, r.grid), Gbb, stream),
+                       "band weights launch");
+        if (rc) return rc;
+    }
+    return SGWB_OK;
+}
+
 }  // namespace sgwb
 
 extern "C" {
+
+double sgwb_baseline_delay_bound(const sgwb_baseline *bl)
+{
+    if (!bl || !finite_det(bl->a) || !finite_det(bl->b)) return 0.0;
+    double ra[3], rb[3], D[9];
+    detector_frame(bl->a, ra, D);
+    detector_frame(bl->b, rb, D);
+    const double d = sqrt((ra[0] - rb[0]) * (ra[0] - rb[0]) + (ra[1] - rb[1]) * (ra[1] - rb[1]) +
+                          (ra[2] - rb[2]) * (ra[2] - rb[2]));
+    // the seeds' delays are this chord's projections, computed in float64:
+    // a relative margin of 1e-9 covers their rounding (and a co-located pair)
+    return d / kLightSpeed * (1.0 + 1e-9) + 1e-15;
+}
+
+size_t sgwb_broadband_maps_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint32_t flags, const sgwb_fgrid *fg,
+                                          int32_t k_lo, int32_t k_hi, double tau_bound_s)
+{
+    if (!fg || nt < 1 || nf < 1 || npix < 1) return 0;
+    BbRoute r;
+    if (bb_route(nt, nf, npix, flags, fg, k_lo, k_hi, tau_bound_s, &r)) return 0;
+    if (!r.table) return sgwb_make_maps_band_workspace_size(nt, nf, npix, flags & (SGWB_MAPS_ANTIPODAL | SGWB_MAPS_VALU_X));
+    return bb_workspace_bytes(nt, npix, k_hi - k_lo, r.grid);
+}
+
+int sgwb_broadband_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
+                        int64_t k0, const float *gamma, const double *tau, int32_t npix, uint32_t flags,
+                        double tau_bound_s, const float *H, int32_t k_lo, int32_t k_hi, float *Xbb, float *Gbb,
+                        void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    return broadband_maps_seeded(C, w, ldc, nt, nf, fg, k0, gamma, tau, npix, flags, tau_bound_s, H, k_lo, k_hi, Xbb,
+                                 Gbb, workspace, workspace_bytes, nullptr, stream);
+}
 
 size_t sgwb_reduce_band_workspace_size(int32_t npix, int32_t k_lo, int32_t k_hi)
 {

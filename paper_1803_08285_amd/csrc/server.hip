@@ -5,8 +5,10 @@
 // query names a baseline, a resolution and a contiguous band of bins; its
 // answer is the broadband pair Xbb, Gbb of that band (Sec. V): the band sums
 // of the narrowband maps (Eqs. eq_dirtymap, eq_fisher split per bin), computed
-// without writing those maps (the dirty map's tiles add up their strips' rows,
-// and Gbb is the band-summed weights against gamma^2, so no beam GEMM runs).
+// without writing those maps by sgwb_broadband_maps (the band summed first
+// through per-segment delay tables, or the dirty map's tiles adding up their
+// strips' rows, whichever its cost estimate favours; Gbb is the band-summed
+// weights against gamma^2, so no beam GEMM runs).
 //
 // A worker thread owns the device side:
 //   * admission (serve_policy.h): cost-aware -- at most one heavy query (one
@@ -83,6 +85,7 @@ struct Slot {
 
 struct sgwb_server {
     std::vector<sgwb_dataset> data;
+    std::vector<double> tau_bound;  // per dataset: its baseline's chord / c
     std::vector<Slot> slots;
     int32_t queue_capacity = 0;
     Arena arena;
@@ -116,7 +119,8 @@ size_t query_footprint(const sgwb_server *s, const sgwb_query &q, size_t *ws_byt
     const sgwb_dataset &d = s->data[q.dataset];
     const int64_t npix = 12LL * q.nside * q.nside;
     const int32_t nf = q.k_hi - q.k_lo;
-    *ws_bytes = sgwb_make_maps_band_workspace_size(d.tg.nt, nf, (int32_t)npix, SGWB_MAPS_ANTIPODAL);
+    *ws_bytes = sgwb_broadband_maps_workspace_size(d.tg.nt, nf, (int32_t)npix, SGWB_MAPS_ANTIPODAL, &d.fg, 0, nf,
+                                                   s->tau_bound[q.dataset]);
     auto up = [](size_t n) { return (n + 255) / 256 * 256; };
     return up(*ws_bytes) + 2 * up(npix * sizeof(float));
 }
@@ -202,11 +206,12 @@ int launch_query(sgwb_server *s, Query &q, int k)
     q.npix = npix;
     const float *C = d.C + 2 * (int64_t)q.q.k_lo;
     const float *w = d.w + q.q.k_lo;
-    // the broadband maps alone: no narrowband row is written and no beam GEMM
-    // runs; the dirty map's seed-side products come from the geometry cache
-    rc = make_maps_band_seeded(C, w, d.ldc, d.tg.nt, nf, &d.fg, d.k0 + q.q.k_lo, g->gamma, g->tau, npix,
-                               SGWB_MAPS_ANTIPODAL, d.H + q.q.k_lo, 0, nf, nullptr, nullptr, q.Xbb, q.Gbb, q.ws,
-                               q.ws_bytes, g->seeded ? g->seeds : nullptr, sl.stream);
+    // the broadband maps alone (no narrowband row, no beam GEMM), by the route
+    // sgwb_broadband_maps picks for the query: the delay tables, or the strips
+    // with the dirty map's seed-side products from the geometry cache
+    rc = broadband_maps_seeded(C, w, d.ldc, d.tg.nt, nf, &d.fg, d.k0 + q.q.k_lo, g->gamma, g->tau, npix,
+                               SGWB_MAPS_ANTIPODAL, s->tau_bound[q.q.dataset], d.H + q.q.k_lo, 0, nf, q.Xbb, q.Gbb,
+                               q.ws, q.ws_bytes, g->seeded ? g->seeds : nullptr, sl.stream);
     if (rc) return rc;
     if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return check_hip(hipGetLastError(), "server: record");
     sl.ticket = q.ticket;
@@ -349,6 +354,7 @@ int sgwb_server_create(const sgwb_server_cfg *cfg, sgwb_server **out)
     }
     sgwb_server *s = new sgwb_server();
     s->data.assign(cfg->datasets, cfg->datasets + cfg->ndatasets);
+    for (const sgwb_dataset &d : s->data) s->tau_bound.push_back(sgwb_baseline_delay_bound(&d.bl));
     s->queue_capacity = cfg->queue_capacity > 0 ? cfg->queue_capacity : 1 << 20;
     size_t budget = cfg->hbm_budget_bytes;
     if (budget == 0) {

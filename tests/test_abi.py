@@ -269,3 +269,61 @@ def test_short_matrix_core_workspace_is_refused_on_the_host():
     # unknown flag bits are refused before anything else
     rc = L.sgwb_make_maps(d, d, 8, 10, 8, ctypes.byref(fg), 0, d, d, 768, 1 | 8, d, None, d, 256, None)
     assert rc == -1 and b"flag" in L.sgwb_last_error()
+
+
+def test_broadband_route_bound_and_validation_on_the_host():
+    """Delay bound of a baseline (its chord / c, the R7 Earth model), the
+    broadband call's route choice and workspace size, and its refusals, all on
+    the host."""
+    import numpy as np
+
+    import paper_1803_08285_amd as sg
+    import synth
+
+    L = sg.lib()
+    R, c = 6.371e6, 299792458.0
+    for name, want_ms in (("AB", 9.993), ("AC", 27.207), ("BC", 26.391)):
+        s = synth.baseline_sites(name)
+        pos = []
+        for lat, lon in ((s[0], s[1]), (s[3], s[4])):
+            la, lo = np.radians(lat), np.radians(lon)
+            pos.append(R * np.array([np.cos(la) * np.cos(lo), np.cos(la) * np.sin(lo), np.sin(la)]))
+        chord = np.linalg.norm(pos[0] - pos[1]) / c
+        b = sg.baseline_delay_bound(s)
+        assert chord <= b <= chord * (1 + 1e-8) + 1e-14
+        assert abs(b * 1e3 - want_ms) < 1e-3
+    fg = sg.FGrid(20.0, 1.0 / 32.0)
+    tb = sg.baseline_delay_bound(synth.baseline_sites("AB"))
+    nt = 898
+    # a GPU-filling band at nside 128 takes the tables, the same band at nside 8 the strips
+    big = sg.broadband_maps_workspace_bytes(nt, 4096, 196608, fg, 0, 4096, tb)
+    forced = sg.broadband_maps_workspace_bytes(nt, 4096, 196608, fg, 0, 4096, tb, route="table")
+    assert big == forced > 0
+    small = sg.broadband_maps_workspace_bytes(nt, 4096, 768, fg, 0, 4096, tb)
+    assert small == sg.band_maps_workspace_bytes(nt, 4096, 768) > 0
+    # the tables need no antipodal seeds and no matrix-core grid; the strips do
+    assert sg.broadband_maps_workspace_bytes(nt, 64, 700, sg.FGrid(20.0, 0.25), 0, 64, tb, antipodal=False) > 0
+    for kw in (dict(route="strips", antipodal=False), dict(tau_bound=-1.0), dict(tau_bound=float("nan"))):
+        args = dict(tau_bound=tb)
+        args.update(kw)
+        assert sg.broadband_maps_workspace_bytes(nt, 64, 768, fg, 0, 64, **args) == 0
+    assert sg.broadband_maps_workspace_bytes(nt, 64, 768, fg, 5, 5, tb) == 0  # empty band
+    # a band whose table would pass 2^21 + 3 nodes: strips when they apply, else refused
+    assert sg.broadband_maps_workspace_bytes(nt, 54592, 768, fg, 0, 54592, 10.0) == 0
+    assert sg.broadband_maps_workspace_bytes(nt, 54592, 768, fg, 0, 54592, 0.04) == sg.band_maps_workspace_bytes(
+        nt, 54592, 768)
+    dummy = ctypes.c_void_p(256)
+    cfg = sg._FGrid(20.0, 1.0 / 32.0)
+    rc = L.sgwb_broadband_maps(dummy, dummy, 64, 10, 64, ctypes.byref(cfg), 0, dummy, dummy, 768,
+                               sg.SGWB_BB_TABLE | sg.SGWB_BB_STRIPS | 1, tb, dummy, 0, 64, dummy, dummy, dummy, 1 << 20,
+                               None)
+    assert rc == -1 and b"both routes" in L.sgwb_last_error()
+    rc = L.sgwb_broadband_maps(dummy, dummy, 64, 10, 64, ctypes.byref(cfg), 0, dummy, dummy, 768, 16 | 1, tb, dummy,
+                               0, 64, dummy, dummy, dummy, 1 << 20, None)
+    assert rc == -1 and b"flag" in L.sgwb_last_error()
+    rc = L.sgwb_broadband_maps(dummy, dummy, 64, 10, 64, ctypes.byref(cfg), 0, dummy, dummy, 768, 1, tb, dummy, 0, 64,
+                               None, None, dummy, 1 << 20, None)
+    assert rc == -1 and b"nothing" in L.sgwb_last_error()
+    rc = L.sgwb_broadband_maps(dummy, dummy, 64, 10, 64, ctypes.byref(cfg), 0, dummy, dummy, 768,
+                               sg.SGWB_BB_TABLE | 1, tb, dummy, 0, 64, dummy, dummy, dummy, 256, None)
+    assert rc == -2 and b"workspace" in L.sgwb_last_error()

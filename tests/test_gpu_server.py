@@ -1,5 +1,6 @@
 """Query server on the GPU: continuous batching, admission by HBM footprint,
-results identical alone and in the mix, errors before device work."""
+results identical alone, in the mix and through the direct sgwb_broadband_maps
+call (both of its routes), errors before device work."""
 import time
 
 import numpy as np
@@ -38,16 +39,39 @@ def datasets(sg):
     return out
 
 
+# (dataset, nside, k_lo, k_hi)
 QUERIES = [(0, 8, 0, 700), (1, 16, 100, 101), (2, 4, 64, 1500), (0, 2, 5, 69), (1, 8, 1000, 1499),
-           (2, 16, 0, 300), (0, 16, 640, 704), (1, 1, 0, 1500)]
+           (2, 16, 0, 300), (0, 16, 640, 704), (1, 1, 0, 1500), (0, 16, 0, 300), (2, 64, 200, 1400)]
+
+
+def _route(sg, d, nside, lo, hi):
+    npix = 12 * nside * nside
+    b = sg.baseline_delay_bound(d.sites)
+    auto = sg.broadband_maps_workspace_bytes(NT, hi - lo, npix, d.fgrid, 0, hi - lo, b)
+    return "table" if auto == sg.broadband_maps_workspace_bytes(NT, hi - lo, npix, d.fgrid, 0, hi - lo, b,
+                                                                route="table") else "strips"
 
 
 def _direct(sg, d, nside, lo, hi):
+    """The same query through sgwb_broadband_maps, the call the server makes."""
     g, t = sg.build_geometry(d.sites, nside, d.tgrid)
-    _, _, Xbb, Gbb = sg.make_maps_band(d.C[:, lo:hi], d.w[:, lo:hi], d.fgrid, d.k0 + lo, g, t,
-                                       d.H[lo:hi].contiguous(), 0, hi - lo)
+    Xbb, Gbb = sg.broadband_maps(d.C[:, lo:hi], d.w[:, lo:hi], d.fgrid, d.k0 + lo, g, t, d.H[lo:hi].contiguous(),
+                                 0, hi - lo, tau_bound=sg.baseline_delay_bound(d.sites))
     torch.cuda.synchronize()
     return Xbb, Gbb
+
+
+ROUTES = ["auto", "strips"]  # auto: the cost rule, which takes the tables for every query of these small days
+
+
+@pytest.fixture(params=ROUTES)
+def route(request, monkeypatch, sg, datasets):
+    if request.param == "auto":
+        monkeypatch.delenv("SGWB_BB_ROUTE", raising=False)
+        assert all(_route(sg, datasets[q[0]], *q[1:]) == "table" for q in QUERIES)
+    else:
+        monkeypatch.setenv("SGWB_BB_ROUTE", request.param)
+    return request.param
 
 
 def _wait(srv, tickets, timeout=60.0):
@@ -64,7 +88,7 @@ def _wait(srv, tickets, timeout=60.0):
     return done
 
 
-def test_server_mix_equals_alone_and_direct(sg, datasets):
+def test_server_mix_equals_alone_and_direct(sg, datasets, route):
     srv = sg.Server(datasets, slots=4, hbm_budget_bytes=2 << 30)
     # all at once (the mix)
     tickets = [srv.submit(*q) for q in QUERIES]
@@ -91,7 +115,7 @@ def test_server_mix_equals_alone_and_direct(sg, datasets):
     srv.close()
 
 
-def test_server_results_vs_oracle(sg, oracle_mod, datasets):
+def test_server_results_vs_oracle(sg, oracle_mod, datasets, route):
     """Served broadband maps against the FP64 oracle (Eq. eq_dirtymap and the
     Eq. eq_fisher diagonal per bin, summed over the query's band as in Sec. V):
     Xbb within 1e-5 of the band-summed scale sum_k S, Gbb (the band sum moved
@@ -130,7 +154,8 @@ def test_server_rejects_bad_queries_before_device_work(sg, datasets):
 
 def test_server_fails_oversized_query_and_keeps_serving(sg, datasets):
     # arena of 4 MiB: an nside-16 full-band query needs more (its workspace alone is 5.7 MiB)
-    assert sg.band_maps_workspace_bytes(NT, NF, 3072, True) > 4 << 20
+    d = datasets[0]
+    assert sg.broadband_maps_workspace_bytes(NT, NF, 3072, d.fgrid, 0, NF, sg.baseline_delay_bound(d.sites)) > 4 << 20
     srv = sg.Server(datasets, slots=2, hbm_budget_bytes=4 << 20)
     big = srv.submit(0, 16, 0, NF)
     small = srv.submit(1, 1, 0, 20)
