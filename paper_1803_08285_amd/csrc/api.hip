@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include "broadband.h"
 #include "fisher_general.h"
 #include "sgwb_internal.h"
 

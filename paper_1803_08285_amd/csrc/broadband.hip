@@ -17,7 +17,7 @@
 #include <math.h>
 #include <stdint.h>
 
-#include "sgwb_internal.h"
+#include "broadband.h"
 
 namespace sgwb {
 

@@ -39,6 +39,7 @@
 #include <vector>
 
 #include "serve_policy.h"
+#include "broadband.h"
 #include "sgwb_internal.h"
 
 using namespace sgwb;

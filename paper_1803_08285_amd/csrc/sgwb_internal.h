@@ -158,24 +158,6 @@ size_t band_gamma_scratch_bytes(int32_t nt, int32_t npix);
 hipError_t launch_band_gamma(const float *w, int64_t ldw, int32_t nt, const float *H, int32_t klo, int32_t khi,
                              const float *gamma, int32_t npix, double *scratch, float *Gbb, hipStream_t s);
 
-// Broadband dirty map with the band's bins summed first: per segment a table
-// of Y_t(tau) = sum_k y(t,k) e^{2 pi i (f_k - f_c) tau} on the delay grid
-// tau_j = (j - m - 1) h, j < G = 2m + 3, read by 4-point Lagrange interpolation.
-struct BbGrid {
-    int32_t m = 0, G = 0;
-    double h = 0.0;      // node spacing (s)
-    double bound = 0.0;  // the seeds' promised bound on |tau| (s), <= m h
-};
-// false: no grid of at most 2^21 + 3 nodes meets the spacing for this band
-bool bb_grid(int32_t nb, double df, double bound, BbGrid *g);
-size_t bb_workspace_bytes(int32_t nt, int32_t npix, int32_t nb, const BbGrid &g);
-// the workspace's share left for launch_band_gamma's scratch
-double *bb_gamma_scratch(void *work, int32_t nt, int32_t npix, int32_t nb, const BbGrid &g);
-// Xbb over columns [klo, khi) of C and w (absolute bins k0 + klo ..)
-hipError_t launch_broadband_table(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t klo, int32_t khi,
-                                  double f0, double df, int64_t k0, const float *gamma, const double *tau,
-                                  int32_t npix, const BbGrid &g, float *Xbb, void *work, hipStream_t s);
-
 // full Fisher matrix of a band for separable weights, and its CG clean map
 size_t fisher_full_workspace_bytes(double f_max, int32_t nbins, int32_t nt, int32_t npix);
 bool fisher_full_band_ok(double f_max);
@@ -235,12 +217,6 @@ hipError_t launch_xm_seed_products(const MapArgs &a, const float *gamma, const d
 int make_maps_band_seeded(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
                           int64_t k0, const float *gamma, const double *tau, int32_t npix, uint32_t flags,
                           const float *H, int32_t k_lo, int32_t k_hi, float *X, float *Gam, float *Xbb, float *Gbb,
-                          void *workspace, size_t workspace_bytes, const void *seeds, hipStream_t stream);
-// sgwb_broadband_maps with the strips route's seed-side products from `seeds`
-// (as make_maps_band_seeded; the table route needs none).
-int broadband_maps_seeded(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
-                          int64_t k0, const float *gamma, const double *tau, int32_t npix, uint32_t flags,
-                          double tau_bound, const float *H, int32_t k_lo, int32_t k_hi, float *Xbb, float *Gbb,
                           void *workspace, size_t workspace_bytes, const void *seeds, hipStream_t stream);
 int seed_products(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,
                   int64_t k0, const float *gamma, const double *tau, int32_t npix, void *seeds, hipStream_t stream,
