@@ -532,6 +532,63 @@ def bench_network(args, torch, sg):
                       "directed_contraction": {"ms": t_dir, "pixels": int(pix.numel())}}), flush=True)
 
 
+def bench_broadband(args, torch, sg):
+    """The served form's largest query alone: the broadband maps of a full day,
+    nside 128, 4096 bins of 1/32 Hz (baseline AB), through sgwb_broadband_maps on
+    each route: the strip sums of the matrix-core dirty map, and the band summed
+    first through per-segment delay tables (the route the cost rule picks)."""
+    dev = torch.device("cuda:0")
+    tg = synth.TGRID_FULL
+    nside, nb, k0 = 128, 4096, 0
+    npix = 12 * nside * nside
+    fgd = synth.FGRID_FULL
+    f = fgd.freqs()[k0:k0 + nb]
+    C = synth.noise_csd(31, tg.nt, f, dtype=np.complex64)
+    w = synth.weights(f, synth.segment_scale(tg.nt, 7)).astype(np.float32)
+    Cd, wd = torch.from_numpy(C).to(dev), torch.from_numpy(w).to(dev)
+    H = torch.from_numpy(synth.spectrum_H(f).astype(np.float32)).to(dev)
+    sites = synth.baseline_sites("AB")
+    g, t = sg.build_geometry(sites, nside, sg.TGrid(tg.nt, tg.t0, tg.stride, tg.dur), device=dev)
+    fg = sg.FGrid(fgd.f0, fgd.df)
+    tb = sg.baseline_delay_bound(sites)
+    res = {}
+    for route in ("strips", "table", "auto"):
+        ws = torch.empty(max(sg.broadband_maps_workspace_bytes(tg.nt, nb, npix, fg, 0, nb, tb, route=route), 256),
+                         dtype=torch.uint8, device=dev)
+        Xbb = torch.empty(npix, dtype=torch.float32, device=dev)
+        Gbb = torch.empty(npix, dtype=torch.float32, device=dev)
+
+        def call():
+            sg.broadband_maps(Cd, wd, fg, k0, g, t, H, 0, nb, tau_bound=tb, route=route, out=(Xbb, Gbb),
+                              workspace=ws)
+
+        for _ in range(args.warmup):
+            call()
+        torch.cuda.synchronize()
+        form = sg.last_x_form()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        res[route] = {"ms": e0.elapsed_time(e1) / args.steps, "form": form}
+        log(f"broadband query, route {route} ({form}): {res[route]['ms']:.3f} ms")
+        del ws
+    ms = res["auto"]["ms"]
+    terms = tg.nt * nb * npix
+    seed_bytes = tg.nt * npix * 12  # gamma (4 B) and tau (8 B) read once per (segment, pixel)
+    print(json.dumps({"metric": "broadband query latency (ms)", "value": ms, "unit": "ms", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f64 tables and sums, f32 interpolation",
+                      "data": "synthetic",
+                      "config": {"workload": "broadband_query_nside128_4096_bins", "baseline": "AB", "nt": tg.nt,
+                                 "nb": nb, "nside": nside, "npix": npix, "parallelism": "single GPU"},
+                      "terms_per_s": terms / (ms * 1e-3),
+                      "seed_read_GBps_whole_call": seed_bytes / (ms * 1e-3) / 1e9,
+                      "routes": res}), flush=True)
+
+
 def bench_folded(args, torch, sg):
     """Folded pipeline over --days synthetic sidereal days of the full band: fold
     (v, u, w, x), dirty map of x, overlap-corrected Fisher diagonal, band sums."""
@@ -751,6 +808,8 @@ def main():
     ap.add_argument("--days", type=int, default=10)
     ap.add_argument("--fisher-overlap", action="store_true",
                     help="overlap-corrected Fisher diagonal over the full band of --workload")
+    ap.add_argument("--broadband", action="store_true",
+                    help="the served form's largest query (nside 128, 4096 bins) on both broadband routes")
     ap.add_argument("--network", action="store_true",
                     help="network sum of three baselines' narrowband maps and the contractions, for --workload")
     ap.add_argument("--fisher-full", action="store_true",
@@ -792,6 +851,9 @@ def main():
         return
     if args.fisher_full:
         bench_fisher_full(args, torch, sg)
+        return
+    if args.broadband:
+        bench_broadband(args, torch, sg)
         return
     if args.network:
         bench_network(args, torch, sg)

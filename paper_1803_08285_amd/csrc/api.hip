@@ -753,20 +753,11 @@ int broadband_maps_seeded(const float *C, const float *w, int64_t ldc, int32_t n
     if (workspace_bytes < need)
         return set_error(SGWB_ENOMEM, "broadband_maps: workspace of %zu bytes needed, %zu given", need,
                          workspace_bytes);
-    if (Xbb) {
-        rc = check_hip(launch_broadband_table(C, w, ldc, nt, k_lo, k_hi, fg->f0_hz, fg->df_hz, k0, gamma, tau, npix,
-                                              r.grid, Xbb, workspace, stream),
-                       "broadband table launch");
-        if (rc) return rc;
-        note_xform(SGWB_XFORM_TABLE);
-    }
-    if (Gbb) {
-        rc = check_hip(launch_band_gamma(w, ldc, nt, H, k_lo, k_hi, gamma, npix,
-                                         bb_gamma_scratch(workspace, nt, npix, nb, r.grid), Gbb, stream),
-                       "band weights launch");
-        if (rc) return rc;
-    }
-    return SGWB_OK;
+    rc = check_hip(launch_broadband_table_maps(C, w, ldc, nt, k_lo, k_hi, fg->f0_hz, fg->df_hz, k0, H, gamma, tau,
+                                               npix, r.grid, Xbb, Gbb, workspace, stream),
+                   "broadband table launch");
+    if (!rc && Xbb) note_xform(SGWB_XFORM_TABLE);
+    return rc;
 }
 
 }  // namespace sgwb

@@ -304,6 +304,15 @@ __global__ __launch_bounds__(256) void band_gamma_kernel(const float *__restrict
     part[(int64_t)blockIdx.y * npix + p] = acc;
 }
 
+int32_t band_gamma_chunks() { return kBandTChunks; }
+
+hipError_t launch_band_weights(const float *w, int64_t ldw, int32_t nt, const float *H, int32_t klo, int32_t khi,
+                               double *v, hipStream_t s)
+{
+    hipLaunchKernelGGL(band_weight_kernel, dim3((unsigned)nt), dim3(kWeightThreads), 0, s, w, ldw, H, klo, khi, v);
+    return hipGetLastError();
+}
+
 size_t band_gamma_scratch_bytes(int32_t nt, int32_t npix)
 {
     return ((size_t)nt + (size_t)kBandTChunks * npix) * sizeof(double);

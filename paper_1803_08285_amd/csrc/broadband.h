@@ -17,12 +17,21 @@ struct BbGrid {
 // false: no grid of at most 2^21 + 3 nodes meets the spacing for this band
 bool bb_grid(int32_t nb, double df, double bound, BbGrid *g);
 size_t bb_workspace_bytes(int32_t nt, int32_t npix, int32_t nb, const BbGrid &g);
-// the workspace's share left for launch_band_gamma's scratch
-double *bb_gamma_scratch(void *work, int32_t nt, int32_t npix, int32_t nb, const BbGrid &g);
-// Xbb over columns [klo, khi) of C and w (absolute bins k0 + klo ..)
-hipError_t launch_broadband_table(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t klo, int32_t khi,
-                                  double f0, double df, int64_t k0, const float *gamma, const double *tau,
-                                  int32_t npix, const BbGrid &g, float *Xbb, void *work, hipStream_t s);
+
+// The layout of launch_band_gamma's work (band.hip), for a pass that computes
+// Gbb beside Xbb with the same bits: its scratch holds v[nt] (the band-summed
+// weights, from launch_band_weights) and then band_gamma_chunks() rows of
+// per-pixel partial sums, row r over segments [r per, (r + 1) per),
+// per = ceil(nt / band_gamma_chunks()), each summed in segment order.
+int32_t band_gamma_chunks();
+hipError_t launch_band_weights(const float *w, int64_t ldw, int32_t nt, const float *H, int32_t klo, int32_t khi,
+                               double *v, hipStream_t s);
+// Xbb (and, with Gbb, Gbb) over columns [klo, khi) of C and w (absolute bins
+// k0 + klo ..); H is needed with Gbb
+hipError_t launch_broadband_table_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t klo,
+                                       int32_t khi, double f0, double df, int64_t k0, const float *H,
+                                       const float *gamma, const double *tau, int32_t npix, const BbGrid &g,
+                                       float *Xbb, float *Gbb, void *work, hipStream_t s);
 
 // sgwb_broadband_maps with the strips route's seed-side products from `seeds`
 // (as make_maps_band_seeded; the table route needs none).

@@ -30,7 +30,6 @@ namespace sgwb {
 constexpr double kBbPhaseStep = 0.03;
 constexpr int32_t kBbMaxHalf = 1 << 20;  // m: at most 2^21 + 3 nodes per table
 constexpr int kBbTileT = 64, kBbTileJ = 64, kBbTileK = 16;
-constexpr int kBbSegBlock = 64;  // segments per workgroup row of the map pass
 
 bool bb_grid(int32_t nb, double df, double bound, BbGrid *g)
 {
@@ -64,8 +63,8 @@ static int32_t bb_splits(int32_t nt, int32_t nb, const BbGrid &g, int32_t *kper)
 }
 
 // Workspace: E [nb][G] float2 | T [nt][G] float2 | the map pass's partial sums
-// [segment blocks][npix] | the table product's partial sums [ranges][nt][G]
-// double2 | the Fisher band weights' scratch.
+// [segment chunks][npix] | the table product's partial sums [ranges][nt][G]
+// double2 | the Fisher band weights' scratch (v, then its partial sums).
 struct BbLayout {
     size_t e, t, part, tpart, gam, total;
 };
@@ -73,7 +72,7 @@ static BbLayout bb_layout(int32_t nt, int32_t npix, int32_t nb, const BbGrid &g)
 {
     int32_t kper;
     const int32_t ns = bb_splits(nt, nb, g, &kper);
-    const size_t ntb = ((size_t)nt + kBbSegBlock - 1) / kBbSegBlock;
+    const size_t ntb = (size_t)band_gamma_chunks();  // the map pass's segment chunks
     BbLayout L;
     L.e = 0;
     L.t = L.e + up256_((size_t)nb * g.G * sizeof(float2));
@@ -199,18 +198,23 @@ __global__ __launch_bounds__(256) void bb_table_finish_kernel(const double2 *__r
     }
 }
 
-// part[blockIdx.y][p] = sum over this block's segments t of
+// part[blockIdx.y][p] = sum over this chunk's segments t of
 // gamma(t,p) Re[e^{2 pi i f_c tau} Y_t(tau)], Y_t from its table by 4-point
 // Lagrange interpolation; a seed with |tau| beyond the grid's bound (or not a
-// number) makes its pixel's sum NaN.
+// number) makes its pixel's sum NaN.  With v (GB), gpart[blockIdx.y][p] =
+// sum_t v[t] gamma(t,p)^2 as band_gamma_kernel sums it (same chunks, same
+// order, same arithmetic), from the gamma values this pass reads anyway.
+template <bool GB>
 __global__ __launch_bounds__(256) void bb_map_kernel(const float *__restrict__ gamma, const double *__restrict__ tau,
                                                      int32_t nt, int32_t npix, const float2 *__restrict__ T,
                                                      int32_t G, int32_t m, double h, double bound, double fc,
-                                                     double *__restrict__ part)
+                                                     int32_t per, double *__restrict__ part,
+                                                     const double *__restrict__ v, double *__restrict__ gpart)
 {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= npix) return;
-    const int32_t t0 = blockIdx.y * kBbSegBlock, t1 = min(nt, t0 + kBbSegBlock);
+    const int32_t t0 = blockIdx.y * per, t1 = min(nt, t0 + per);
+    double gacc = 0.0;
     const double inv_h = 1.0 / h, origin = (double)(m + 1);
     const double jmax = (double)(2 * m);
     double acc = 0.0;
@@ -256,20 +260,32 @@ __global__ __launch_bounds__(256) void bb_map_kernel(const float *__restrict__ g
             float sn, cs;
             sincospif(2.0f * r, &sn, &cs);
             acc = fma(valid ? (double)g[e] : 0.0, (double)fmaf(cs, yr, -sn * yi), acc);
+            if (GB) {
+                const double gd = (double)g[e];
+                const double ga = fma(v[min(tq + e, t1 - 1)], gd * gd, gacc);
+                gacc = valid ? ga : gacc;
+            }
         }
     }
     part[(int64_t)blockIdx.y * npix + p] = bad ? (double)__builtin_nanf("") : acc;
+    if (GB) gpart[(int64_t)blockIdx.y * npix + p] = gacc;
 }
 
-hipError_t launch_broadband_table(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t klo, int32_t khi,
-                                  double f0, double df, int64_t k0, const float *gamma, const double *tau,
-                                  int32_t npix, const BbGrid &g, float *Xbb, void *work, hipStream_t s)
+hipError_t launch_broadband_table_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t klo,
+                                       int32_t khi, double f0, double df, int64_t k0, const float *H,
+                                       const float *gamma, const double *tau, int32_t npix, const BbGrid &g,
+                                       float *Xbb, float *Gbb, void *work, hipStream_t s)
 {
     const int32_t nb = khi - klo;
     const BbLayout L = bb_layout(nt, npix, nb, g);
+    char *ws = reinterpret_cast<char *>(work);
+    double *v = reinterpret_cast<double *>(ws + L.gam), *gpart = v + nt;
+    const int32_t nchunks = band_gamma_chunks(), per = (nt + nchunks - 1) / nchunks;
+    if (!Xbb) {  // Gbb alone: the weight-side kernels by themselves
+        return launch_band_gamma(w, ldc, nt, H, klo, khi, gamma, npix, v, Gbb, s);
+    }
     int32_t kper;
     const int32_t ns = bb_splits(nt, nb, g, &kper);
-    char *ws = reinterpret_cast<char *>(work);
     float2 *E = reinterpret_cast<float2 *>(ws + L.e);
     float2 *T = reinterpret_cast<float2 *>(ws + L.t);
     double *part = reinterpret_cast<double *>(ws + L.part);
@@ -289,19 +305,25 @@ hipError_t launch_broadband_table(const float *C, const float *w, int64_t ldc, i
                        0, s, (const double2 *)Tpart, nT, ns, T);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (Gbb) {
+        e = launch_band_weights(w, ldc, nt, H, klo, khi, v, s);
+        if (e != hipSuccess) return e;
+    }
     // the band's centre: absolute bin k0 + klo + (nb - 1) / 2
     const double fc = f0 + ((double)(k0 + klo) + 0.5 * (nb - 1)) * df;
-    const int32_t ntb = (nt + kBbSegBlock - 1) / kBbSegBlock;
-    hipLaunchKernelGGL(bb_map_kernel, dim3((unsigned)((npix + 255) / 256), (unsigned)ntb), dim3(256), 0, s, gamma,
-                       tau, nt, npix, (const float2 *)T, g.G, g.m, g.h, g.bound, fc, part);
+    const dim3 grid((unsigned)((npix + 255) / 256), (unsigned)nchunks);
+    if (Gbb)
+        hipLaunchKernelGGL(bb_map_kernel<true>, grid, dim3(256), 0, s, gamma, tau, nt, npix, (const float2 *)T, g.G,
+                           g.m, g.h, g.bound, fc, per, part, (const double *)v, gpart);
+    else
+        hipLaunchKernelGGL(bb_map_kernel<false>, grid, dim3(256), 0, s, gamma, tau, nt, npix, (const float2 *)T, g.G,
+                           g.m, g.h, g.bound, fc, per, part, (const double *)nullptr, (double *)nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_band_partial_finish(part, ntb, npix, Xbb, s);
+    e = launch_band_partial_finish(part, nchunks, npix, Xbb, s);
+    if (e != hipSuccess || !Gbb) return e;
+    return launch_band_partial_finish(gpart, nchunks, npix, Gbb, s);
 }
 
-double *bb_gamma_scratch(void *work, int32_t nt, int32_t npix, int32_t nb, const BbGrid &g)
-{
-    return reinterpret_cast<double *>(reinterpret_cast<char *>(work) + bb_layout(nt, npix, nb, g).gam);
-}
 
 }  // namespace sgwb
