@@ -30,6 +30,7 @@ namespace sgwb {
 constexpr double kBbPhaseStep = 0.03;
 constexpr int32_t kBbMaxHalf = 1 << 20;  // m: at most 2^21 + 3 nodes per table
 constexpr int kBbTileT = 64, kBbTileJ = 64, kBbTileK = 16;
+constexpr int kBbBatch = 2;  // segments whose loads the map pass issues together
 
 bool bb_grid(int32_t nb, double df, double bound, BbGrid *g)
 {
@@ -219,22 +220,22 @@ __global__ __launch_bounds__(256) void bb_map_kernel(const float *__restrict__ g
     const double jmax = (double)(2 * m);
     double acc = 0.0;
     bool bad = false;
-    // segments four at a time: their seed loads, then their table reads, are
+    // segments kBbBatch at a time: their seed loads, then their table reads, are
     // issued together (segments past t1 repeat t1 - 1 with weight zero; no
     // branch, so that the compiler keeps the loads ahead of the arithmetic)
-    for (int32_t tq = t0; tq < t1; tq += 4) {
-        double ta[4];
-        float g[4];
+    for (int32_t tq = t0; tq < t1; tq += kBbBatch) {
+        double ta[kBbBatch];
+        float g[kBbBatch];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < kBbBatch; ++e) {
             const int64_t o = (int64_t)min(tq + e, t1 - 1) * npix + p;
             ta[e] = tau[o];
             g[e] = gamma[o];
         }
-        float2 a[4][4];
-        float x[4];
+        float2 a[kBbBatch][4];
+        float x[kBbBatch];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < kBbBatch; ++e) {
             const double u = fma(ta[e], inv_h, origin);
             const double jd = fmin(fmax(floor(u), 1.0), jmax);  // NaN and out-of-range delays stay inside the table
             x[e] = (float)(u - jd);
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(256) void bb_map_kernel(const float *__restrict__ g
             for (int i = 0; i < 4; ++i) a[e][i] = row[i];
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < kBbBatch; ++e) {
             const bool valid = tq + e < t1;
             bad |= valid && !(fabs(ta[e]) <= bound);
             // Lagrange weights of the nodes at -1, 0, 1, 2
