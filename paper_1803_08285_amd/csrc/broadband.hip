@@ -9,11 +9,10 @@
 // 4-point Lagrange interpolation, replaces the per-bin phase of every
 // (segment, bin, pixel) term by one interpolation per (segment, pixel).
 //
-// Kernels: the table's phase factors E(k,j) (float64, rounded once), the
-// tables T = y E (a complex product [nt x nb] x [nb x G], float64 sums over
-// ranges of bins, the ranges added in order), and
-// the map pass (one pixel a thread, one block of segments a workgroup row,
-// float64 partial sums added in a fixed order by the band finish kernel).
+// Kernels: the tables (Horner's rule in e^{2 pi i df tau_j}, float64, one
+// (segment, node) a thread), and the map pass (one pixel a thread, one chunk
+// of segments a workgroup row, float64 partial sums added in a fixed order by
+// the band finish kernel).
 #include <math.h>
 #include <stdint.h>
 
@@ -29,7 +28,7 @@ namespace sgwb {
 // 2 pi F h = kBbPhaseStep = 0.03 keeps it below 1.9e-8 of sum_k |y(t,k)|.
 constexpr double kBbPhaseStep = 0.03;
 constexpr int32_t kBbMaxHalf = 1 << 20;  // m: at most 2^21 + 3 nodes per table
-constexpr int kBbTileT = 64, kBbTileJ = 64, kBbTileK = 16;
+constexpr int kBbNodes = 64;  // table nodes per workgroup (one wave)
 constexpr int kBbBatch = 2;  // segments whose loads the map pass issues together
 
 bool bb_grid(int32_t nb, double df, double bound, BbGrid *g)
@@ -49,154 +48,74 @@ bool bb_grid(int32_t nb, double df, double bound, BbGrid *g)
 
 static size_t up256_(size_t n) { return (n + 255) / 256 * 256; }
 
-// Bin ranges of the table product: enough workgroups to fill the chip (about
-// 1024), each range a whole number of 16-bin steps.
-static int32_t bb_splits(int32_t nt, int32_t nb, const BbGrid &g, int32_t *kper)
-{
-    const int64_t tiles = (int64_t)((g.G + kBbTileJ - 1) / kBbTileJ) * ((nt + kBbTileT - 1) / kBbTileT);
-    const int32_t steps = (nb + kBbTileK - 1) / kBbTileK;
-    int64_t want = (1024 + tiles - 1) / tiles;
-    if (want > steps) want = steps;
-    if (want < 1) want = 1;
-    const int32_t per_steps = (int32_t)((steps + want - 1) / want);
-    *kper = per_steps * kBbTileK;
-    return (nb + *kper - 1) / *kper;
-}
-
-// Workspace: E [nb][G] float2 | T [nt][G] float2 | the map pass's partial sums
-// [segment chunks][npix] | the table product's partial sums [ranges][nt][G]
-// double2 | the Fisher band weights' scratch (v, then its partial sums).
+// Workspace: T [nt][G] float2 | the map pass's partial sums [segment
+// chunks][npix] | the Fisher band weights' scratch (v, then its partial sums).
 struct BbLayout {
-    size_t e, t, part, tpart, gam, total;
+    size_t t, part, gam, total;
 };
-static BbLayout bb_layout(int32_t nt, int32_t npix, int32_t nb, const BbGrid &g)
+static BbLayout bb_layout(int32_t nt, int32_t npix, const BbGrid &g)
 {
-    int32_t kper;
-    const int32_t ns = bb_splits(nt, nb, g, &kper);
     const size_t ntb = (size_t)band_gamma_chunks();  // the map pass's segment chunks
     BbLayout L;
-    L.e = 0;
-    L.t = L.e + up256_((size_t)nb * g.G * sizeof(float2));
+    L.t = 0;
     L.part = L.t + up256_((size_t)nt * g.G * sizeof(float2));
-    L.tpart = L.part + up256_(ntb * (size_t)npix * sizeof(double));
-    L.gam = L.tpart + up256_((size_t)ns * nt * g.G * sizeof(double2));
+    L.gam = L.part + up256_(ntb * (size_t)npix * sizeof(double));
     L.total = L.gam + up256_(band_gamma_scratch_bytes(nt, npix));
     return L;
 }
 
 size_t bb_workspace_bytes(int32_t nt, int32_t npix, int32_t nb, const BbGrid &g)
 {
-    return bb_layout(nt, npix, nb, g).total;
+    (void)nb;
+    return bb_layout(nt, npix, g).total;
 }
 
-// E[k][j] = e^{2 pi i (k - kc) df tau_j}, kc = (nb - 1) / 2: the phase in
-// turns, (k - kc) (df h) (j - m - 1), in float64, reduced to [-1/2, 1/2] and
-// turned into the phasor in float64, rounded once to float32.
-__global__ __launch_bounds__(256) void bb_phase_kernel(int32_t nb, int32_t G, int32_t m, double dfh,
-                                                       float2 *__restrict__ E)
+// T[t][j] = sum_k y(t,k) e^{2 pi i (k - kc) df tau_j}, kc = (nb - 1) / 2,
+// y(t,k) = w[t][klo + k] C[t][klo + k]: with omega = e^{2 pi i df tau_j},
+// T = omega^{-kc} sum_k y(t,k) omega^k, the sum by Horner's rule from the top
+// bin down (|omega| = 1, so rounding errors do not grow with the power), all
+// in float64; omega and omega^{-kc} from phases reduced in float64.  One wave
+// a workgroup (blockIdx.x the segment, blockIdx.y a block of 64 nodes), its y
+// staged through LDS 64 bins at a time (every lane then reads the same bin).
+__global__ __launch_bounds__(kBbNodes) void bb_table_kernel(const float *__restrict__ C, const float *__restrict__ w,
+                                                            int64_t ldc, int32_t klo, int32_t nb, int32_t G,
+                                                            int32_t m, double dfh, float2 *__restrict__ T)
 {
-    const int64_t n = (int64_t)nb * G;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const int32_t k = (int32_t)(i / G), j = (int32_t)(i - (int64_t)k * G);
-        const double turns = ((double)k - 0.5 * (nb - 1)) * dfh * (double)(j - m - 1);
-        const double r = turns - rint(turns);
-        double s, c;
-        sincospi(2.0 * r, &s, &c);
-        E[i] = make_float2((float)c, (float)s);
-    }
-}
-
-// T[t][j] = sum_k y(t,k) E[k][j], y(t,k) = w[t][klo + k] C[t][klo + k]: a
-// 64 x 64 tile of (segment, node) per 256-thread workgroup, 16 bins at a time
-// through LDS (y and E as float64 pairs; y staged 16 consecutive bins of a row
-// per 16 lanes, E 64 consecutive nodes per wave); thread (ty, tx) holds
-// segments ty + 16 a and nodes tx + 16 b, a, b < 4, summed in float64 in bin
-// order.
-__global__ __launch_bounds__(256) void bb_table_kernel(const float *__restrict__ C, const float *__restrict__ w,
-                                                       int64_t ldc, int32_t nt, int32_t klo, int32_t nb, int32_t G,
-                                                       int32_t kper, const float2 *__restrict__ E,
-                                                       double2 *__restrict__ Tpart)
-{
-    __shared__ double2 ys[kBbTileT][kBbTileK + 1];  // padded: the four rows a wave reads fall in different banks
-    __shared__ double2 es[kBbTileK][kBbTileJ];
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const int32_t j0 = blockIdx.x * kBbTileJ, t0 = blockIdx.y * kBbTileT;
-    double2 acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
-    const int32_t kb = blockIdx.z * kper, ke = min(nb, kb + kper);
-    for (int32_t k0 = kb; k0 < ke; k0 += kBbTileK) {
-        // stage: 64 x 16 of y and 16 x 64 of E, four of each per thread (zero past the ends)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int e = tid + 256 * r;
-            {
-                const int kk = e & 15, c = e >> 4;
-                const int32_t k = k0 + kk, t = t0 + c;
-                double2 yv = make_double2(0.0, 0.0);
-                if (k < ke && t < nt) {
-                    const int64_t o = (int64_t)t * ldc + klo + k;
-                    const double wv = (double)w[o];
-                    yv = make_double2(wv * (double)C[2 * o], wv * (double)C[2 * o + 1]);
-                }
-                ys[c][kk] = yv;
-            }
-            {
-                const int kk = e >> 6, c = e & 63;
-                const int32_t k = k0 + kk, j = j0 + c;
-                double2 ev = make_double2(0.0, 0.0);
-                if (k < ke && j < G) {
-                    const float2 v = E[(int64_t)k * G + j];
-                    ev = make_double2((double)v.x, (double)v.y);
-                }
-                es[kk][c] = ev;
-            }
+    __shared__ double2 ys[kBbNodes];
+    const int32_t t = blockIdx.x, j = blockIdx.y * kBbNodes + threadIdx.x;
+    const double node = (double)(j - m - 1);  // tau_j / h
+    double turns = dfh * node;
+    turns -= rint(turns);
+    double os, oc;
+    sincospi(2.0 * turns, &os, &oc);
+    const int64_t row = (int64_t)t * ldc + klo;
+    double ar = 0.0, ai = 0.0;
+    for (int32_t kb = (nb - 1) / kBbNodes * kBbNodes; kb >= 0; kb -= kBbNodes) {
+        const int32_t k = kb + (int32_t)threadIdx.x;
+        double2 yv = make_double2(0.0, 0.0);
+        if (k < nb) {
+            const double wv = (double)w[row + k];
+            yv = make_double2(wv * (double)C[2 * (row + k)], wv * (double)C[2 * (row + k) + 1]);
         }
+        __syncthreads();  // the previous block's reads are done
+        ys[threadIdx.x] = yv;
         __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < kBbTileK; ++kk) {
-            double2 yv[4], ev[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) yv[a] = ys[ty + 16 * a][kk];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) ev[b] = es[kk][tx + 16 * b];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    acc[a][b].x = fma(yv[a].x, ev[b].x, fma(-yv[a].y, ev[b].y, acc[a][b].x));
-                    acc[a][b].y = fma(yv[a].x, ev[b].y, fma(yv[a].y, ev[b].x, acc[a][b].y));
-                }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int32_t t = t0 + ty + 16 * a;
-        if (t >= nt) continue;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int32_t j = j0 + tx + 16 * b;
-            if (j < G) Tpart[((int64_t)blockIdx.z * nt + t) * G + j] = acc[a][b];
+        // bins past the band were staged as zeros: above the top bin they keep
+        // the sum at exactly zero, so every block runs the full count
+#pragma unroll 16
+        for (int i = kBbNodes - 1; i >= 0; --i) {
+            const double2 y = ys[i];
+            const double nr = fma(ar, oc, fma(-ai, os, y.x));
+            const double ni = fma(ar, os, fma(ai, oc, y.y));
+            ar = nr;
+            ai = ni;
         }
     }
-}
-
-// T[i] = sum over the bin ranges r, in order, of Tpart[r][i], rounded once.
-__global__ __launch_bounds__(256) void bb_table_finish_kernel(const double2 *__restrict__ Tpart, int64_t n,
-                                                              int32_t nsplit, float2 *__restrict__ T)
-{
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        double2 a = Tpart[i];
-        for (int32_t r = 1; r < nsplit; ++r) {
-            const double2 b = Tpart[(int64_t)r * n + i];
-            a.x += b.x;
-            a.y += b.y;
-        }
-        T[i] = make_float2((float)a.x, (float)a.y);
-    }
+    double back = 0.5 * (nb - 1) * dfh * node;  // omega^{-kc}
+    back -= rint(back);
+    double bs, bc;
+    sincospi(-2.0 * back, &bs, &bc);
+    if (j < G) T[(int64_t)t * G + j] = make_float2((float)(ar * bc - ai * bs), (float)(ar * bs + ai * bc));
 }
 
 // part[blockIdx.y][p] = sum over this chunk's segments t of
@@ -278,33 +197,18 @@ hipError_t launch_broadband_table_maps(const float *C, const float *w, int64_t l
                                        float *Xbb, float *Gbb, void *work, hipStream_t s)
 {
     const int32_t nb = khi - klo;
-    const BbLayout L = bb_layout(nt, npix, nb, g);
+    const BbLayout L = bb_layout(nt, npix, g);
     char *ws = reinterpret_cast<char *>(work);
     double *v = reinterpret_cast<double *>(ws + L.gam), *gpart = v + nt;
     const int32_t nchunks = band_gamma_chunks(), per = (nt + nchunks - 1) / nchunks;
     if (!Xbb) {  // Gbb alone: the weight-side kernels by themselves
         return launch_band_gamma(w, ldc, nt, H, klo, khi, gamma, npix, v, Gbb, s);
     }
-    int32_t kper;
-    const int32_t ns = bb_splits(nt, nb, g, &kper);
-    float2 *E = reinterpret_cast<float2 *>(ws + L.e);
     float2 *T = reinterpret_cast<float2 *>(ws + L.t);
     double *part = reinterpret_cast<double *>(ws + L.part);
-    double2 *Tpart = reinterpret_cast<double2 *>(ws + L.tpart);
-    const int64_t ne = (int64_t)nb * g.G;
-    hipLaunchKernelGGL(bb_phase_kernel, dim3((unsigned)std::min<int64_t>((ne + 255) / 256, 16384)), dim3(256), 0, s,
-                       nb, g.G, g.m, df * g.h, E);
+    hipLaunchKernelGGL(bb_table_kernel, dim3((unsigned)nt, (unsigned)((g.G + kBbNodes - 1) / kBbNodes)),
+                       dim3(kBbNodes), 0, s, C, w, ldc, klo, nb, g.G, g.m, df * g.h, T);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(bb_table_kernel, dim3((unsigned)((g.G + kBbTileJ - 1) / kBbTileJ),
-                                             (unsigned)((nt + kBbTileT - 1) / kBbTileT), (unsigned)ns),
-                       dim3(256), 0, s, C, w, ldc, nt, klo, nb, g.G, kper, (const float2 *)E, Tpart);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int64_t nT = (int64_t)nt * g.G;
-    hipLaunchKernelGGL(bb_table_finish_kernel, dim3((unsigned)std::min<int64_t>((nT + 255) / 256, 16384)), dim3(256),
-                       0, s, (const double2 *)Tpart, nT, ns, T);
-    e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (Gbb) {
         e = launch_band_weights(w, ldc, nt, H, klo, khi, v, s);

@@ -153,10 +153,10 @@ def test_server_rejects_bad_queries_before_device_work(sg, datasets):
 
 
 def test_server_fails_oversized_query_and_keeps_serving(sg, datasets):
-    # arena of 4 MiB: an nside-16 full-band query needs more (its workspace alone is 5.7 MiB)
+    # arena of 1 MiB: an nside-16 full-band query needs more (its workspace alone is 1.5 MiB, its seeds 1.7 MiB)
     d = datasets[0]
-    assert sg.broadband_maps_workspace_bytes(NT, NF, 3072, d.fgrid, 0, NF, sg.baseline_delay_bound(d.sites)) > 4 << 20
-    srv = sg.Server(datasets, slots=2, hbm_budget_bytes=4 << 20)
+    assert sg.broadband_maps_workspace_bytes(NT, NF, 3072, d.fgrid, 0, NF, sg.baseline_delay_bound(d.sites)) > 1 << 20
+    srv = sg.Server(datasets, slots=2, hbm_budget_bytes=1 << 20)
     big = srv.submit(0, 16, 0, NF)
     small = srv.submit(1, 1, 0, 20)
     res = _wait(srv, [big, small])
