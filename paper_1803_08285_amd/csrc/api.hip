@@ -715,12 +715,12 @@ static int bb_route(int32_t nt, int32_t nf, int32_t npix, uint32_t flags, const 
     // nside 8..128, bands of 16..4096 bins): the strips route takes ~0.19 ms
     // of preparation, ~1.2e11 (segment, pixel) seed items/s and ~4.2e13 map
     // terms/s over its whole 64-bin strips; the table route ~0.03 ms of
-    // launches, ~1.1e13 float64 products/s for the tables (4 per segment, bin
-    // and node), ~1.6e11 phase factors/s and ~3.3e11 items/s in the map pass.
+    // launches, ~1.5e13 float64 FMAs/s for the tables (4 per segment, bin and
+    // node; the rate rises to ~2e13 with more nodes) and ~3.3e11 items/s in
+    // the map pass.
     const double strip_cols = (double)(((int64_t)nf + 63) / 64 * 64);
     const double strips = 1.9e-4 + (double)nt * npix / 1.2e11 + (double)nt * strip_cols * npix / 4.2e13;
-    const double table = 3e-5 + (double)nt * nb * r->grid.G * 4.0 / 1.1e13 + (double)nb * r->grid.G / 1.6e11 +
-                         (double)nt * npix / 3.3e11;
+    const double table = 3e-5 + (double)nt * nb * r->grid.G * 4.0 / 1.5e13 + (double)nt * npix / 3.3e11;
     r->table = have_grid && table < strips;
     return SGWB_OK;
 }
