@@ -433,6 +433,10 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
  * tau_bound_s, or a band whose table would exceed 2^21 + 3 nodes.            */
 #define SGWB_BB_TABLE 4u
 #define SGWB_BB_STRIPS 8u
+/* |x_a - x_b| / c (s) of the baseline's two sites on the Earth sphere of
+ * radius R (Sec. II: the delay Omega . Delta x / c is at most this for every
+ * direction and time), with a 1e-9 relative margin for the seeds' rounding;
+ * 0.0 for a null or invalid baseline.  Host only.                            */
 double sgwb_baseline_delay_bound(const sgwb_baseline *bl /*host*/);
 size_t sgwb_broadband_maps_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint32_t flags,
                                           const sgwb_fgrid *fg /*host*/, int32_t k_lo, int32_t k_hi,
