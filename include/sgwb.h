@@ -434,7 +434,7 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
 #define SGWB_BB_TABLE 4u
 #define SGWB_BB_STRIPS 8u
 /* |x_a - x_b| / c (s) of the baseline's two sites on the Earth sphere of
- * radius R (Sec. II: the delay Omega . Delta x / c is at most this for every
+ * radius R (Sec. II.A, Eq. eq_overlap_red: the delay Omega . Delta x / c is at most this for every
  * direction and time), with a 1e-9 relative margin for the seeds' rounding;
  * 0.0 for a null or invalid baseline.  Host only.                            */
 double sgwb_baseline_delay_bound(const sgwb_baseline *bl /*host*/);
