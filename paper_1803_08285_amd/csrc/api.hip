@@ -717,10 +717,11 @@ static int bb_route(int32_t nt, int32_t nf, int32_t npix, uint32_t flags, const 
     // terms/s over its whole 64-bin strips; the table route ~0.03 ms of
     // launches, ~1.5e13 float64 FMAs/s for the tables (4 per segment, bin and
     // node; the rate rises to ~2e13 with more nodes) and ~3.3e11 items/s in
-    // the map pass.
+    // the map pass (twice that for antipodal seeds, read once per pixel pair).
     const double strip_cols = (double)(((int64_t)nf + 63) / 64 * 64);
     const double strips = 1.9e-4 + (double)nt * npix / 1.2e11 + (double)nt * strip_cols * npix / 4.2e13;
-    const double table = 3e-5 + (double)nt * nb * r->grid.G * 4.0 / 1.5e13 + (double)nt * npix / 3.3e11;
+    const double table = 3e-5 + (double)nt * nb * r->grid.G * 4.0 / 1.5e13 +
+                         (double)nt * npix / (a.nside > 0 ? 6.6e11 : 3.3e11);
     r->table = have_grid && table < strips;
     return SGWB_OK;
 }
@@ -754,7 +755,7 @@ int broadband_maps_seeded(const float *C, const float *w, int64_t ldc, int32_t n
         return set_error(SGWB_ENOMEM, "broadband_maps: workspace of %zu bytes needed, %zu given", need,
                          workspace_bytes);
     rc = check_hip(launch_broadband_table_maps(C, w, ldc, nt, k_lo, k_hi, fg->f0_hz, fg->df_hz, k0, H, gamma, tau,
-                                               npix, r.grid, Xbb, Gbb, workspace, stream),
+                                               npix, a.nside, r.grid, Xbb, Gbb, workspace, stream),
                    "broadband table launch");
     if (!rc && Xbb) note_xform(SGWB_XFORM_TABLE);
     return rc;

@@ -28,10 +28,11 @@ hipError_t launch_band_weights(const float *w, int64_t ldw, int32_t nt, const fl
                                double *v, hipStream_t s);
 // Xbb (and, with Gbb, Gbb) over columns [klo, khi) of C and w (absolute bins
 // k0 + klo ..); H is needed with Gbb
+// nside > 0: antipodal seeds (spot-checked), one thread per pixel pair
 hipError_t launch_broadband_table_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t klo,
                                        int32_t khi, double f0, double df, int64_t k0, const float *H,
-                                       const float *gamma, const double *tau, int32_t npix, const BbGrid &g,
-                                       float *Xbb, float *Gbb, void *work, hipStream_t s);
+                                       const float *gamma, const double *tau, int32_t npix, int64_t nside,
+                                       const BbGrid &g, float *Xbb, float *Gbb, void *work, hipStream_t s);
 
 // sgwb_broadband_maps with the strips route's seed-side products from `seeds`
 // (as make_maps_band_seeded; the table route needs none).

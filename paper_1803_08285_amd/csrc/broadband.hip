@@ -49,9 +49,10 @@ bool bb_grid(int32_t nb, double df, double bound, BbGrid *g)
 static size_t up256_(size_t n) { return (n + 255) / 256 * 256; }
 
 // Workspace: T [nt][G] float2 | the map pass's partial sums [segment
-// chunks][npix] | the Fisher band weights' scratch (v, then its partial sums).
+// chunks][npix] | the Fisher band weights' scratch (v, then its partial sums)
+// | the antipodal spot check's flags.
 struct BbLayout {
-    size_t t, part, gam, total;
+    size_t t, part, gam, flags, total;
 };
 static BbLayout bb_layout(int32_t nt, int32_t npix, const BbGrid &g)
 {
@@ -60,7 +61,8 @@ static BbLayout bb_layout(int32_t nt, int32_t npix, const BbGrid &g)
     L.t = 0;
     L.part = L.t + up256_((size_t)nt * g.G * sizeof(float2));
     L.gam = L.part + up256_(ntb * (size_t)npix * sizeof(double));
-    L.total = L.gam + up256_(band_gamma_scratch_bytes(nt, npix));
+    L.flags = L.gam + up256_(band_gamma_scratch_bytes(nt, npix));
+    L.total = L.flags + up256_(kSymParts * sizeof(double));
     return L;
 }
 
@@ -191,10 +193,99 @@ __global__ __launch_bounds__(256) void bb_map_kernel(const float *__restrict__ g
     if (GB) gpart[(int64_t)blockIdx.y * npix + p] = gacc;
 }
 
+// The same sums for a pixel p of the northern half and its antipode pB at
+// once, from p's seeds alone: antipodal seeds have gamma(t,pB) = gamma(t,p)
+// and tau(t,pB) = -tau(t,p), and the delay grid is symmetric about zero, so
+// pB's value is the table read at -tau with the conjugate carrier.  The
+// seeds' promise is spot-checked (flags, one per part of the check): a failed
+// check makes both maps NaN everywhere.
+template <bool GB>
+__global__ __launch_bounds__(256) void bb_map_pair_kernel(const float *__restrict__ gamma,
+                                                          const double *__restrict__ tau, int32_t nt, int32_t npix,
+                                                          int64_t nside, const float2 *__restrict__ T, int32_t G,
+                                                          int32_t m, double h, double bound, double fc, int32_t per,
+                                                          const double *__restrict__ flags, double *__restrict__ part,
+                                                          const double *__restrict__ v, double *__restrict__ gpart)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= npix / 2) return;
+    const int64_t pB = antipode_north(ring_of_north(p, nside), npix);
+    const int32_t t0 = blockIdx.y * per, t1 = min(nt, t0 + per);
+    const double inv_h = 1.0 / h, origin = (double)(m + 1);
+    const double jmax = (double)(2 * m);
+    double accA = 0.0, accB = 0.0, gacc = 0.0;
+    bool bad = false;
+    for (int32_t tq = t0; tq < t1; tq += kBbBatch) {
+        double ta[kBbBatch];
+        float g[kBbBatch];
+#pragma unroll
+        for (int e = 0; e < kBbBatch; ++e) {
+            const int64_t o = (int64_t)min(tq + e, t1 - 1) * npix + p;
+            ta[e] = tau[o];
+            g[e] = gamma[o];
+        }
+        float2 a[kBbBatch][2][4];
+        float x[kBbBatch][2];
+#pragma unroll
+        for (int e = 0; e < kBbBatch; ++e)
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const double u = fma(side ? -ta[e] : ta[e], inv_h, origin);
+                const double jd = fmin(fmax(floor(u), 1.0), jmax);  // NaN and out-of-range delays stay inside the table
+                x[e][side] = (float)(u - jd);
+                const float2 *row = T + (int64_t)min(tq + e, t1 - 1) * G + ((int32_t)jd - 1);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[e][side][i] = row[i];
+            }
+#pragma unroll
+        for (int e = 0; e < kBbBatch; ++e) {
+            const bool valid = tq + e < t1;
+            bad |= valid && !(fabs(ta[e]) <= bound);
+            float yr[2], yi[2];
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                // Lagrange weights of the nodes at -1, 0, 1, 2
+                const float xe = x[e][side], xp = xe + 1.0f, xm = xe - 1.0f, xm2 = xe - 2.0f;
+                const float l0 = -(1.0f / 6.0f) * xe * xm * xm2;
+                const float l1 = 0.5f * xp * xm * xm2;
+                const float l2 = -0.5f * xp * xe * xm2;
+                const float l3 = (1.0f / 6.0f) * xp * xe * xm;
+                const float2 *aa = a[e][side];
+                yr[side] = fmaf(l0, aa[0].x, fmaf(l1, aa[1].x, fmaf(l2, aa[2].x, l3 * aa[3].x)));
+                yi[side] = fmaf(l0, aa[0].y, fmaf(l1, aa[1].y, fmaf(l2, aa[2].y, l3 * aa[3].y)));
+            }
+            // carrier e^{2 pi i f_c tau} for p, its conjugate for pB
+            const double turns = fc * ta[e];
+            const float r = (float)(turns - rint(turns));
+            float sn, cs;
+            sincospif(2.0f * r, &sn, &cs);
+            const double wg = valid ? (double)g[e] : 0.0;
+            accA = fma(wg, (double)fmaf(cs, yr[0], -sn * yi[0]), accA);
+            accB = fma(wg, (double)fmaf(cs, yr[1], sn * yi[1]), accB);
+            if (GB) {
+                const double gd = (double)g[e];
+                const double ga = fma(v[min(tq + e, t1 - 1)], gd * gd, gacc);
+                gacc = valid ? ga : gacc;
+            }
+        }
+    }
+    bool broken = false;
+    for (int i = 0; i < kSymParts; ++i) broken |= flags[i] != 0.0;
+    const double nan = (double)__builtin_nanf("");
+    double *row = part + (int64_t)blockIdx.y * npix;
+    row[p] = bad || broken ? nan : accA;
+    row[pB] = bad || broken ? nan : accB;
+    if (GB) {
+        double *grow = gpart + (int64_t)blockIdx.y * npix;
+        grow[p] = broken ? nan : gacc;
+        grow[pB] = broken ? nan : gacc;
+    }
+}
+
 hipError_t launch_broadband_table_maps(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t klo,
                                        int32_t khi, double f0, double df, int64_t k0, const float *H,
-                                       const float *gamma, const double *tau, int32_t npix, const BbGrid &g,
-                                       float *Xbb, float *Gbb, void *work, hipStream_t s)
+                                       const float *gamma, const double *tau, int32_t npix, int64_t nside,
+                                       const BbGrid &g, float *Xbb, float *Gbb, void *work, hipStream_t s)
 {
     const int32_t nb = khi - klo;
     const BbLayout L = bb_layout(nt, npix, g);
@@ -216,6 +307,25 @@ hipError_t launch_broadband_table_maps(const float *C, const float *w, int64_t l
     }
     // the band's centre: absolute bin k0 + klo + (nb - 1) / 2
     const double fc = f0 + ((double)(k0 + klo) + 0.5 * (nb - 1)) * df;
+    if (nside > 0) {  // antipodal seeds: each thread a pixel pair
+        double *flags = reinterpret_cast<double *>(ws + L.flags);
+        e = launch_antipodal_check(gamma, tau, nt, npix, nside, flags, s);
+        if (e != hipSuccess) return e;
+        const dim3 pgrid((unsigned)((npix / 2 + 255) / 256), (unsigned)nchunks);
+        if (Gbb)
+            hipLaunchKernelGGL(bb_map_pair_kernel<true>, pgrid, dim3(256), 0, s, gamma, tau, nt, npix, nside,
+                               (const float2 *)T, g.G, g.m, g.h, g.bound, fc, per, (const double *)flags, part,
+                               (const double *)v, gpart);
+        else
+            hipLaunchKernelGGL(bb_map_pair_kernel<false>, pgrid, dim3(256), 0, s, gamma, tau, nt, npix, nside,
+                               (const float2 *)T, g.G, g.m, g.h, g.bound, fc, per, (const double *)flags, part,
+                               (const double *)nullptr, (double *)nullptr);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = launch_band_partial_finish(part, nchunks, npix, Xbb, s);
+        if (e != hipSuccess || !Gbb) return e;
+        return launch_band_partial_finish(gpart, nchunks, npix, Gbb, s);
+    }
     const dim3 grid((unsigned)((npix + 255) / 256), (unsigned)nchunks);
     if (Gbb)
         hipLaunchKernelGGL(bb_map_kernel<true>, grid, dim3(256), 0, s, gamma, tau, nt, npix, (const float2 *)T, g.G,

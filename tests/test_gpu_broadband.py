@@ -155,3 +155,20 @@ def test_full_day_nside128_band4096_sampled(sg, oracle_mod):
     Sb = S.reshape(pix.size, nf).sum(axis=1)
     err = np.abs(Xbb.cpu().numpy()[pix].astype(np.float64) - ref)
     assert np.all(err <= TOL * Sb), float((err / Sb).max())
+
+
+def test_broken_antipodal_promise_gives_nan_maps(sg):
+    """With SGWB_MAPS_ANTIPODAL the table route reads each pixel pair's seeds
+    once; seeds that fail the antipodal spot check give NaN maps, not wrong ones."""
+    g, t, C, w, H = _setup(sg, "AC", 4, 30, 0, 64, 1 / 32, 8)
+    fg = sg.FGrid(F0, 1 / 32)
+    t2 = t.clone()
+    t2[0, 5] += 1e-6  # segment 0 is one the spot check reads
+    Xbb, Gbb = sg.broadband_maps(C, w, fg, 0, g, t2, H, 0, 64, route="table")
+    Xok, Gok = sg.broadband_maps(C, w, fg, 0, g, t, H, 0, 64, route="table")
+    Xnp, Gnp = sg.broadband_maps(C, w, fg, 0, g, t, H, 0, 64, route="table", antipodal=False)
+    torch.cuda.synchronize()
+    assert torch.isnan(Xbb).all() and torch.isnan(Gbb).all()
+    assert torch.isfinite(Xok).all() and torch.equal(Gok, Gnp)
+    # the pair pass and the one-pixel pass agree to the route's tolerance
+    assert float((Xok - Xnp).abs().max()) <= 1e-6 * float(Xok.abs().max())
