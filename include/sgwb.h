@@ -407,12 +407,15 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
  *      Xbb(p) = sum_t gamma(t,p) Re[e^{2 pi i f_c tau} Y_t(tau)], tau = tau(t,p),
  *      Y_t(tau) = sum_{k_lo <= k < k_hi} w(t,k) C(t,k) e^{2 pi i (f_k - f_c) tau},
  *    f_c the band's centre.  Y_t is tabulated per segment on the delay grid
- *    tau_j = (j - m - 1) h (float64 sums, stored as float32), h =
+ *    tau_j = (j - m - 1) h (float64 Horner sums, stored as float32), h =
  *    0.03 / (2 pi F), F = (k_hi - k_lo - 1) df / 2, m = ceil(tau_bound / h),
  *    and read by 4-point Lagrange interpolation (error below 1.9e-8 of
  *    sum_k |w C| per segment); the carrier phase is reduced in float64.  The
  *    error against the definition stays below 1e-6 of
  *    S_bb(p) = sum_t sum_k |gamma w C|.  Any df, any seeds within tau_bound.
+ *    With SGWB_MAPS_ANTIPODAL each pixel pair's seeds are read once (the
+ *    antipode's value is the table read at -tau), the promise spot-checked
+ *    as on the strips route: seeds that fail give NaN maps.
  *  Gbb (either route): the band sum moved into the weights, as in
  *    sgwb_make_maps_band.
  * The route is chosen on the host from the arguments alone: SGWB_BB_TABLE or
@@ -420,8 +423,9 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
  * the environment, where that route applies; otherwise the table route runs
  * where the strips route does not apply or a cost estimate (the tables' nt nb G
  * products and nt npix interpolations against the strips' preparation and
- * nt nf npix map terms, rates measured on an MI355X) favours it.  sgwb_last_x_form reports the
- * route (SGWB_XFORM_TABLE, or the matrix-core form).
+ * nt nf npix map terms, rates measured on an MI355X) favours it.
+ * sgwb_last_x_form reports the route (SGWB_XFORM_TABLE, or the matrix-core
+ * form).
  * tau_bound_s: a bound on |tau(t,p)| that the seeds meet, e.g.
  * sgwb_baseline_delay_bound() of their baseline; 0 takes 2R/c (any baseline
  * on the Earth).  In the table route a seed beyond it (or not a number) makes
@@ -434,9 +438,9 @@ int sgwb_make_maps_band(const float *C, const float *w, int64_t ldc, int32_t nt,
 #define SGWB_BB_TABLE 4u
 #define SGWB_BB_STRIPS 8u
 /* |x_a - x_b| / c (s) of the baseline's two sites on the Earth sphere of
- * radius R (Sec. II.A, Eq. eq_overlap_red: the delay Omega . Delta x / c is at most this for every
- * direction and time), with a 1e-9 relative margin for the seeds' rounding;
- * 0.0 for a null or invalid baseline.  Host only.                            */
+ * radius R (Sec. II.A, Eq. eq_overlap_red: the delay Omega . Delta x / c is
+ * at most this for every direction and time), with a 1e-9 relative margin
+ * for the seeds' rounding; 0.0 for a null or invalid baseline.  Host only.   */
 double sgwb_baseline_delay_bound(const sgwb_baseline *bl /*host*/);
 size_t sgwb_broadband_maps_workspace_size(int32_t nt, int32_t nf, int32_t npix, uint32_t flags,
                                           const sgwb_fgrid *fg /*host*/, int32_t k_lo, int32_t k_hi,
