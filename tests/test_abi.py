@@ -327,3 +327,27 @@ def test_broadband_route_bound_and_validation_on_the_host():
     rc = L.sgwb_broadband_maps(dummy, dummy, 64, 10, 64, ctypes.byref(cfg), 0, dummy, dummy, 768,
                                sg.SGWB_BB_TABLE | 1, tb, dummy, 0, 64, dummy, dummy, dummy, 256, None)
     assert rc == -2 and b"workspace" in L.sgwb_last_error()
+
+
+def test_broadband_cost_rule_picks_the_measured_winner():
+    """The route the host's cost rule picks for full-day queries (898 segments,
+    1/32 Hz) against the faster route measured on one MI355X for each of them
+    (strips / tables, ms): only the widest bands at the lowest resolutions
+    keep the strips."""
+    import paper_1803_08285_amd as sg
+    import synth
+
+    measured = {  # (baseline, nside, bins): (strips ms, tables ms)
+        ("AB", 8, 16): (0.205, 0.040), ("AB", 8, 1024): (0.202, 0.086), ("AB", 8, 4096): (0.229, 0.294),
+        ("AB", 16, 4096): (0.409, 0.311), ("AB", 32, 4096): (1.200, 0.317), ("AB", 128, 16): (1.521, 0.409),
+        ("AB", 128, 4096): (17.016, 0.659), ("AC", 8, 4096): (0.259, 0.584), ("AC", 16, 1024): (0.247, 0.093),
+        ("AC", 16, 4096): (0.461, 0.570), ("AC", 32, 4096): (1.352, 0.584), ("AC", 128, 4096): (20.190, 0.979),
+    }
+    fg = sg.FGrid(20.0, 1 / 32)
+    for (bl, nside, nb), (t_strips, t_table) in measured.items():
+        tb = sg.baseline_delay_bound(synth.baseline_sites(bl))
+        npix = 12 * nside * nside
+        auto = sg.broadband_maps_workspace_bytes(898, nb, npix, fg, 0, nb, tb)
+        table = sg.broadband_maps_workspace_bytes(898, nb, npix, fg, 0, nb, tb, route="table")
+        picked_table = auto == table
+        assert picked_table == (t_table < t_strips), (bl, nside, nb)
