@@ -539,9 +539,12 @@ int sgwb_plan_describe(const sgwb_plan *plan, char *buf, size_t len);
  * maps, and new seeds) fits in an HBM arena of
  * hbm_budget_bytes (0: 60 % of the free memory) reserved at creation; queries
  * that arrive while others run are admitted as slots and memory free up, and
- * their kernels overlap on the device.  Admission is cost-aware: a query of at
- * least 3e10 map terms (segments x bins x pixels; SGWB_SERVER_HEAVY_TERMS in
- * the environment overrides the threshold) fills the GPU alone, so at most
+ * their kernels overlap on the device.  Admission is cost-aware: a query's
+ * cost is the time sgwb_broadband_maps' cost rule estimates for it, counted in
+ * map terms at the strips route's rate (4.2e13 terms/s; for a strips-route
+ * query about its segments x bins x pixels); one of at least 3e10
+ * (SGWB_SERVER_HEAVY_TERMS in the environment overrides the threshold) fills
+ * the GPU alone, so at most
  * one such heavy query runs at a time (SGWB_SERVER_MAX_HEAVY, 1 to 64,
  * overrides) and heavy queries start in arrival order; lighter queries start
  * in arrival order among themselves, run in the other slots beside it and

@@ -660,6 +660,7 @@ int make_maps_band_seeded(const float *C, const float *w, int64_t ldc, int32_t n
 struct BbRoute {
     bool table = false;
     BbGrid grid;
+    double seconds = 0.0;  // the cost estimate of the route taken
 };
 
 static int bb_route(int32_t nt, int32_t nf, int32_t npix, uint32_t flags, const sgwb_fgrid *fg, int32_t k_lo,
@@ -685,32 +686,6 @@ static int bb_route(int32_t nt, int32_t nf, int32_t npix, uint32_t flags, const 
     // the strips route: the matrix-core dirty map over the call's columns
     const bool strips_ok = a.nside > 0 && !(flags & SGWB_MAPS_VALU_X) && x_kernel_choice() != kXKernelValu &&
                            xm_eligible(a) && bound <= earth;
-    if (flags & SGWB_BB_STRIPS) {
-        if (!strips_ok)
-            return set_error(SGWB_EINVAL, "broadband_maps: the strips route needs the matrix-core dirty map "
-                                          "(antipodal seeds, df <= 0.0344 Hz, seeds within 2R/c)");
-        r->table = false;
-        return SGWB_OK;
-    }
-    if (!have_grid && ((flags & SGWB_BB_TABLE) || !strips_ok))
-        return set_error(SGWB_EINVAL, "broadband_maps: a delay table for %d bins of %g Hz up to %g s would "
-                                      "exceed 2^21 + 3 nodes", nb, fg->df_hz, bound);
-    if ((flags & SGWB_BB_TABLE) || !strips_ok) {
-        r->table = true;
-        return SGWB_OK;
-    }
-    // SGWB_BB_ROUTE=table|strips in the environment sets the route of calls
-    // that force none (read at every call; a route that does not apply is ignored)
-    if (const char *e = getenv("SGWB_BB_ROUTE")) {
-        if (strcmp(e, "strips") == 0) {
-            r->table = false;
-            return SGWB_OK;
-        }
-        if (strcmp(e, "table") == 0 && have_grid) {
-            r->table = true;
-            return SGWB_OK;
-        }
-    }
     // Cost estimate (s), from timings of both routes on one MI355X (full day,
     // nside 8..128, bands of 16..4096 bins): the strips route takes ~0.19 ms
     // of preparation, ~1.2e11 (segment, pixel) seed items/s and ~4.2e13 map
@@ -720,10 +695,50 @@ static int bb_route(int32_t nt, int32_t nf, int32_t npix, uint32_t flags, const 
     // the map pass (twice that for antipodal seeds, read once per pixel pair).
     const double strip_cols = (double)(((int64_t)nf + 63) / 64 * 64);
     const double strips = 1.9e-4 + (double)nt * npix / 1.2e11 + (double)nt * strip_cols * npix / 4.2e13;
-    const double table = 3e-5 + (double)nt * nb * r->grid.G * 4.0 / 1.5e13 +
-                         (double)nt * npix / (a.nside > 0 ? 6.6e11 : 3.3e11);
+    const double table = have_grid ? 3e-5 + (double)nt * nb * r->grid.G * 4.0 / 1.5e13 +
+                                         (double)nt * npix / (a.nside > 0 ? 6.6e11 : 3.3e11)
+                                   : HUGE_VAL;
+    if (flags & SGWB_BB_STRIPS) {
+        if (!strips_ok)
+            return set_error(SGWB_EINVAL, "broadband_maps: the strips route needs the matrix-core dirty map "
+                                          "(antipodal seeds, df <= 0.0344 Hz, seeds within 2R/c)");
+        r->table = false;
+        r->seconds = strips;
+        return SGWB_OK;
+    }
+    if (!have_grid && ((flags & SGWB_BB_TABLE) || !strips_ok))
+        return set_error(SGWB_EINVAL, "broadband_maps: a delay table for %d bins of %g Hz up to %g s would "
+                                      "exceed 2^21 + 3 nodes", nb, fg->df_hz, bound);
+    if ((flags & SGWB_BB_TABLE) || !strips_ok) {
+        r->table = true;
+        r->seconds = table;
+        return SGWB_OK;
+    }
+    // SGWB_BB_ROUTE=table|strips in the environment sets the route of calls
+    // that force none (read at every call; a route that does not apply is ignored)
+    if (const char *e = getenv("SGWB_BB_ROUTE")) {
+        if (strcmp(e, "strips") == 0) {
+            r->table = false;
+            r->seconds = strips;
+            return SGWB_OK;
+        }
+        if (strcmp(e, "table") == 0 && have_grid) {
+            r->table = true;
+            r->seconds = table;
+            return SGWB_OK;
+        }
+    }
     r->table = have_grid && table < strips;
+    r->seconds = r->table ? table : strips;
     return SGWB_OK;
+}
+
+double broadband_cost_seconds(int32_t nt, int32_t nf, int32_t npix, uint32_t flags, const sgwb_fgrid *fg,
+                              int32_t k_lo, int32_t k_hi, double tau_bound)
+{
+    BbRoute r;
+    if (!fg || bb_route(nt, nf, npix, flags, fg, k_lo, k_hi, tau_bound, &r)) return -1.0;
+    return r.seconds;
 }
 
 int broadband_maps_seeded(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,

@@ -34,6 +34,11 @@ hipError_t launch_broadband_table_maps(const float *C, const float *w, int64_t l
                                        const float *gamma, const double *tau, int32_t npix, int64_t nside,
                                        const BbGrid &g, float *Xbb, float *Gbb, void *work, hipStream_t s);
 
+// The host's cost estimate (s) of the route sgwb_broadband_maps takes for
+// these arguments; -1 where it would refuse them.
+double broadband_cost_seconds(int32_t nt, int32_t nf, int32_t npix, uint32_t flags, const sgwb_fgrid *fg,
+                              int32_t k_lo, int32_t k_hi, double tau_bound);
+
 // sgwb_broadband_maps with the strips route's seed-side products from `seeds`
 // (as make_maps_band_seeded; the table route needs none).
 int broadband_maps_seeded(const float *C, const float *w, int64_t ldc, int32_t nt, int32_t nf, const sgwb_fgrid *fg,

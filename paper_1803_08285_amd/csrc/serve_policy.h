@@ -109,10 +109,11 @@ class Arena {
     std::map<size_t, size_t> sizes_;  // offset -> length of live blocks
 };
 
-// Default heavy threshold: 3e10 terms, about 0.8 ms of the whole GPU; queries
-// above it have enough tiles to occupy every compute unit for long enough that
-// letting them overlap only stretches both, while those below it finish
-// quickly enough to run beside a heavy one.
+// Default heavy threshold: 3e10 map-term equivalents (a query's estimated GPU
+// time at 4.2e13 terms/s), about 0.7 ms of the whole GPU; queries above it
+// occupy every compute unit for long enough that letting them overlap only
+// stretches both, while those below it finish quickly enough to run beside a
+// heavy one.
 constexpr double kHeavyTermsDefault = 3e10;
 
 struct PendingView {

@@ -413,7 +413,13 @@ int sgwb_server_submit(sgwb_server *s, const sgwb_query *q, uint64_t *ticket)
     if ((int64_t)s->pending.size() >= s->queue_capacity) return set_error(SGWB_EBUSY, "server_submit: queue full");
     Query qq;
     qq.q = *q;
-    qq.cost = (double)d.tg.nt * (double)(q->k_hi - q->k_lo) * 12.0 * (double)q->nside * (double)q->nside;
+    // cost in map-term equivalents: the route's time estimate at the strips
+    // route's rate (4.2e13 terms/s), so that a band-first query counts for
+    // what it costs, not for its nt x band x npix terms
+    const int32_t npix = 12 * q->nside * q->nside, nb = q->k_hi - q->k_lo;
+    const double est = broadband_cost_seconds(d.tg.nt, nb, npix, SGWB_MAPS_ANTIPODAL, &d.fg, 0, nb,
+                                              s->tau_bound[q->dataset]);
+    qq.cost = est >= 0.0 ? est * 4.2e13 : (double)d.tg.nt * nb * (double)npix;
     qq.ticket = s->next_ticket++;
     qq.t_submit = Clock::now();
     s->queries.emplace(qq.ticket, qq);
